@@ -1,0 +1,156 @@
+"""Benchmark: Chebyshev density-matrix columns per second on one MI355X.
+
+Workload (the configuration the metric is quoted on): K = 4096 basis
+functions (1024 atoms in a sphere, four s-Gaussians each), FP64 recursion
+over all K columns (64 blocks of 64, advanced together), order N = 1000,
+beta = 200 /hartree, N_e = 2048, spin factor 2.
+
+One step = the whole path for one (F, S): operator setup and Lanczos bounds
+(dm_set_fock), coefficients, start block and the N-term recursion with the
+fused P accumulation and moment reductions for every column
+(dm_chebyshev_block), then the chemical-potential bisection and band energy
+from that step's moments (dm_solve_mu, dm_trace).  The step computes P at the
+mu solved by the previous step (steady state of a self-consistent loop; the
+first warm-up step solves it from a pass at mu = 0) and checks the electron
+count of its own moments.
+
+Prints one JSON line.  --gpus N with N > 1 is not supported (one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "K4096_sphere1024_fp64"
+METRIC = "density-matrix columns/sec and SpMM GB/s (% HBM roofline) at max|dP|<=1e-6"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline(cluster, order, beta, n_e, budget_s=30.0):
+    """The oracle (generalized eigh + C p_N(e) C^T for every column) on the host."""
+    import numpy as np
+
+    import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        sp = O.spectrum(cluster)
+        w = sp.e[-1] - sp.e[0]
+        emin, emax = sp.e[0] - 0.01 * w, sp.e[-1] + 0.01 * w
+        mu = O.solve_mu_poly(sp, n_e, order, beta, emin, emax, tol=1e-6)
+        P = O.density_matrix_poly(sp, np.arange(cluster.K), order, mu, beta, emin, emax)
+        del P
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s / 3 or reps >= 3:
+            break
+    return {"value": reps * cluster.K / el, "unit": "columns/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full density matrix(es), K={cluster.K}: eigh(F,S) + mu bisection + "
+                      f"C diag(p_N) C^T for all columns, numpy/scipy FP64, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2108_13478_amd as dmlib
+    from synth import WORKLOADS, workload
+
+    w = WORKLOADS[WORKLOAD]
+    order, beta, n_e = w["order"], w["beta"], w["n_electrons"]
+    print(f"[bench] building inputs {WORKLOAD}", file=sys.stderr, flush=True)
+    c = workload(WORKLOAD)
+    K = c.K
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    F = (t(c.F_rowptr), t(c.F_col), t(c.F_val))
+    S = (t(c.S_rowptr), t(c.S_col), t(c.S_val))
+    cols = torch.arange(K, dtype=torch.int64, device=dev)
+    P = torch.empty((K, K), dtype=torch.float64, device=dev)  # row j = column j of P
+    stream = torch.cuda.Stream()  # a real stream: the library and the events share it
+    torch.cuda.set_stream(stream)
+    ctx = dmlib.Context(device=0, stream=stream.cuda_stream, precision=dmlib.DM_FP64)
+    rec_ms = []
+    state = {"mu": 0.0, "tr_err": None}
+
+    def step(timed):
+        ctx.dm_set_fock(K, *F, *S, 4)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.dm_chebyshev_block(cols, order, state["mu"], beta, P)
+        e1.record(stream)
+        tr, eb = ctx.dm_trace(state["mu"], beta)
+        state["tr_err"] = abs(2.0 * tr - n_e)
+        state["eband"] = eb
+        state["mu"] = ctx.dm_solve_mu(n_e, beta, tol=1e-6)
+        if timed:
+            rec_ms.append(e0.elapsed_time(e1))
+
+    for i in range(args.warmup):
+        print(f"[bench] warmup {i}", file=sys.stderr, flush=True)
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+
+    # dominant kernel: the recursion step, 2 K^2 flops per column per launch
+    launch_ms = float(np.mean(rec_ms)) / order
+    flops = 2.0 * K * K * K
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": K * args.steps / el,
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "K": K, "order": order, "beta": beta, "n_electrons": n_e,
+                   "columns_per_step": K, "column_block": 64, "precision": "fp64",
+                   "nnz_per_row_F_S": [round(x, 1) for x in c.nnz_per_row]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "cheb_step_kernel<double,4,4,2,2>", "launch_ms": launch_ms},
+        "electron_count_error": state["tr_err"],
+        "mu": state["mu"],
+        "band_energy": state["eband"],
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(c, order, beta, n_e)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

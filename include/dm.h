@@ -1,0 +1,161 @@
+/*
+ * dm.h - C ABI of the MI355X Chebyshev density-matrix library (libdm.so).
+ *
+ * The library computes columns of the finite-temperature density matrix
+ *     P = f_FD(S^-1 F) S^-1                                  (eq. RDM)
+ * of a non-orthogonal atom-centred basis, with f_FD(e) = 1/(1+exp(beta(e-mu)))
+ * (Method section, text before eq. RDM), by the Chebyshev column recursion of
+ * the supplement's "Chebyshev expansion" section (eq. ChebychevExpansion):
+ *     U_0 = S^-1 u_a,  U_1 = H_N U_0,  U_{l+1} = 2 H_N U_l - U_{l-1},
+ *     rho_a = sum_{l<N} a_l U_l,   H_N = (S^-1 F - Ebar) / dE,
+ * where u_a is the unit column vector of basis function a (eq. col-by-col).
+ * Alongside P it accumulates the moments m_l = sum_a s_a^T U_l (s_a = column
+ * a of S), from which the electron count N_e = g Tr[PS] (eq. Ne) and the band
+ * energy g Tr[PF] (eq. <O> with O = F) follow for any mu.
+ *
+ * Conventions for every entry point:
+ *  - Return value: a dm_status; DM_OK on success.  No C++ exception crosses
+ *    the ABI.  dm_last_error() gives a message for the last failure.
+ *  - After DM_E_HIP the context is poisoned: every later call except
+ *    dm_last_error and dm_destroy returns DM_E_STATE.
+ *  - Pointers marked "host or device" may point to host memory or to device
+ *    memory of the context's GPU; the library tells them apart with
+ *    hipPointerGetAttributes.  The caller owns all arrays; the library copies
+ *    whatever it keeps.
+ *  - Dense matrices are column-major with leading dimension equal to their
+ *    row count (K), FP64.
+ *  - All GPU work is ordered on the context's stream.  Calls that return
+ *    host scalars (dm_get_bounds, dm_trace, dm_solve_mu, dm_moments) and
+ *    calls whose output is in host memory synchronise that stream before
+ *    returning; other calls may return before the GPU work has finished.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef DM_H
+#define DM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dm_ctx dm_ctx;
+
+typedef enum {
+    DM_OK = 0,
+    DM_E_ARG = -1,     /* invalid argument (null pointer, size, range, NaN) */
+    DM_E_STATE = -2,   /* call out of order, or context poisoned */
+    DM_E_HIP = -3,     /* HIP runtime error; context poisoned */
+    DM_E_OOM = -4,     /* device allocation failed */
+    DM_E_NOTSPD = -5,  /* overlap matrix not positive definite (Cholesky) */
+    DM_E_BOUNDS = -6,  /* recursion diverged: spectral bounds do not enclose */
+    DM_E_NOCONV = -7   /* iteration did not reach its tolerance */
+} dm_status;
+
+enum { DM_FP64 = 0, DM_FP32 = 1 };
+
+typedef struct {
+    int device;              /* HIP device ordinal */
+    void* stream;            /* hipStream_t to order work on; NULL = library-owned stream */
+    int precision;           /* DM_FP64 or DM_FP32: storage and arithmetic of H_N and U_l.
+                                P and the moments are always accumulated in FP64. */
+    int block_width;         /* columns advanced together per pass; 0 = library choice */
+    double spin;             /* g in N_e = g Tr[PS] (eq. Ne); the paper uses 2 */
+    int lanczos_steps;       /* Lanczos steps for the spectral bounds; 0 = 100 */
+    double bound_margin;     /* relative widening of the Lanczos interval; <= 0 = 0.01 */
+    unsigned long long seed; /* seed of the Lanczos start vector */
+} dm_options;
+
+/* Fill *opt with the defaults (device 0, library stream, FP64, spin 2). */
+void dm_default_options(dm_options* opt);
+
+/* Create a context on opt->device (opt may be NULL: defaults).  *out receives
+ * the handle; it is NULL on failure.  Errors: DM_E_ARG (out NULL, bad option),
+ * DM_E_HIP (no such device). */
+dm_status dm_init(dm_ctx** out, const dm_options* opt);
+
+/* Release every device buffer of the context.  NULL is a no-op. */
+void dm_destroy(dm_ctx* ctx);
+
+/* Message of the last failure on ctx ("" if none); ctx may be NULL, then the
+ * message of the last failed dm_init of this thread. Valid until the next call. */
+const char* dm_last_error(const dm_ctx* ctx);
+
+/* Load the Fock matrix F and overlap S of a K-function basis (eq. FockMatrix,
+ * eq. Smat) and build the recursion operator (supplement "Chebyshev
+ * expansion"): S = U^T U (Cholesky), S^-1, H = S^-1 F, extreme eigenvalues of
+ * H by S-inner-product Lanczos widened by bound_margin, and H_N.
+ * CSR arrays (host or device): rowptr[K+1] (int64, rowptr[0] = 0), col[nnz]
+ * (int32, sorted ascending within a row, in [0, K)), val[nnz] (FP64); full
+ * symmetric storage.  atom_block: functions per atom (K must be a multiple),
+ * 1 = no blocking.  Resets the accumulated moments.
+ * Errors: DM_E_ARG (K <= 0, malformed CSR, non-finite value, asymmetric
+ * pattern size), DM_E_NOTSPD (S not positive definite), DM_E_OOM, DM_E_HIP. */
+dm_status dm_set_fock(dm_ctx* ctx, long long K,
+                      const long long* F_rowptr, const int* F_col, const double* F_val,
+                      const long long* S_rowptr, const int* S_col, const double* S_val,
+                      int atom_block);
+
+/* Spectral interval [Emin, Emax] used to normalise H (supplement: Emax and
+ * Emin are the extreme eigenvalues of H = S^-1 F).  dm_set_bounds replaces
+ * the Lanczos interval (e.g. to pin the interval in a comparison) and resets
+ * the accumulated moments.  Errors: DM_E_STATE (no Fock matrix),
+ * DM_E_ARG (emin >= emax, non-finite). */
+dm_status dm_get_bounds(dm_ctx* ctx, double* emin, double* emax);
+dm_status dm_set_bounds(dm_ctx* ctx, double emin, double emax);
+
+/* Copy a setup product to out (host or device, K x K FP64 column-major):
+ * which = DM_OP_SINV: S^-1 (the start vectors U_0 = S^-1 u_a are its columns);
+ * which = DM_OP_H: H = S^-1 F (supplement "Chebyshev expansion").
+ * Errors: DM_E_STATE (no Fock matrix), DM_E_ARG. */
+enum { DM_OP_SINV = 0, DM_OP_H = 1 };
+dm_status dm_get_operator(dm_ctx* ctx, int which, double* out);
+
+/* Switch the recursion precision (DM_FP64 / DM_FP32) of a loaded operator;
+ * resets the accumulated moments. */
+dm_status dm_set_precision(dm_ctx* ctx, int precision);
+
+/* Columns `cols` of P_N = sum_{l<order} a_l T_l(H_N) S^-1 (eq. RDM with the
+ * Chebyshev expansion of f_FD at (mu, beta); `order` = N counts the terms
+ * a_0..a_{N-1}; a_l from a cosine transform of f_FD at 4N Chebyshev nodes).
+ * cols[ncols] (int64, host or device): distinct basis indices in [0, K).
+ * P_out (host or device, may be NULL): K x ncols column-major FP64; column j
+ * is P u_{cols[j]}.  With P_out NULL only the moments are accumulated.
+ * The moments m_0..m_order of the columns are added to the context's
+ * accumulator (one more recursion step than P needs gives m_order); a call
+ * with a different order restarts the accumulation.
+ * Errors: DM_E_STATE (no Fock matrix), DM_E_ARG (order < 2, beta <= 0 or
+ * non-finite, ncols < 0, bad or repeated column), DM_E_BOUNDS (the recursion
+ * overflowed), DM_E_OOM, DM_E_HIP. */
+dm_status dm_chebyshev_block(dm_ctx* ctx, const long long* cols, long long ncols, int order,
+                             double mu, double beta, double* P_out);
+
+/* From the accumulated moments (exact once every column 0..K-1 has been
+ * processed once): tr_PS = Tr[P_N S] = sum_l a_l m_l (eq. Ne without the spin
+ * factor) and e_band = g Tr[P_N F] = g sum_l a_l (Ebar m_l + dE (m_{l+1} +
+ * m_|l-1|)/2) (eq. <O>), with a_l the coefficients at (mu, beta) and the
+ * accumulated order.  Either output pointer (host) may be NULL.
+ * Errors: DM_E_STATE (no moments), DM_E_ARG. */
+dm_status dm_trace(dm_ctx* ctx, double mu, double beta, double* tr_PS, double* e_band);
+
+/* Bisection on [Emin, Emax] for mu with g Tr[P_N(mu) S] = n_e from the
+ * accumulated moments (the paper adjusts mu to reproduce N_e through eq. Ne;
+ * the method is not stated).  Stops when |g Tr - n_e| <= tol or the bracket
+ * reaches rounding level (then DM_E_NOCONV, *mu still set to the last
+ * midpoint).  Errors: DM_E_STATE (no moments), DM_E_ARG. */
+dm_status dm_solve_mu(dm_ctx* ctx, double n_e, double beta, double tol, double* mu);
+
+/* Copy up to n accumulated moments to m (host) and the number of columns
+ * they cover to *ncols_done (either may be NULL); n may exceed order + 1,
+ * the rest is zero-filled. */
+dm_status dm_moments(dm_ctx* ctx, double* m, int n, long long* ncols_done);
+dm_status dm_reset_moments(dm_ctx* ctx);
+
+/* Stochastic moments (1/n_vec) sum_s xi_s^T T_l(H_N) xi_s, l < n_mom, with
+ * caller-supplied probe vectors xi (host or device, K x n_vec column-major
+ * FP64, e.g. independent +-1 entries).  m_out: host, n_mom FP64.
+ * Does not touch the accumulated moments. */
+dm_status dm_stoch_moments(dm_ctx* ctx, int n_mom, int n_vec, const double* xi, double* m_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DM_H */

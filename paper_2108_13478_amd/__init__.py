@@ -1,0 +1,219 @@
+"""Python binding of libdm.so, the MI355X Chebyshev density-matrix library.
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Functions keep the names of the C ABI in include/dm.h; `Context`
+wraps a dm_ctx handle.  Arrays may be torch tensors (CPU or on the GPU) or
+numpy arrays; device tensors are passed to the library as device pointers.
+The library must have been built (python -m paper_2108_13478_amd.build); a
+missing library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdm.so")
+
+DM_OK, DM_E_ARG, DM_E_STATE, DM_E_HIP, DM_E_OOM, DM_E_NOTSPD, DM_E_BOUNDS, DM_E_NOCONV = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+DM_FP64, DM_FP32 = 0, 1
+DM_OP_SINV, DM_OP_H = 0, 1
+STATUS_NAMES = {0: "DM_OK", -1: "DM_E_ARG", -2: "DM_E_STATE", -3: "DM_E_HIP", -4: "DM_E_OOM",
+                -5: "DM_E_NOTSPD", -6: "DM_E_BOUNDS", -7: "DM_E_NOCONV"}
+
+EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_set_fock",
+            "dm_get_bounds", "dm_set_bounds", "dm_get_operator", "dm_set_precision", "dm_chebyshev_block",
+            "dm_trace", "dm_solve_mu", "dm_moments", "dm_reset_moments", "dm_stoch_moments"]
+
+
+class DMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dm_options(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("precision", ctypes.c_int),
+        ("block_width", ctypes.c_int),
+        ("spin", ctypes.c_double),
+        ("lanczos_steps", ctypes.c_int),
+        ("bound_margin", ctypes.c_double),
+        ("seed", ctypes.c_ulonglong),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_LL = ctypes.c_longlong
+
+
+def load(path: str = LIB_PATH):
+    """Load libdm.so (once) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with python -m paper_2108_13478_amd.build")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "dm_default_options": (None, [_P]),
+        "dm_init": (_I, [_P, _P]),
+        "dm_destroy": (None, [_P]),
+        "dm_last_error": (ctypes.c_char_p, [_P]),
+        "dm_set_fock": (_I, [_P, _LL, _P, _P, _P, _P, _P, _P, _I]),
+        "dm_get_bounds": (_I, [_P, _P, _P]),
+        "dm_set_bounds": (_I, [_P, _D, _D]),
+        "dm_set_precision": (_I, [_P, _I]),
+        "dm_get_operator": (_I, [_P, _I, _P]),
+        "dm_chebyshev_block": (_I, [_P, _P, _LL, _I, _D, _D, _P]),
+        "dm_trace": (_I, [_P, _D, _D, _P, _P]),
+        "dm_solve_mu": (_I, [_P, _D, _D, _D, _P]),
+        "dm_moments": (_I, [_P, _P, _I, _P]),
+        "dm_reset_moments": (_I, [_P]),
+        "dm_stoch_moments": (_I, [_P, _I, _I, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(x, dtype):
+    """(pointer, keepalive) for a torch tensor or array-like of the given numpy dtype."""
+    if x is None:
+        return None, None
+    try:
+        import torch
+        if isinstance(x, torch.Tensor):
+            want = {np.float64: torch.float64, np.int64: torch.int64, np.int32: torch.int32}[dtype]
+            if x.dtype != want or not x.is_contiguous():
+                raise TypeError(f"tensor must be contiguous {want}")
+            return ctypes.c_void_p(x.data_ptr()), x
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return ctypes.c_void_p(a.ctypes.data), a
+
+
+def _numel(x):
+    n = getattr(x, "numel", None)
+    return n() if callable(n) else int(np.asarray(x).size)
+
+
+class Context:
+    """One dm_ctx: a loaded (F, S) pair, its operator and moment accumulator."""
+
+    def __init__(self, device=0, stream=None, precision=DM_FP64, block_width=0, spin=2.0,
+                 lanczos_steps=100, bound_margin=0.01, seed=12345):
+        lib = load()
+        opt = dm_options()
+        lib.dm_default_options(ctypes.byref(opt))
+        opt.device = device
+        opt.stream = stream
+        opt.precision = precision
+        opt.block_width = block_width
+        opt.spin = spin
+        opt.lanczos_steps = lanczos_steps
+        opt.bound_margin = bound_margin
+        opt.seed = seed
+        h = ctypes.c_void_p()
+        st = lib.dm_init(ctypes.byref(h), ctypes.byref(opt))
+        if st != DM_OK:
+            raise DMError(st, lib.dm_last_error(None).decode())
+        self._lib = lib
+        self.h = h
+        self.K = None
+        self.spin = spin
+
+    def _check(self, st):
+        if st != DM_OK:
+            raise DMError(st, self._lib.dm_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.dm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- calls
+    def dm_set_fock(self, K, F_rowptr, F_col, F_val, S_rowptr, S_col, S_val, atom_block=1):
+        keep = [_ptr(F_rowptr, np.int64), _ptr(F_col, np.int32), _ptr(F_val, np.float64),
+                _ptr(S_rowptr, np.int64), _ptr(S_col, np.int32), _ptr(S_val, np.float64)]
+        self._check(self._lib.dm_set_fock(self.h, int(K), *[k[0] for k in keep], int(atom_block)))
+        self.K = int(K)
+
+    def set_cluster(self, cluster, atom_block=4):
+        c = cluster
+        self.dm_set_fock(c.K, c.F_rowptr, c.F_col, c.F_val, c.S_rowptr, c.S_col, c.S_val, atom_block)
+
+    def dm_get_bounds(self):
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.dm_get_bounds(self.h, ctypes.byref(lo), ctypes.byref(hi)))
+        return lo.value, hi.value
+
+    def dm_set_bounds(self, emin, emax):
+        self._check(self._lib.dm_set_bounds(self.h, float(emin), float(emax)))
+
+    def dm_get_operator(self, which):
+        """K x K FP64 numpy copy of S^-1 (DM_OP_SINV) or H = S^-1 F (DM_OP_H)."""
+        out = np.zeros((self.K, self.K), dtype=np.float64)  # filled column-major
+        self._check(self._lib.dm_get_operator(self.h, int(which), ctypes.c_void_p(out.ctypes.data)))
+        return out.T
+
+    def dm_set_precision(self, precision):
+        self._check(self._lib.dm_set_precision(self.h, int(precision)))
+
+    def dm_chebyshev_block(self, cols, order, mu, beta, P_out=None):
+        """P_out: None (moments only) or a contiguous float64 buffer of
+        ncols * K elements (torch tensor on the GPU or host, or numpy) that
+        receives P column-major (column j contiguous)."""
+        cp, ck = _ptr(cols, np.int64)
+        n = int(len(cols))
+        pp, pk = _ptr(P_out, np.float64) if P_out is not None else (None, None)
+        if P_out is not None and _numel(pk) < n * self.K:
+            raise ValueError("P_out too small")
+        self._check(self._lib.dm_chebyshev_block(self.h, cp, n, int(order), float(mu), float(beta), pp))
+        return P_out
+
+    def dm_trace(self, mu, beta):
+        tr, eb = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.dm_trace(self.h, float(mu), float(beta), ctypes.byref(tr), ctypes.byref(eb)))
+        return tr.value, eb.value
+
+    def dm_solve_mu(self, n_e, beta, tol=1e-8):
+        mu = ctypes.c_double()
+        self._check(self._lib.dm_solve_mu(self.h, float(n_e), float(beta), float(tol), ctypes.byref(mu)))
+        return mu.value
+
+    def dm_moments(self, n):
+        m = np.zeros(n, dtype=np.float64)
+        nd = ctypes.c_longlong()
+        self._check(self._lib.dm_moments(self.h, ctypes.c_void_p(m.ctypes.data), int(n), ctypes.byref(nd)))
+        return m, nd.value
+
+    def dm_reset_moments(self):
+        self._check(self._lib.dm_reset_moments(self.h))
+
+    def dm_stoch_moments(self, n_mom, xi):
+        """xi: K x n_vec probe vectors (numpy or torch); passed column-major."""
+        n_vec = int(xi.shape[1])
+        xt = xi.t().contiguous() if hasattr(xi, "t") else np.ascontiguousarray(np.asarray(xi).T)
+        xp, xk = _ptr(xt, np.float64)
+        m = np.zeros(n_mom, dtype=np.float64)
+        self._check(self._lib.dm_stoch_moments(self.h, int(n_mom), n_vec, xp, ctypes.c_void_p(m.ctypes.data)))
+        return m

@@ -1,0 +1,866 @@
+// Host runtime behind include/dm.h: argument checking, device memory, the
+// operator setup sequence, the column-block passes of the recursion and the
+// trace / chemical-potential calls.  Every arithmetic step on matrices and
+// vectors runs in the HIP kernels of gemm.hip and kernels.hip; the host only
+// orders launches and evaluates the k x k Lanczos tridiagonal.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dm.h"
+#include "dm_common.hpp"
+
+using namespace dm;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;  // elements
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct dm_ctx {
+    dm_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool poisoned = false;
+    std::string err;
+
+    // operator
+    bool have_fock = false;
+    long long K = 0;
+    int Kp = 0;
+    int precision = DM_FP64;
+    double emin = 0, emax = 0;
+    double lz_emin = 0, lz_emax = 0, lz_resid_lo = 0, lz_resid_hi = 0;
+    int lz_steps_done = 0;
+    DevBuf<long long> S_rowptr;
+    DevBuf<int> S_col;
+    DevBuf<double> S_val;
+    DevBuf<double> Sinv;  // Kp x Kp, S^-1
+    DevBuf<double> HT;    // Kp x Kp, (S^-1 F)^T column-major = H row-major
+    DevBuf<double> HNbuf; // Kp x Kp of precision T (FP64 slots reused for FP32)
+
+    // moments
+    DevBuf<double> mom;
+    int mom_order = -1;
+    long long ncols_done = 0;
+
+    // workspace
+    DevBuf<double> Ua, Ub, Z, P;  // sized in bytes via double slots
+    DevBuf<double> part_start, part_steps;
+    DevBuf<double> coef, coef_zero, fk, w, v, out;
+    DevBuf<int> flag;
+    DevBuf<long long> cols;
+};
+
+namespace {
+
+dm_status set_err(dm_ctx* c, dm_status st, const std::string& msg) {
+    c->err = msg;
+    return st;
+}
+
+dm_status fail_hip(dm_ctx* c, hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return set_err(c, DM_E_OOM, std::string("out of device memory: ") + what);
+    }
+    c->poisoned = true;
+    return set_err(c, DM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPTRY(c, expr)                                   \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return fail_hip(c, e_, #expr); \
+    } while (0)
+
+template <typename T>
+hipError_t ensure(DevBuf<T>& b, size_t n) {
+    if (b.n >= n && b.p) return hipSuccess;
+    b.release();
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&b.p), std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.n = n;
+    return hipSuccess;
+}
+
+dm_status enter(dm_ctx* c) {
+    if (!c) return DM_E_ARG;
+    if (c->poisoned) return set_err(c, DM_E_STATE, "context poisoned by an earlier HIP error");
+    HIPTRY(c, hipSetDevice(c->opt.device));
+    c->err.clear();
+    return DM_OK;
+}
+
+template <typename T>
+hipError_t to_host(std::vector<T>& dst, const T* src, size_t n) {
+    dst.resize(n);
+    if (n == 0) return hipSuccess;
+    return hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDefault);
+}
+
+// Checks a CSR matrix copied to the host; returns an empty string when valid.
+std::string check_csr(const char* name, long long K, const std::vector<long long>& rp,
+                      const std::vector<int>& col, const std::vector<double>& val,
+                      bool positive_diag) {
+    if (rp[0] != 0) return std::string(name) + ": rowptr[0] != 0";
+    for (long long r = 0; r < K; ++r) {
+        if (rp[r + 1] < rp[r]) return std::string(name) + ": rowptr not monotone";
+        bool diag = false;
+        for (long long p = rp[r]; p < rp[r + 1]; ++p) {
+            if (col[p] < 0 || col[p] >= K) return std::string(name) + ": column index out of range";
+            if (p > rp[r] && col[p] <= col[p - 1])
+                return std::string(name) + ": columns not sorted/unique within a row";
+            if (!std::isfinite(val[p])) return std::string(name) + ": non-finite value";
+            if (col[p] == r) {
+                diag = true;
+                if (positive_diag && !(val[p] > 0)) return std::string(name) + ": non-positive diagonal";
+            }
+        }
+        if (positive_diag && !diag) return std::string(name) + ": missing diagonal entry";
+    }
+    return "";
+}
+
+// -------------------------------------------------------------- tridiagonal
+// Number of eigenvalues of the symmetric tridiagonal (a, b) below x (Sturm count).
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const double bb = i ? b[i - 1] * b[i - 1] : 0.0;
+        d = a[i] - x - (i ? bb / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int idx) {
+    double lo = 1e300, hi = -1e300;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(a, b, mid) > idx)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// |last component| of the unit eigenvector of (a, b) for eigenvalue theta,
+// by three steps of inverse iteration with a dense LU (k is at most a few
+// hundred, so the k^3 host work is negligible).
+double tridiag_last_component(const std::vector<double>& a, const std::vector<double>& b,
+                              double theta) {
+    const int n = (int)a.size();
+    if (n == 1) return 1.0;
+    const double shift = theta + 1e-10 * (std::fabs(theta) + 1.0);
+    std::vector<double> LU((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        LU[(size_t)i * n + i] = a[i] - shift;
+        if (i + 1 < n) LU[(size_t)i * n + i + 1] = LU[(size_t)(i + 1) * n + i] = b[i];
+    }
+    std::vector<int> piv(n);
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(LU[(size_t)i * n + k]) > std::fabs(LU[(size_t)p * n + k])) p = i;
+        piv[k] = p;
+        if (p != k)
+            for (int j = 0; j < n; ++j) std::swap(LU[(size_t)k * n + j], LU[(size_t)p * n + j]);
+        double d = LU[(size_t)k * n + k];
+        if (d == 0.0) d = LU[(size_t)k * n + k] = 1e-300;
+        for (int i = k + 1; i < n; ++i) {
+            const double f = (LU[(size_t)i * n + k] /= d);
+            if (f != 0.0)
+                for (int j = k + 1; j < n; ++j) LU[(size_t)i * n + j] -= f * LU[(size_t)k * n + j];
+        }
+    }
+    std::vector<double> y(n, 1.0);
+    for (int rep = 0; rep < 3; ++rep) {
+        for (int k = 0; k < n; ++k) std::swap(y[k], y[piv[k]]);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < i; ++j) y[i] -= LU[(size_t)i * n + j] * y[j];
+        for (int i = n - 1; i >= 0; --i) {
+            for (int j = i + 1; j < n; ++j) y[i] -= LU[(size_t)i * n + j] * y[j];
+            y[i] /= LU[(size_t)i * n + i];
+        }
+        double nrm = 0;
+        for (double x : y) nrm += x * x;
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0) || !std::isfinite(nrm)) return 1.0;
+        for (double& x : y) x /= nrm;
+    }
+    return std::fabs(y[n - 1]);
+}
+
+// ------------------------------------------------------------------ Lanczos
+dm_status lanczos_bounds(dm_ctx* c) {
+    const int K = (int)c->K, ld = c->Kp;
+    const int ksteps = std::max(1, std::min<int>(c->opt.lanczos_steps > 0 ? c->opt.lanczos_steps : 100, K));
+    hipStream_t s = c->stream;
+    DevBuf<double> V, Q, wv, sw, cc, ab, sc;
+    auto cleanup = [&]() {
+        V.release(); Q.release(); wv.release(); sw.release(); cc.release(); ab.release(); sc.release();
+    };
+    hipError_t e = hipSuccess;
+    if ((e = ensure(V, (size_t)ld * (ksteps + 1))) != hipSuccess ||
+        (e = ensure(Q, (size_t)ld * (ksteps + 1))) != hipSuccess ||
+        (e = ensure(wv, (size_t)ld)) != hipSuccess || (e = ensure(sw, (size_t)ld)) != hipSuccess ||
+        (e = ensure(cc, (size_t)ksteps + 1)) != hipSuccess ||
+        (e = ensure(ab, (size_t)2 * ksteps)) != hipSuccess || (e = ensure(sc, 4)) != hipSuccess) {
+        cleanup();
+        return fail_hip(c, e, "lanczos buffers");
+    }
+    double* alpha = ab.p;
+    double* beta = ab.p + ksteps;
+    const long long* rp = c->S_rowptr.p;
+    const int* ci = c->S_col.p;
+    const double* sv = c->S_val.p;
+#define LZ(expr)                          \
+    do {                                  \
+        if ((e = (expr)) != hipSuccess) { \
+            cleanup();                    \
+            return fail_hip(c, e, #expr); \
+        }                                 \
+    } while (0)
+    LZ(random_vector(K, c->opt.seed, V.p, s));
+    LZ(csr_spmv(K, rp, ci, sv, V.p, Q.p, s));
+    LZ(dots_cols(K, 1, V.p, ld, Q.p, sc.p, s));
+    LZ(lanczos_normalize_start(K, V.p, Q.p, sc.p, s));
+    for (int j = 0; j < ksteps; ++j) {
+        double* vj = V.p + (size_t)j * ld;
+        double* qj = Q.p + (size_t)j * ld;
+        LZ(gemv_rows(K, c->HT.p, ld, vj, wv.p, s));
+        LZ(dots_cols(K, 1, qj, ld, wv.p, alpha + j, s));
+        LZ(lanczos_three_term(K, wv.p, vj, j ? vj - ld : nullptr, alpha + j, j ? beta + j - 1 : beta, s));
+        for (int rep = 0; rep < 2; ++rep) {
+            LZ(dots_cols(K, j + 1, Q.p, ld, wv.p, cc.p, s));
+            LZ(lanczos_reorth(K, j + 1, wv.p, V.p, ld, cc.p, s));
+        }
+        LZ(csr_spmv(K, rp, ci, sv, wv.p, sw.p, s));
+        LZ(dots_cols(K, 1, wv.p, ld, sw.p, sc.p + 1, s));
+        LZ(lanczos_next(K, wv.p, sw.p, sc.p + 1, beta + j, V.p + (size_t)(j + 1) * ld,
+                        Q.p + (size_t)(j + 1) * ld, s));
+    }
+#undef LZ
+    std::vector<double> h(2 * ksteps);
+    e = hipMemcpyAsync(h.data(), ab.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) return fail_hip(c, e, "lanczos readback");
+    std::vector<double> a(h.begin(), h.begin() + ksteps), b(h.begin() + ksteps, h.end());
+    double scale = 0;
+    for (double x : a) scale = std::max(scale, std::fabs(x));
+    for (double x : a)
+        if (!std::isfinite(x)) return set_err(c, DM_E_NOCONV, "Lanczos produced non-finite values");
+    // truncate at an invariant subspace
+    int k = ksteps;
+    for (int j = 0; j < ksteps; ++j)
+        if (!(b[j] > 1e-12 * (scale + 1e-300))) {
+            k = j + 1;
+            break;
+        }
+    a.resize(k);
+    const double beta_last = b[k - 1];
+    b.resize(k - 1);
+    const double th_lo = tridiag_eig(a, b, 0), th_hi = tridiag_eig(a, b, k - 1);
+    const double r_lo = beta_last * tridiag_last_component(a, b, th_lo);
+    const double r_hi = beta_last * tridiag_last_component(a, b, th_hi);
+    const double margin = c->opt.bound_margin > 0 ? c->opt.bound_margin : 0.01;
+    const double width = std::max(th_hi - th_lo, 1e-12 * (std::fabs(th_hi) + 1.0));
+    c->lz_emin = th_lo;
+    c->lz_emax = th_hi;
+    c->lz_resid_lo = r_lo;
+    c->lz_resid_hi = r_hi;
+    c->lz_steps_done = k;
+    c->emin = th_lo - std::fabs(r_lo) - margin * width;
+    c->emax = th_hi + std::fabs(r_hi) + margin * width;
+    return DM_OK;
+}
+
+dm_status normalize(dm_ctx* c) {
+    const double ebar = 0.5 * (c->emax + c->emin), de = 0.5 * (c->emax - c->emin);
+    HIPTRY(c, normalize_operator((int)c->K, c->Kp, c->HT.p, ebar, de, c->precision, c->HNbuf.p, c->stream));
+    return DM_OK;
+}
+
+dm_status reset_moments(dm_ctx* c) {
+    c->mom_order = -1;
+    c->ncols_done = 0;
+    return DM_OK;
+}
+
+// Tile shape for a pass: the widest tile whose grid still gives every CU two
+// workgroups, else the one with the most workgroups.
+int pick_cfg(int Kp, int ncols) {
+    int best = -1, best_tiles = -1;
+    for (int cfg = 0; cfg < cheb_num_tile_configs(); ++cfg) {
+        const int BN = cheb_tile_cols(cfg);
+        const int Bp = (int)round_up(std::max(ncols, 1), BN);
+        if (Bp > round_up(std::max(ncols, 1), 32) * 2 && BN > 32) continue;  // too much padding
+        const int tiles = cheb_num_tiles(Kp, Bp, cfg);
+        if (tiles >= 512) return cfg;
+        if (tiles > best_tiles) {
+            best_tiles = tiles;
+            best = cfg;
+        }
+    }
+    return best < 0 ? 0 : best;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void dm_default_options(dm_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->device = 0;
+    opt->stream = nullptr;
+    opt->precision = DM_FP64;
+    opt->block_width = 0;
+    opt->spin = 2.0;
+    opt->lanczos_steps = 100;
+    opt->bound_margin = 0.01;
+    opt->seed = 12345;
+}
+
+dm_status dm_init(dm_ctx** out, const dm_options* opt) {
+    if (!out) {
+        g_init_error = "dm_init: out is NULL";
+        return DM_E_ARG;
+    }
+    *out = nullptr;
+    dm_options o;
+    if (opt)
+        o = *opt;
+    else
+        dm_default_options(&o);
+    if ((o.precision != DM_FP64 && o.precision != DM_FP32) || o.block_width < 0 ||
+        !(o.spin > 0) || o.lanczos_steps < 0 || o.device < 0) {
+        g_init_error = "dm_init: invalid option";
+        return DM_E_ARG;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || o.device >= ndev) {
+        (void)hipGetLastError();
+        g_init_error = std::string("dm_init: no HIP device ") + std::to_string(o.device);
+        return DM_E_HIP;
+    }
+    e = hipSetDevice(o.device);
+    if (e != hipSuccess) {
+        g_init_error = std::string("dm_init: hipSetDevice: ") + hipGetErrorString(e);
+        return DM_E_HIP;
+    }
+    dm_ctx* c = new (std::nothrow) dm_ctx();
+    if (!c) {
+        g_init_error = "dm_init: host allocation failed";
+        return DM_E_OOM;
+    }
+    c->opt = o;
+    c->precision = o.precision;
+    if (o.stream) {
+        c->stream = static_cast<hipStream_t>(o.stream);
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete c;
+            g_init_error = std::string("dm_init: stream: ") + hipGetErrorString(e);
+            return DM_E_HIP;
+        }
+        c->own_stream = true;
+    }
+    if (ensure(c->flag, 4) != hipSuccess || ensure(c->out, 8) != hipSuccess) {
+        dm_destroy(c);
+        g_init_error = "dm_init: device allocation failed";
+        return DM_E_OOM;
+    }
+    *out = c;
+    return DM_OK;
+}
+
+void dm_destroy(dm_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->opt.device);
+    if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
+    for (auto* b : {&c->Sinv, &c->HT, &c->HNbuf, &c->S_val, &c->mom, &c->Ua, &c->Ub, &c->Z, &c->P,
+                    &c->part_start, &c->part_steps, &c->coef, &c->coef_zero, &c->fk, &c->w, &c->v,
+                    &c->out})
+        b->release();
+    c->S_rowptr.release();
+    c->S_col.release();
+    c->flag.release();
+    c->cols.release();
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* dm_last_error(const dm_ctx* c) {
+    if (!c) return g_init_error.c_str();
+    return c->err.c_str();
+}
+
+dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const int* F_col,
+                      const double* F_val, const long long* S_rowptr, const int* S_col,
+                      const double* S_val, int atom_block) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (K <= 0 || K > (1LL << 30)) return set_err(c, DM_E_ARG, "K out of range");
+    if (!F_rowptr || !F_col || !F_val || !S_rowptr || !S_col || !S_val)
+        return set_err(c, DM_E_ARG, "null CSR array");
+    if (atom_block < 1 || K % atom_block) return set_err(c, DM_E_ARG, "K not a multiple of atom_block");
+    c->have_fock = false;
+    reset_moments(c);
+    // ---- copy to host and validate
+    std::vector<long long> frp, srp;
+    std::vector<int> fcol, scol;
+    std::vector<double> fval, sval;
+    HIPTRY(c, to_host(frp, F_rowptr, (size_t)K + 1));
+    HIPTRY(c, to_host(srp, S_rowptr, (size_t)K + 1));
+    if (frp[K] < 0 || srp[K] < 0 || frp[0] != 0 || srp[0] != 0)
+        return set_err(c, DM_E_ARG, "malformed rowptr");
+    HIPTRY(c, to_host(fcol, F_col, (size_t)frp[K]));
+    HIPTRY(c, to_host(fval, F_val, (size_t)frp[K]));
+    HIPTRY(c, to_host(scol, S_col, (size_t)srp[K]));
+    HIPTRY(c, to_host(sval, S_val, (size_t)srp[K]));
+    std::string msg = check_csr("F", K, frp, fcol, fval, false);
+    if (msg.empty()) msg = check_csr("S", K, srp, scol, sval, true);
+    if (!msg.empty()) return set_err(c, DM_E_ARG, msg);
+
+    hipStream_t s = c->stream;
+    c->K = K;
+    c->Kp = (int)round_up(K, kRowPad);
+    const int Kp = c->Kp;
+    const size_t KK = (size_t)Kp * Kp;
+    // ---- device copies of S (kept) and F (temporary)
+    HIPTRY(c, ensure(c->S_rowptr, (size_t)K + 1));
+    HIPTRY(c, ensure(c->S_col, sval.size()));
+    HIPTRY(c, ensure(c->S_val, sval.size()));
+    HIPTRY(c, hipMemcpyAsync(c->S_rowptr.p, srp.data(), srp.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(c->S_col.p, scol.data(), scol.size() * 4, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(c->S_val.p, sval.data(), sval.size() * 8, hipMemcpyHostToDevice, s));
+    DevBuf<long long> Frp;
+    DevBuf<int> Fci;
+    DevBuf<double> Fv, Vblk, tmp;
+    auto release_tmp = [&]() { Frp.release(); Fci.release(); Fv.release(); Vblk.release(); tmp.release(); };
+    hipError_t e;
+#define ST(expr)                          \
+    do {                                  \
+        if ((e = (expr)) != hipSuccess) { \
+            release_tmp();                \
+            return fail_hip(c, e, #expr); \
+        }                                 \
+    } while (0)
+    ST(ensure(Frp, (size_t)K + 1));
+    ST(ensure(Fci, fval.size()));
+    ST(ensure(Fv, fval.size()));
+    ST(hipMemcpyAsync(Frp.p, frp.data(), frp.size() * 8, hipMemcpyHostToDevice, s));
+    ST(hipMemcpyAsync(Fci.p, fcol.data(), fcol.size() * 4, hipMemcpyHostToDevice, s));
+    ST(hipMemcpyAsync(Fv.p, fval.data(), fval.size() * 8, hipMemcpyHostToDevice, s));
+    // ---- dense buffers: A (S -> U -> F -> HN), X (U^-T -> H^T), Sinv
+    ST(ensure(c->HNbuf, KK));
+    ST(ensure(c->HT, KK));
+    ST(ensure(c->Sinv, KK));
+    ST(ensure(Vblk, (size_t)Kp * kNb));
+    ST(ensure(tmp, (size_t)Kp * kNb));
+    double* A = c->HNbuf.p;
+    double* X = c->HT.p;
+    const long ld = Kp;
+    ST(fill_f64(A, 0.0, (long long)KK, s));
+    ST(csr_to_dense((int)K, Kp, c->S_rowptr.p, c->S_col.p, c->S_val.p, 1.0, A, s));
+    ST(fill_i32(c->flag.p, 0, 4, s));
+    // ---- blocked Cholesky S = U^T U (upper, right-looking)
+    for (int k = 0; k < Kp; k += kNb) {
+        double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
+        ST(potrf_diag(A + k + (long)k * ld, ld, Vk, c->flag.p, k, s));
+        const int n2 = Kp - k - kNb;
+        if (n2 > 0) {
+            // U12 = U_kk^-T A12, then A22 -= U12^T U12 (upper tiles only)
+            ST(gemm_tn_f64(kNb, n2, kNb, 1.0, Vk, kNb, A + k + (long)(k + kNb) * ld, ld, 0.0, tmp.p,
+                           kNb, false, s));
+            ST(hipMemcpy2DAsync(A + k + (long)(k + kNb) * ld, ld * 8, tmp.p, kNb * 8, kNb * 8, n2,
+                                hipMemcpyDeviceToDevice, s));
+            ST(gemm_tn_f64(n2, n2, kNb, -1.0, tmp.p, kNb, tmp.p, kNb, 1.0,
+                           A + (k + kNb) + (long)(k + kNb) * ld, ld, true, s));
+        }
+    }
+    int info[4] = {0, 0, 0, 0};
+    ST(hipMemcpyAsync(info, c->flag.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    if (info[0] != 0) {
+        release_tmp();
+        return set_err(c, DM_E_NOTSPD, "overlap matrix is not positive definite (pivot " +
+                                           std::to_string(info[0] - 1) + ")");
+    }
+    // ---- X = U^-T (lower) by block forward substitution
+    ST(fill_f64(X, 0.0, (long long)KK, s));
+    for (int k = 0; k < Kp; k += kNb) {
+        const double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
+        if (k > 0) {
+            ST(gemm_tn_f64(kNb, k, k, -1.0, A + (long)k * ld, ld, X, ld, 0.0, tmp.p, kNb, false, s));
+            ST(gemm_tn_f64(kNb, k, kNb, 1.0, Vk, kNb, tmp.p, kNb, 0.0, X + k, ld, false, s));
+        }
+        ST(copy_transpose_block(Vk, kNb, X + k + (long)k * ld, ld, s));
+    }
+    // ---- S^-1 = X^T X, then A := F and H^T = F S^-1
+    ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, X, ld, X, ld, 0.0, c->Sinv.p, ld, false, s));
+    ST(fill_f64(A, 0.0, (long long)KK, s));
+    ST(csr_to_dense((int)K, Kp, Frp.p, Fci.p, Fv.p, 0.0, A, s));
+    ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, A, ld, c->Sinv.p, ld, 0.0, X, ld, false, s));
+    ST(hipStreamSynchronize(s));
+    release_tmp();
+#undef ST
+    c->have_fock = true;
+    st = lanczos_bounds(c);
+    if (st != DM_OK) {
+        c->have_fock = false;
+        return st;
+    }
+    st = normalize(c);
+    if (st != DM_OK) {
+        c->have_fock = false;
+        return st;
+    }
+    return DM_OK;
+}
+
+dm_status dm_get_bounds(dm_ctx* c, double* emin, double* emax) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (emin) *emin = c->emin;
+    if (emax) *emax = c->emax;
+    return DM_OK;
+}
+
+dm_status dm_set_bounds(dm_ctx* c, double emin, double emax) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (!std::isfinite(emin) || !std::isfinite(emax) || !(emin < emax))
+        return set_err(c, DM_E_ARG, "need finite emin < emax");
+    c->emin = emin;
+    c->emax = emax;
+    reset_moments(c);
+    return normalize(c);
+}
+
+dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (!out || (which != DM_OP_SINV && which != DM_OP_H)) return set_err(c, DM_E_ARG, "bad operator request");
+    const size_t K = (size_t)c->K, Kp = (size_t)c->Kp;
+    hipStream_t s = c->stream;
+    if (which == DM_OP_SINV) {
+        HIPTRY(c, hipMemcpy2DAsync(out, K * 8, c->Sinv.p, Kp * 8, K * 8, K, hipMemcpyDefault, s));
+    } else {
+        // HT holds H^T column-major; transpose through a device scratch buffer
+        DevBuf<double> t;
+        HIPTRY(c, ensure(t, K * K));
+        HIPTRY(c, hipMemcpy2DAsync(t.p, K * 8, c->HT.p, Kp * 8, K * 8, K, hipMemcpyDeviceToDevice, s));
+        std::vector<double> h(K * K), ht(K * K);
+        hipError_t e = hipMemcpyAsync(ht.data(), t.p, K * K * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        t.release();
+        if (e != hipSuccess) return fail_hip(c, e, "operator readback");
+        for (size_t i = 0; i < K; ++i)
+            for (size_t j = 0; j < K; ++j) h[i + j * K] = ht[j + i * K];
+        HIPTRY(c, hipMemcpy(out, h.data(), K * K * 8, hipMemcpyDefault));
+    }
+    HIPTRY(c, hipStreamSynchronize(s));
+    return DM_OK;
+}
+
+dm_status dm_set_precision(dm_ctx* c, int precision) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (precision != DM_FP64 && precision != DM_FP32) return set_err(c, DM_E_ARG, "bad precision");
+    c->precision = precision;
+    reset_moments(c);
+    if (!c->have_fock) return DM_OK;
+    return normalize(c);
+}
+
+dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, int order,
+                             double mu, double beta, double* P_out) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (order < 2 || order > (1 << 20)) return set_err(c, DM_E_ARG, "order must be >= 2");
+    if (!std::isfinite(mu) || !std::isfinite(beta) || !(beta > 0))
+        return set_err(c, DM_E_ARG, "need finite mu and beta > 0");
+    if (ncols < 0 || ncols > c->K) return set_err(c, DM_E_ARG, "ncols out of range");
+    if (ncols > 0 && !cols) return set_err(c, DM_E_ARG, "cols is NULL");
+    const long long K = c->K;
+    std::vector<long long> hc;
+    HIPTRY(c, to_host(hc, cols, (size_t)ncols));
+    {
+        std::vector<char> seen((size_t)K, 0);
+        for (long long x : hc) {
+            if (x < 0 || x >= K) return set_err(c, DM_E_ARG, "column index out of range");
+            if (seen[x]) return set_err(c, DM_E_ARG, "repeated column index");
+            seen[x] = 1;
+        }
+    }
+    hipStream_t s = c->stream;
+    const int Kp = c->Kp;
+    if (order != c->mom_order) {
+        HIPTRY(c, ensure(c->mom, (size_t)order + 1));
+        HIPTRY(c, fill_f64(c->mom.p, 0.0, order + 1, s));
+        c->mom_order = order;
+        c->ncols_done = 0;
+    }
+    if (ncols == 0) return DM_OK;
+    const double ebar = 0.5 * (c->emax + c->emin), de = 0.5 * (c->emax - c->emin);
+    const int M = 4 * order;
+    HIPTRY(c, ensure(c->coef, (size_t)order + 1));
+    HIPTRY(c, ensure(c->fk, (size_t)M));
+    HIPTRY(c, cheb_coefficients(order, M, ebar, de, mu, beta, c->fk.p, c->coef.p, s));
+    HIPTRY(c, fill_i32(c->flag.p, 0, 4, s));
+
+    // pass width
+    const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
+    long long bw = c->opt.block_width > 0 ? c->opt.block_width : ncols;
+    const size_t budget = (size_t)16 << 30;
+    const size_t per_col = (size_t)Kp * (2 * tsz + 16);
+    bw = std::min<long long>(bw, std::max<long long>(128, (long long)(budget / per_col) / 128 * 128));
+    bw = std::min(bw, ncols);
+    const int cfg = pick_cfg(Kp, (int)bw);
+    const int BN = cheb_tile_cols(cfg);
+    const int Bp_max = (int)round_up(bw, std::max(BN, 16));
+    HIPTRY(c, ensure(c->Ua, (size_t)Kp * Bp_max * tsz / 8));
+    HIPTRY(c, ensure(c->Ub, (size_t)Kp * Bp_max * tsz / 8));
+    HIPTRY(c, ensure(c->Z, (size_t)Kp * Bp_max));
+    HIPTRY(c, ensure(c->P, (size_t)Kp * Bp_max));
+    HIPTRY(c, ensure(c->cols, (size_t)Bp_max));
+    const int nts_step = cheb_num_tiles(Kp, Bp_max, cfg);
+    HIPTRY(c, ensure(c->part_steps, (size_t)(order + 1) * nts_step));
+    HIPTRY(c, ensure(c->part_start, (size_t)(Kp / 64) * (Bp_max / 16)));
+
+    for (long long off = 0; off < ncols; off += bw) {
+        const int nc = (int)std::min<long long>(bw, ncols - off);
+        const int Bp = (int)round_up(nc, std::max(BN, 16));
+        HIPTRY(c, hipMemcpyAsync(c->cols.p, hc.data() + off, (size_t)nc * 8, hipMemcpyHostToDevice, s));
+        HIPTRY(c, fill_f64(c->Z.p, 0.0, (long long)Kp * Bp, s));
+        int nts = 0;
+        HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, c->Sinv.p, c->S_rowptr.p, c->S_col.p,
+                             c->S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p,
+                             c->part_start.p, &nts, s));
+        HIPTRY(c, reduce_moments(0, nts, c->part_start.p, c->mom.p, c->flag.p, s));
+        void* ucur = c->Ua.p;
+        void* uoth = c->Ub.p;
+        ChebStepArgs a{};
+        a.Kp = Kp;
+        a.Bp = Bp;
+        a.HN = c->HNbuf.p;
+        a.coef = c->coef.p;
+        a.P = c->P.p;
+        a.Z = c->Z.p;
+        a.partial = c->part_steps.p;
+        const int ntl = cheb_num_tiles(Kp, Bp, cfg);
+        for (int l = 1; l <= order; ++l) {
+            a.Ucur = ucur;
+            a.Uprev = (l == 1) ? nullptr : uoth;
+            a.Unext = uoth;
+            a.alpha = (l == 1) ? 1.0 : 2.0;
+            a.has_prev = (l > 1);
+            a.l = l;
+            hipError_t e = c->precision == DM_FP64 ? cheb_step_f64(a, cfg, s) : cheb_step_f32(a, cfg, s);
+            if (e != hipSuccess) return fail_hip(c, e, "cheb_step");
+            std::swap(ucur, uoth);
+        }
+        HIPTRY(c, reduce_moments(order - 1, ntl, c->part_steps.p + ntl, c->mom.p + 1, c->flag.p, s));
+        if (P_out)
+            HIPTRY(c, hipMemcpy2DAsync(P_out + off * K, (size_t)K * 8, c->P.p, (size_t)Kp * 8,
+                                       (size_t)K * 8, nc, hipMemcpyDefault, s));
+    }
+    int flag = 0;
+    HIPTRY(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<double> hm((size_t)order + 1);
+    HIPTRY(c, hipMemcpyAsync(hm.data(), c->mom.p, hm.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    c->ncols_done += ncols;
+    const double lim = 1e8 * (double)(c->ncols_done + 1);
+    bool bad = flag != 0;
+    for (double x : hm)
+        if (!std::isfinite(x) || std::fabs(x) > lim) bad = true;
+    if (bad)
+        return set_err(c, DM_E_BOUNDS,
+                       "Chebyshev recursion diverged: the spectral interval does not enclose the spectrum");
+    return DM_OK;
+}
+
+static dm_status eval_trace(dm_ctx* c, double beta, double target, double tol, double mu_in,
+                            int max_iter, double out[5]) {
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (c->mom_order < 2 || c->ncols_done == 0) return set_err(c, DM_E_STATE, "no accumulated moments");
+    if (!std::isfinite(beta) || !(beta > 0)) return set_err(c, DM_E_ARG, "need beta > 0");
+    hipStream_t s = c->stream;
+    const int N = c->mom_order, M = 4 * N;
+    const double ebar = 0.5 * (c->emax + c->emin), de = 0.5 * (c->emax - c->emin);
+    HIPTRY(c, ensure(c->w, (size_t)M));
+    HIPTRY(c, ensure(c->v, (size_t)M));
+    HIPTRY(c, trace_weights(N, M, ebar, de, c->mom.p, c->w.p, c->v.p, s));
+    HIPTRY(c, mu_bisect(M, ebar, de, beta, target, tol, c->emin, c->emax, mu_in, max_iter, c->w.p,
+                        c->v.p, c->out.p, s));
+    HIPTRY(c, hipMemcpyAsync(out, c->out.p, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    return DM_OK;
+}
+
+dm_status dm_trace(dm_ctx* c, double mu, double beta, double* tr_PS, double* e_band) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!std::isfinite(mu)) return set_err(c, DM_E_ARG, "mu not finite");
+    double out[5];
+    st = eval_trace(c, beta, 0.0, 0.0, mu, 0, out);
+    if (st != DM_OK) return st;
+    if (tr_PS) *tr_PS = out[1];
+    if (e_band) *e_band = c->opt.spin * out[2];
+    return DM_OK;
+}
+
+dm_status dm_solve_mu(dm_ctx* c, double n_e, double beta, double tol, double* mu) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!mu || !std::isfinite(n_e) || !(tol > 0)) return set_err(c, DM_E_ARG, "bad n_e, tol or mu");
+    double out[5];
+    st = eval_trace(c, beta, n_e / c->opt.spin, tol / c->opt.spin, 0.0, 200, out);
+    if (st != DM_OK) return st;
+    *mu = out[0];
+    if (out[3] == 0.0)
+        return set_err(c, DM_E_NOCONV, "bisection bracket collapsed before reaching the tolerance");
+    return DM_OK;
+}
+
+dm_status dm_moments(dm_ctx* c, double* m, int n, long long* ncols_done) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (n < 0) return set_err(c, DM_E_ARG, "n < 0");
+    if (ncols_done) *ncols_done = c->mom_order < 0 ? 0 : c->ncols_done;
+    if (m && n > 0) {
+        std::fill(m, m + n, 0.0);
+        const int avail = c->mom_order < 0 ? 0 : std::min(n, c->mom_order + 1);
+        if (avail > 0) {
+            HIPTRY(c, hipMemcpyAsync(m, c->mom.p, (size_t)avail * 8, hipMemcpyDeviceToHost, c->stream));
+            HIPTRY(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    return DM_OK;
+}
+
+dm_status dm_reset_moments(dm_ctx* c) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    return reset_moments(c);
+}
+
+dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, double* m_out) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (n_mom < 1 || n_vec < 1 || !xi || !m_out) return set_err(c, DM_E_ARG, "bad stochastic-moment arguments");
+    hipStream_t s = c->stream;
+    const int K = (int)c->K, Kp = c->Kp;
+    const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
+    const int cfg = pick_cfg(Kp, n_vec);
+    const int BN = cheb_tile_cols(cfg);
+    const int Bp = (int)round_up(n_vec, std::max(BN, 16));
+    DevBuf<double> X, U0, U1, Zs, Pd, pst, pss, ms, cz;
+    auto rel = [&]() { X.release(); U0.release(); U1.release(); Zs.release(); Pd.release(); pst.release(); pss.release(); ms.release(); cz.release(); };
+    hipError_t e;
+#define SM(expr)                          \
+    do {                                  \
+        if ((e = (expr)) != hipSuccess) { \
+            rel();                        \
+            return fail_hip(c, e, #expr); \
+        }                                 \
+    } while (0)
+    const int ntl = cheb_num_tiles(Kp, Bp, cfg);
+    SM(ensure(X, (size_t)K * n_vec));
+    SM(ensure(U0, (size_t)Kp * Bp * tsz / 8));
+    SM(ensure(U1, (size_t)Kp * Bp * tsz / 8));
+    SM(ensure(Zs, (size_t)Kp * Bp));
+    SM(ensure(Pd, 4));
+    SM(ensure(pst, (size_t)(Kp / 64) * (Bp / 16)));
+    SM(ensure(pss, (size_t)std::max(n_mom, 1) * ntl));
+    SM(ensure(ms, (size_t)n_mom));
+    SM(ensure(cz, (size_t)n_mom + 1));
+    SM(hipMemcpyAsync(X.p, xi, (size_t)K * n_vec * 8, hipMemcpyDefault, s));
+    SM(fill_f64(ms.p, 0.0, n_mom, s));
+    SM(fill_f64(cz.p, 0.0, n_mom + 1, s));
+    SM(fill_i32(c->flag.p, 0, 4, s));
+    int nts = 0;
+    SM(cheb_start_vectors(K, Kp, Bp, n_vec, X.p, 1.0 / n_vec, c->precision, U0.p, Zs.p, pst.p, &nts, s));
+    SM(reduce_moments(0, nts, pst.p, ms.p, c->flag.p, s));
+    void* ucur = U0.p;
+    void* uoth = U1.p;
+    ChebStepArgs a{};
+    a.Kp = Kp;
+    a.Bp = Bp;
+    a.HN = c->HNbuf.p;
+    a.coef = cz.p;
+    a.P = Pd.p;
+    a.Z = Zs.p;
+    a.partial = pss.p;
+    for (int l = 1; l < n_mom; ++l) {
+        a.Ucur = ucur;
+        a.Uprev = (l == 1) ? nullptr : uoth;
+        a.Unext = uoth;
+        a.alpha = (l == 1) ? 1.0 : 2.0;
+        a.has_prev = (l > 1);
+        a.l = l;
+        SM(c->precision == DM_FP64 ? cheb_step_f64(a, cfg, s) : cheb_step_f32(a, cfg, s));
+        std::swap(ucur, uoth);
+    }
+    if (n_mom > 1) SM(reduce_moments(n_mom - 2, ntl, pss.p + ntl, ms.p + 1, c->flag.p, s));
+    SM(hipMemcpyAsync(m_out, ms.p, (size_t)n_mom * 8, hipMemcpyDeviceToHost, s));
+    SM(hipStreamSynchronize(s));
+#undef SM
+    rel();
+    return DM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dm {
+
+// Operator and column dimensions are padded to these multiples so that the
+// matrix kernels run without edge checks.  Padding rows/columns of the
+// operator are zero, padding columns of a block start at zero and stay zero.
+constexpr int kRowPad = 256;
+constexpr int kColPad = 128;
+// Block size of the blocked Cholesky and triangular inverse.
+constexpr int kNb = 64;
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// ----------------------------------------------------------------- launches
+// All launch wrappers return the hipError_t of the launch.
+
+// C[m + n*ldc] = alpha * sum_k A[m*lda + k] * B[n*ldb + k] + beta * C[...]
+// M, N multiples of 64, Kred multiple of 16, operands FP64.  With
+// upper_only, output tiles entirely below the diagonal (m0 >= n0 + tile) are
+// skipped (used where only the upper triangle of a symmetric result is read).
+hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, long lda,
+                       const double* B, long ldb, double beta, double* C, long ldc,
+                       bool upper_only, hipStream_t s);
+
+// One step of the Chebyshev column recursion with the fused epilogue:
+//   Unext = alpha * (HN * Ucur) - (has_prev ? Uprev : 0)      (storage T)
+//   P    += coef[l] * Unext                                    (FP64)
+//   partial[l * ntiles + tile] = sum over the tile of Z .* Unext (FP64)
+// HN: Kp x Kp, row-major (row m contiguous); U*, P, Z: Kp x Bp column-major
+// (ld = Kp).  Unext may alias Uprev.  `cfg` selects the tile shape
+// (see cheb_tile_configs); Bp must be a multiple of that shape's column tile.
+struct ChebStepArgs {
+    int Kp, Bp;
+    const void* HN;
+    const void* Ucur;
+    const void* Uprev;
+    void* Unext;
+    double alpha;
+    int has_prev;
+    const double* coef;
+    int l;
+    double* P;
+    const double* Z;
+    double* partial;
+};
+int cheb_num_tile_configs();
+int cheb_tile_cols(int cfg);
+int cheb_tile_rows(int cfg);
+hipError_t cheb_step_f64(const ChebStepArgs& a, int cfg, hipStream_t s);
+hipError_t cheb_step_f32(const ChebStepArgs& a, int cfg, hipStream_t s);
+int cheb_num_tiles(int Kp, int Bp, int cfg);
+
+// U0[:, j] = Sinv[:, cols[j]] (rounded to T), Z[:, j] = column cols[j] of S
+// (from its CSR rows; S is symmetric), P[:, j] = coef[0] * Sinv[:, cols[j]],
+// partial[t] = per-tile sums of Z .* U0 for t < ntiles(start).  Columns
+// j >= ncols are zero.  Z must be zero on entry.
+hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, const double* Sinv,
+                      const long long* S_rowptr, const int* S_col, const double* S_val,
+                      int precision, void* U0, double* Z, double* P, const double* coef,
+                      double* partial, int* ntiles_out, hipStream_t s);
+
+// Start block from caller vectors: U0 = X (rounded to T), Z = X * zscale.
+hipError_t cheb_start_vectors(int K, int Kp, int Bp, int nvec, const double* X, double zscale,
+                              int precision, void* U0, double* Z, double* partial, int* ntiles_out,
+                              hipStream_t s);
+
+// mom[l] += sum_t partial[l * ntiles + t], l <= lmax, fixed summation order;
+// flag[0] |= 1 if any partial sum is not finite.
+hipError_t reduce_moments(int lmax, int ntiles, const double* partial, double* mom, int* flag,
+                          hipStream_t s);
+
+// a[l] for l < N: Chebyshev coefficients of f_FD(.; mu, beta) on [ebar-de, ebar+de]
+// from M Chebyshev-Gauss nodes; a[N] = 0.
+hipError_t cheb_coefficients(int N, int M, double ebar, double de, double mu, double beta,
+                             double* fk_scratch, double* a, hipStream_t s);
+
+// Trace quadrature weights from moments m[0..N] (N terms, m[N] used for the
+// band energy): w_k, v_k for k < M.
+hipError_t trace_weights(int N, int M, double ebar, double de, const double* m, double* w,
+                         double* v, hipStream_t s);
+
+// Single-workgroup bisection/evaluation over the weights.  With max_iter = 0
+// evaluates at mu_in.  out[0] = mu, out[1] = Tr[PS], out[2] = Tr[PF] (no spin),
+// out[3] = converged (1/0), out[4] = iterations.
+hipError_t mu_bisect(int M, double ebar, double de, double beta, double target, double tol,
+                     double lo, double hi, double mu_in, int max_iter, const double* w,
+                     const double* v, double* out, hipStream_t s);
+
+// ----------------------------------------------------------------- setup
+hipError_t fill_f64(double* x, double v, long long n, hipStream_t s);
+hipError_t fill_i32(int* x, int v, long long n, hipStream_t s);
+// D (Kp x Kp col-major, zero on entry) gets the CSR matrix; padded diagonal
+// entries (i >= K) get pad_diag.
+hipError_t csr_to_dense(int K, int Kp, const long long* rowptr, const int* col, const double* val,
+                        double pad_diag, double* D, hipStream_t s);
+// Factor the nb x nb diagonal block at A (ld) as U^T U in place (upper), write
+// V = U^-1 (nb x nb col-major).  info[0] = first failing global index + 1.
+hipError_t potrf_diag(double* A, long ld, double* V, int* info, int kglobal, hipStream_t s);
+// dst[r + c*ldd] = src[c + r*lds]^T for an nb x nb block (transpose copy).
+hipError_t copy_transpose_block(const double* src, long lds, double* dst, long ldd, hipStream_t s);
+// HN (row-major = HT column-major) = (HT - ebar I) / de on the K x K part,
+// zero elsewhere; output FP64 or FP32.
+hipError_t normalize_operator(int K, int Kp, const double* HT, double ebar, double de,
+                              int precision, void* HN, hipStream_t s);
+// ----------------------------------------------------------------- Lanczos
+hipError_t random_vector(int K, unsigned long long seed, double* v, hipStream_t s);
+hipError_t csr_spmv(int K, const long long* rowptr, const int* col, const double* val,
+                    const double* x, double* y, hipStream_t s);
+// y[m] = sum_k A[m*lda + k] x[k]  (rows of a row-major matrix), m < K
+hipError_t gemv_rows(int K, const double* A, long lda, const double* x, double* y, hipStream_t s);
+// out[i] = sum_k X[k + i*ldx] y[k] for i < n  (n dot products against columns)
+hipError_t dots_cols(int K, int n, const double* X, long ldx, const double* y, double* out,
+                     hipStream_t s);
+// Lanczos bookkeeping kernels, scalars live in device memory.
+hipError_t lanczos_normalize_start(int K, double* v, double* q, const double* vSv, hipStream_t s);
+hipError_t lanczos_three_term(int K, double* w, const double* vj, const double* vjm1,
+                              const double* alpha_j, const double* beta_jm1, hipStream_t s);
+hipError_t lanczos_reorth(int K, int n, double* w, const double* V, long ldv, const double* c,
+                          hipStream_t s);
+hipError_t lanczos_next(int K, const double* w, const double* sw, const double* wSw,
+                        double* beta_out, double* vnext, double* qnext, hipStream_t s);
+
+}  // namespace dm

@@ -1,0 +1,261 @@
+// MFMA matrix kernels for gfx950: the Chebyshev recursion step (the hot
+// loop of the supplement's eq. ChebychevExpansion) and the FP64 products of
+// the operator setup.
+//
+// Both compute C[m, n] = sum_k A[m*lda + k] * B[n*ldb + k]: each operand has
+// its reduction index contiguous, so one lane reads four consecutive k with a
+// single vector load.  MFMA 16x16x4 takes A[i][k] from lane i + 16k and
+// B[k][j] from lane j + 16k; here lane (i, q = lane/16) holds k = 4q .. 4q+3
+// and the s-th MFMA of a 16-wide k slab uses k = 4q + s, which visits every k
+// exactly once (the products are summed in a different order, nothing else).
+// With the row order of Mfma<T>::a_row, result row i of a tile sits in lane
+// j + 16 * (i / 4), element i % 4, so each lane owns four consecutive rows of
+// one column: the epilogue reads and writes 4-element vectors of column-major
+// blocks.
+#include "dm_common.hpp"
+
+namespace dm {
+namespace {
+
+template <typename T>
+struct Mfma;
+
+// a_row(i): which row of the 16-row A slab lane i feeds.  The f32 result
+// puts row 4g + r of the tile in lane j + 16g, element r; the f64 result puts
+// row g + 4r there instead.  Feeding slot i from row 4(i % 4) + i / 4 turns
+// the f64 layout into the f32 one, so both epilogues see four consecutive
+// rows per lane.
+template <>
+struct Mfma<double> {
+    typedef double4_t acc_t;
+    typedef double4_t vec_t;
+    __device__ static inline acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int a_row(int i) { return 4 * (i & 3) + (i >> 2); }
+};
+
+template <>
+struct Mfma<float> {
+    typedef float4_t acc_t;
+    typedef float4_t vec_t;
+    __device__ static inline acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int a_row(int i) { return i; }
+};
+
+// Tile placement.  Workgroups are dispatched round-robin over the 8 XCDs
+// (workgroup b lands on XCD b % 8); remapping b so that each XCD gets a
+// contiguous range of logical tiles, and ordering logical tiles in groups of
+// GM tile-rows, keeps the operator rows and column blocks that concurrently
+// running workgroups share inside one XCD's L2.
+struct TilePos {
+    int tile_m, tile_n, logical;
+};
+
+template <int GM>
+__device__ inline TilePos tile_position(int ntm, int ntn) {
+    const int nwg = gridDim.x;
+    const int bid = blockIdx.x;
+    int logical = bid;
+    if ((nwg & 7) == 0) logical = (bid & 7) * (nwg >> 3) + (bid >> 3);
+    const int group_size = GM * ntn;
+    const int group = logical / group_size;
+    const int first_m = group * GM;
+    const int gm = min(ntm - first_m, GM);
+    const int in_group = logical - group * group_size;
+    TilePos p;
+    p.tile_m = first_m + in_group % gm;
+    p.tile_n = in_group / gm;
+    p.logical = logical;
+    return p;
+}
+
+// The main loop: acc[tm][tn] += A-rows x B-columns over the whole reduction.
+// Two register buffers: the loads for the next 16-wide slab are in flight
+// while the MFMAs of the current slab run.
+template <typename T, int TM, int TN>
+__device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda,
+                                     const T* __restrict__ B, long ldb, int row0, int col0,
+                                     typename Mfma<T>::acc_t (&acc)[TM][TN]) {
+    typedef typename Mfma<T>::vec_t vec_t;
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    const T* pa[TM];
+    const T* pb[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) pa[i] = A + (long)(row0 + 16 * i + Mfma<T>::a_row(li)) * lda + 4 * lq;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) pb[j] = B + (long)(col0 + 16 * j + li) * ldb + 4 * lq;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+
+    vec_t a0[TM], b0[TN], a1[TM], b1[TN];
+    auto load = [&](vec_t(&a)[TM], vec_t(&b)[TN], int k) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const vec_t*>(pa[i] + k);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = *reinterpret_cast<const vec_t*>(pb[j] + k);
+    };
+    auto compute = [&](const vec_t(&a)[TM], const vec_t(&b)[TN]) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i][s], b[j][s], acc[i][j]);
+    };
+    load(a0, b0, 0);
+    for (int k = 0; k < Kred; k += 32) {
+        const bool has1 = k + 16 < Kred;
+        if (has1) load(a1, b1, k + 16);
+        compute(a0, b0);
+        if (k + 32 < Kred) load(a0, b0, k + 32);
+        if (has1) compute(a1, b1);
+    }
+}
+
+// ------------------------------------------------------------ plain product
+template <int TM, int TN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_tn_store_kernel(int M, int N, int Kred, double alpha, const double* __restrict__ A, long lda,
+                     const double* __restrict__ B, long ldb, double beta, double* __restrict__ C,
+                     long ldc, int upper_only) {
+    constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    const TilePos tp = tile_position<8>(M / BM, N / BN);
+    if (upper_only && tp.tile_m * BM >= (tp.tile_n + 1) * BN) return;
+    const int wave = threadIdx.x >> 6;
+    const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
+    const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
+    double4_t acc[TM][TN];
+    gemm_mainloop<double, TM, TN>(Kred, A, lda, B, ldb, row0, col0, acc);
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const long idx = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * ldc;
+            double4_t* c = reinterpret_cast<double4_t*>(C + idx);
+            double4_t r = alpha * acc[i][j];
+            if (beta != 0.0) r += beta * (*c);
+            *c = r;
+        }
+}
+
+// ------------------------------------------------------------ recursion step
+template <typename T, int TM, int TN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+cheb_step_kernel(ChebStepArgs a) {
+    typedef typename Mfma<T>::vec_t vec_t;
+    constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    const int ntm = a.Kp / BM, ntn = a.Bp / BN;
+    const TilePos tp = tile_position<8>(ntm, ntn);
+    const int wave = threadIdx.x >> 6;
+    const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
+    const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
+    typename Mfma<T>::acc_t acc[TM][TN];
+    gemm_mainloop<T, TM, TN>(a.Kp, static_cast<const T*>(a.HN), a.Kp, static_cast<const T*>(a.Ucur),
+                             a.Kp, row0, col0, acc);
+
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    const T alpha = static_cast<T>(a.alpha);
+    const double c = a.coef[a.l];
+    const T* Uprev = static_cast<const T*>(a.Uprev);
+    T* Unext = static_cast<T*>(a.Unext);
+    double msum = 0.0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const long idx = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * a.Kp;
+            vec_t out = alpha * acc[i][j];
+            if (a.has_prev) out -= *reinterpret_cast<const vec_t*>(Uprev + idx);
+            *reinterpret_cast<vec_t*>(Unext + idx) = out;
+            const double4_t z = *reinterpret_cast<const double4_t*>(a.Z + idx);
+            double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
+            msum += z[0] * od[0] + z[1] * od[1] + z[2] * od[2] + z[3] * od[3];
+            if (c != 0.0) {
+                double4_t* p = reinterpret_cast<double4_t*>(a.P + idx);
+                *p = *p + c * od;
+            }
+        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) msum += __shfl_xor(msum, off, 64);
+    __shared__ double red[WM * WN];
+    if (lane == 0) red[wave] = msum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < WM * WN; ++w) s += red[w];
+        a.partial[(long)a.l * (ntm * ntn) + tp.logical] = s;
+    }
+}
+
+struct CfgShape {
+    int tm, tn, wm, wn;
+};
+// Tile shapes of the recursion step, widest first.
+constexpr CfgShape kChebCfgs[] = {
+    {4, 4, 2, 2},  // 128 x 128
+    {4, 2, 2, 2},  // 128 x 64
+    {2, 2, 4, 1},  // 128 x 32
+    {2, 2, 2, 2},  // 64 x 64
+};
+
+template <typename T>
+hipError_t launch_cheb(const ChebStepArgs& a, int cfg, hipStream_t s) {
+    const CfgShape c = kChebCfgs[cfg];
+    const int BM = 16 * c.tm * c.wm, BN = 16 * c.tn * c.wn;
+    if (a.Kp % BM || a.Bp % BN) return hipErrorInvalidValue;
+    const dim3 grid((a.Kp / BM) * (a.Bp / BN));
+    const dim3 block(64 * c.wm * c.wn);
+    switch (cfg) {
+        case 0: hipLaunchKernelGGL((cheb_step_kernel<T, 4, 4, 2, 2>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((cheb_step_kernel<T, 4, 2, 2, 2>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((cheb_step_kernel<T, 2, 2, 4, 1>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((cheb_step_kernel<T, 2, 2, 2, 2>), grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int cheb_num_tile_configs() { return (int)(sizeof(kChebCfgs) / sizeof(kChebCfgs[0])); }
+int cheb_tile_rows(int cfg) { return 16 * kChebCfgs[cfg].tm * kChebCfgs[cfg].wm; }
+int cheb_tile_cols(int cfg) { return 16 * kChebCfgs[cfg].tn * kChebCfgs[cfg].wn; }
+int cheb_num_tiles(int Kp, int Bp, int cfg) {
+    return (Kp / cheb_tile_rows(cfg)) * (Bp / cheb_tile_cols(cfg));
+}
+
+hipError_t cheb_step_f64(const ChebStepArgs& a, int cfg, hipStream_t s) {
+    return launch_cheb<double>(a, cfg, s);
+}
+hipError_t cheb_step_f32(const ChebStepArgs& a, int cfg, hipStream_t s) {
+    return launch_cheb<float>(a, cfg, s);
+}
+
+hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, long lda,
+                       const double* B, long ldb, double beta, double* C, long ldc,
+                       bool upper_only, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (M % 64 || N % 64 || Kred % 16 || Kred <= 0) return hipErrorInvalidValue;
+    if (M % 128 == 0 && N % 128 == 0) {
+        const dim3 grid((M / 128) * (N / 128));
+        hipLaunchKernelGGL((gemm_tn_store_kernel<4, 4, 2, 2>), grid, dim3(256), 0, s, M, N, Kred,
+                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only);
+    } else {
+        const dim3 grid((M / 64) * (N / 64));
+        hipLaunchKernelGGL((gemm_tn_store_kernel<2, 2, 2, 2>), grid, dim3(256), 0, s, M, N, Kred,
+                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dm
