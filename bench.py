@@ -31,6 +31,20 @@ WORKLOAD = "K4096_sphere1024_fp64"
 METRIC = "density-matrix columns/sec and SpMM GB/s (% HBM roofline) at max|dP|<=1e-6"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE averages per recursion launch of this
+# workload (KiB), and the scale factors from a plain 1 GiB copy (FETCH_SIZE
+# counts half of the bytes a copy reads on this part, WRITE_SIZE all of them).
+# Valid only for the kernel source they were taken with.
+COUNTERS = {"kernel_source_sha256_16": "43a68252a6b01cab", "fetch_kib": 992796.1,
+            "write_kib": 262021.7, "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+def kernel_source_hash():
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2108_13478_amd", "csrc", "gemm.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def cpu_baseline(cluster, order, beta, n_e, budget_s=30.0):
@@ -64,10 +78,25 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1, "
+                                   "the multi-GPU column sharding is not part of this build"}))
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+
+        n = 1 << 27  # 2^27 doubles = 1 GiB read + 1 GiB written per copy
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 8 * n, "copy_calibration_bytes_written": 8 * n,
+                          "copies": 3}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -122,6 +151,13 @@ def main():
     launch_ms = float(np.mean(rec_ms)) / order
     flops = 2.0 * K * K * K
     achieved = flops / (launch_ms * 1e-3) / 1e12
+    traffic = None
+    if kernel_source_hash() == COUNTERS["kernel_source_sha256_16"]:
+        traffic = 1024.0 * (COUNTERS["fetch_kib"] * COUNTERS["fetch_scale"]
+                            + COUNTERS["write_kib"] * COUNTERS["write_scale"])
+    # algorithmic bytes per launch: operator K^2, reads of U_l, U_{l-1}, Z, P and
+    # writes of U_{l+1}, P (K x columns each), FP64
+    alg_bytes = 8.0 * (K * K + 6.0 * K * K)
     out = {
         "metric": METRIC,
         "value": K * args.steps / el,
@@ -139,8 +175,12 @@ def main():
                    "columns_per_step": K, "column_block": 64, "precision": "fp64",
                    "nnz_per_row_F_S": [round(x, 1) for x in c.nnz_per_row]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "cheb_step_kernel<double,4,4,2,2>", "launch_ms": launch_ms},
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "cheb_step_kernel<double,4,4,2,2>", "launch_ms": launch_ms,
+                     "algorithmic_bytes": alg_bytes,
+                     "algorithmic_GBps": alg_bytes / (launch_ms * 1e-3) / 1e9,
+                     "counter_GBps": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
+                     "hbm_peak_GBps": PEAK_HBM_GBS},
         "electron_count_error": state["tr_err"],
         "mu": state["mu"],
         "band_energy": state["eband"],
