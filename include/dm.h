@@ -149,6 +149,19 @@ dm_status dm_solve_mu(dm_ctx* ctx, double n_e, double beta, double tol, double* 
 dm_status dm_moments(dm_ctx* ctx, double* m, int n, long long* ncols_done);
 dm_status dm_reset_moments(dm_ctx* ctx);
 
+/* Pick the pass width and tile shape of the recursion for this operator and
+ * precision by timing `steps` recursion steps of every candidate (widths 32,
+ * 64, 128, 256 columns, capped at max(ncols, 32); every tile shape whose
+ * column tile divides the width).  The fastest in columns x steps per
+ * second is kept in the context and used by dm_chebyshev_block while the
+ * block_width option is 0.  table (host, may be NULL) receives up to
+ * *ntable rows of (width, tile config, tile rows, tile cols, ms per step,
+ * column-steps per second); *ntable returns the number of candidates.
+ * Chooses nothing across Fock matrices: dm_set_fock forgets the choice.
+ * Errors: DM_E_STATE (no Fock matrix), DM_E_ARG (ncols < 1, steps < 1). */
+dm_status dm_autotune(dm_ctx* ctx, long long ncols, int steps, double* table, int* ntable,
+                      int* best_width, int* best_cfg);
+
 /* Stochastic moments (1/n_vec) sum_s xi_s^T T_l(H_N) xi_s, l < n_mom, with
  * caller-supplied probe vectors xi (host or device, K x n_vec column-major
  * FP64, e.g. independent +-1 entries).  m_out: host, n_mom FP64.

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "DM_OK", -1: "DM_E_ARG", -2: "DM_E_STATE", -3: "DM_E_HIP", -4
 
 EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_set_fock",
             "dm_get_bounds", "dm_set_bounds", "dm_get_operator", "dm_set_precision", "dm_chebyshev_block",
-            "dm_trace", "dm_solve_mu", "dm_moments", "dm_reset_moments", "dm_stoch_moments"]
+            "dm_trace", "dm_solve_mu", "dm_moments", "dm_reset_moments", "dm_stoch_moments",
+            "dm_autotune"]
 
 
 class DMError(RuntimeError):
@@ -79,6 +80,7 @@ def load(path: str = LIB_PATH):
         "dm_moments": (_I, [_P, _P, _I, _P]),
         "dm_reset_moments": (_I, [_P]),
         "dm_stoch_moments": (_I, [_P, _I, _I, _P, _P]),
+        "dm_autotune": (_I, [_P, _LL, _I, _P, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -217,3 +219,14 @@ class Context:
         m = np.zeros(n_mom, dtype=np.float64)
         self._check(self._lib.dm_stoch_moments(self.h, int(n_mom), n_vec, xp, ctypes.c_void_p(m.ctypes.data)))
         return m
+
+    def dm_autotune(self, ncols, steps=5):
+        """Returns (best_width, best_cfg, table) with table rows (width, cfg,
+        tile_rows, tile_cols, ms_per_step, column_steps_per_s)."""
+        cap = 64
+        table = np.zeros((cap, 6), dtype=np.float64)
+        n = ctypes.c_int(cap)
+        bw, bc = ctypes.c_int(), ctypes.c_int()
+        self._check(self._lib.dm_autotune(self.h, int(ncols), int(steps), ctypes.c_void_p(table.ctypes.data),
+                                          ctypes.byref(n), ctypes.byref(bw), ctypes.byref(bc)))
+        return bw.value, bc.value, table[:min(n.value, cap)].copy()

@@ -61,6 +61,10 @@ struct dm_ctx {
     int mom_order = -1;
     long long ncols_done = 0;
 
+    // pass width and tile shape chosen by dm_autotune (0 / -1: none)
+    int tuned_width = 0;
+    int tuned_cfg = -1;
+
     // workspace
     DevBuf<double> Ua, Ub, Z, P;  // sized in bytes via double slots
     DevBuf<double> part_start, part_steps;
@@ -318,14 +322,15 @@ dm_status reset_moments(dm_ctx* c) {
     return DM_OK;
 }
 
-// Tile shape for a pass: the widest tile whose grid still gives every CU two
-// workgroups, else the one with the most workgroups.
+// Tile shape for a pass when nothing was tuned: among the four standard
+// shapes, the widest tile whose grid still gives every CU two workgroups,
+// else the one with the most workgroups.
 int pick_cfg(int Kp, int ncols) {
     int best = -1, best_tiles = -1;
-    for (int cfg = 0; cfg < cheb_num_tile_configs(); ++cfg) {
+    for (int cfg = 0; cfg < 4; ++cfg) {
         const int BN = cheb_tile_cols(cfg);
         const int Bp = (int)round_up(std::max(ncols, 1), BN);
-        if (Bp > round_up(std::max(ncols, 1), 32) * 2 && BN > 32) continue;  // too much padding
+        if (Bp > round_up(std::max(ncols, 1), 32) && BN > 32) continue;  // padding beyond 32
         const int tiles = cheb_num_tiles(Kp, Bp, cfg);
         if (tiles >= 512) return cfg;
         if (tiles > best_tiles) {
@@ -441,6 +446,8 @@ dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const i
         return set_err(c, DM_E_ARG, "null CSR array");
     if (atom_block < 1 || K % atom_block) return set_err(c, DM_E_ARG, "K not a multiple of atom_block");
     c->have_fock = false;
+    c->tuned_width = 0;
+    c->tuned_cfg = -1;
     reset_moments(c);
     // ---- copy to host and validate
     std::vector<long long> frp, srp;
@@ -657,12 +664,14 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
 
     // pass width
     const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
-    long long bw = c->opt.block_width > 0 ? c->opt.block_width : ncols;
+    const bool tuned = c->opt.block_width == 0 && c->tuned_width > 0;
+    long long bw = c->opt.block_width > 0 ? c->opt.block_width : (tuned ? c->tuned_width : ncols);
     const size_t budget = (size_t)16 << 30;
     const size_t per_col = (size_t)Kp * (2 * tsz + 16);
     bw = std::min<long long>(bw, std::max<long long>(128, (long long)(budget / per_col) / 128 * 128));
     bw = std::min(bw, ncols);
-    const int cfg = pick_cfg(Kp, (int)bw);
+    int cfg = pick_cfg(Kp, (int)bw);
+    if (tuned && bw % cheb_tile_cols(c->tuned_cfg) == 0) cfg = c->tuned_cfg;
     const int BN = cheb_tile_cols(cfg);
     const int Bp_max = (int)round_up(bw, std::max(BN, 16));
     HIPTRY(c, ensure(c->Ua, (size_t)Kp * Bp_max * tsz / 8));
@@ -794,6 +803,119 @@ dm_status dm_reset_moments(dm_ctx* c) {
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     return reset_moments(c);
+}
+
+dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int* ntable,
+                      int* best_width, int* best_cfg) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (ncols < 1 || steps < 1) return set_err(c, DM_E_ARG, "need ncols >= 1 and steps >= 1");
+    hipStream_t s = c->stream;
+    const int K = (int)c->K, Kp = c->Kp;
+    const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
+    const int wmax = (int)std::max<long long>(32, std::min<long long>(ncols, 256));
+    struct Cand { int w, cfg; double ms; };
+    std::vector<Cand> cands;
+    for (int w : {32, 64, 128, 256}) {
+        if (w > wmax) continue;
+        for (int cfg = 0; cfg < cheb_num_tile_configs(); ++cfg)
+            if (w % cheb_tile_cols(cfg) == 0 && cheb_cfg_supports(cfg, c->precision))
+                cands.push_back({w, cfg, 0.0});
+    }
+    const int W = 256;
+    DevBuf<double> U0, U1, Zb, Pb, part, pst, coef;
+    DevBuf<long long> colsd;
+    auto rel = [&]() { U0.release(); U1.release(); Zb.release(); Pb.release(); part.release(); pst.release(); coef.release(); colsd.release(); };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+#define AT(expr)                                         \
+    do {                                                 \
+        if ((e = (expr)) != hipSuccess) {                \
+            rel();                                       \
+            if (e0) (void)hipEventDestroy(e0);           \
+            if (e1) (void)hipEventDestroy(e1);           \
+            return fail_hip(c, e, #expr);                \
+        }                                                \
+    } while (0)
+    AT(hipEventCreate(&e0));
+    AT(hipEventCreate(&e1));
+    AT(ensure(U0, (size_t)Kp * W * tsz / 8));
+    AT(ensure(U1, (size_t)Kp * W * tsz / 8));
+    AT(ensure(Zb, (size_t)Kp * W));
+    AT(ensure(Pb, (size_t)Kp * W));
+    AT(ensure(pst, (size_t)(Kp / 64) * (W / 16)));
+    AT(ensure(coef, (size_t)steps + 4));
+    int max_tiles = 0;
+    for (const Cand& cd : cands) max_tiles = std::max(max_tiles, cheb_num_tiles(Kp, cd.w, cd.cfg));
+    AT(ensure(part, (size_t)(steps + 4) * max_tiles));
+    std::vector<long long> hc(W);
+    for (int j = 0; j < W; ++j) hc[j] = j % K;
+    AT(ensure(colsd, (size_t)W));
+    AT(hipMemcpyAsync(colsd.p, hc.data(), W * 8, hipMemcpyHostToDevice, s));
+    AT(fill_f64(coef.p, 0.0, steps + 4, s));  // coefficient 0: the timing leaves P untouched
+    for (Cand& cd : cands) {
+        const int nc = std::min(cd.w, K);
+        AT(fill_f64(Zb.p, 0.0, (long long)Kp * cd.w, s));
+        int nts = 0;
+        AT(cheb_start(K, Kp, cd.w, nc, colsd.p, c->Sinv.p, c->S_rowptr.p, c->S_col.p, c->S_val.p,
+                      c->precision, U0.p, Zb.p, Pb.p, coef.p, pst.p, &nts, s));
+        ChebStepArgs a{};
+        a.Kp = Kp;
+        a.Bp = cd.w;
+        a.HN = c->HNbuf.p;
+        a.coef = coef.p;
+        a.P = Pb.p;
+        a.Z = Zb.p;
+        a.partial = part.p;
+        void* ucur = U0.p;
+        void* uoth = U1.p;
+        for (int l = 1; l <= steps + 2; ++l) {
+            if (l == 3) AT(hipEventRecord(e0, s));
+            a.Ucur = ucur;
+            a.Uprev = (l == 1) ? nullptr : uoth;
+            a.Unext = uoth;
+            a.alpha = (l == 1) ? 1.0 : 2.0;
+            a.has_prev = l > 1;
+            a.l = l;
+            AT(c->precision == DM_FP64 ? cheb_step_f64(a, cd.cfg, s) : cheb_step_f32(a, cd.cfg, s));
+            std::swap(ucur, uoth);
+        }
+        AT(hipEventRecord(e1, s));
+        AT(hipEventSynchronize(e1));
+        float ms = 0;
+        AT(hipEventElapsedTime(&ms, e0, e1));
+        cd.ms = ms / steps;
+    }
+    rel();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+#undef AT
+    int best = 0;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        const double r = cands[i].w / cands[i].ms, rb = cands[best].w / cands[best].ms;
+        if (r > rb) best = (int)i;
+    }
+    c->tuned_width = cands[best].w;
+    c->tuned_cfg = cands[best].cfg;
+    if (best_width) *best_width = c->tuned_width;
+    if (best_cfg) *best_cfg = c->tuned_cfg;
+    if (ntable) {
+        const int cap = *ntable;
+        if (table)
+            for (int i = 0; i < (int)cands.size() && i < cap; ++i) {
+                double* row = table + 6 * i;
+                row[0] = cands[i].w;
+                row[1] = cands[i].cfg;
+                row[2] = cheb_tile_rows(cands[i].cfg);
+                row[3] = cheb_tile_cols(cands[i].cfg);
+                row[4] = cands[i].ms;
+                row[5] = cands[i].w / (cands[i].ms * 1e-3);
+            }
+        *ntable = (int)cands.size();
+    }
+    return DM_OK;
 }
 
 dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, double* m_out) {

@@ -22,7 +22,7 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // All launch wrappers return the hipError_t of the launch.
 
 // C[m + n*ldc] = alpha * sum_k A[m*lda + k] * B[n*ldb + k] + beta * C[...]
-// M, N multiples of 64, Kred multiple of 16, operands FP64.  With
+// M, N multiples of 64, Kred multiple of 32, operands FP64.  With
 // upper_only, output tiles entirely below the diagonal (m0 >= n0 + tile) are
 // skipped (used where only the upper triangle of a symmetric result is read).
 hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, long lda,
@@ -51,6 +51,7 @@ struct ChebStepArgs {
     double* partial;
 };
 int cheb_num_tile_configs();
+bool cheb_cfg_supports(int cfg, int precision);
 int cheb_tile_cols(int cfg);
 int cheb_tile_rows(int cfg);
 hipError_t cheb_step_f64(const ChebStepArgs& a, int cfg, hipStream_t s);

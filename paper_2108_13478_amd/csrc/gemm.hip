@@ -73,21 +73,33 @@ __device__ inline TilePos tile_position(int ntm, int ntn) {
 }
 
 // The main loop: acc[tm][tn] += A-rows x B-columns over the whole reduction.
-// Two register buffers: the loads for the next 16-wide slab are in flight
-// while the MFMAs of the current slab run.
-template <typename T, int TM, int TN>
+// Each lane loads KV consecutive k per operand row/column and slab (one
+// vector load of KV elements); a slab is 4 KV wide and takes KV MFMA k-steps.
+// Two register buffers keep the next slab's loads in flight while the MFMAs
+// of the current slab run; a larger KV puts more bytes in flight per wave,
+// which is what the memory-bound narrow-block shapes need.
+template <typename T, int KV>
+struct VecOf;
+template <> struct VecOf<double, 4> { typedef double4_t type; };
+template <> struct VecOf<float, 4> { typedef float4_t type; };
+template <> struct VecOf<double, 8> { typedef double type __attribute__((ext_vector_type(8))); };
+template <> struct VecOf<float, 8> { typedef float type __attribute__((ext_vector_type(8))); };
+template <> struct VecOf<float, 16> { typedef float type __attribute__((ext_vector_type(16))); };
+
+template <typename T, int TM, int TN, int KV>
 __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda,
                                      const T* __restrict__ B, long ldb, int row0, int col0,
                                      typename Mfma<T>::acc_t (&acc)[TM][TN]) {
-    typedef typename Mfma<T>::vec_t vec_t;
+    typedef typename VecOf<T, KV>::type vec_t;
+    constexpr int SLAB = 4 * KV;
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
     const T* pa[TM];
     const T* pb[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) pa[i] = A + (long)(row0 + 16 * i + Mfma<T>::a_row(li)) * lda + 4 * lq;
+    for (int i = 0; i < TM; ++i) pa[i] = A + (long)(row0 + 16 * i + Mfma<T>::a_row(li)) * lda + KV * lq;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) pb[j] = B + (long)(col0 + 16 * j + li) * ldb + 4 * lq;
+    for (int j = 0; j < TN; ++j) pb[j] = B + (long)(col0 + 16 * j + li) * ldb + KV * lq;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -102,20 +114,27 @@ __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda
     };
     auto compute = [&](const vec_t(&a)[TM], const vec_t(&b)[TN]) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < KV; ++s)
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i][s], b[j][s], acc[i][j]);
     };
+    // Kred is a multiple of 2 SLAB (checked by the launchers).  The steady
+    // state has no branch between a load and the MFMAs that follow it, so the
+    // compiler can wait for exactly the older buffer's loads instead of for
+    // every load in flight.
     load(a0, b0, 0);
-    for (int k = 0; k < Kred; k += 32) {
-        const bool has1 = k + 16 < Kred;
-        if (has1) load(a1, b1, k + 16);
+    int k = 0;
+    for (; k < Kred - 2 * SLAB; k += 2 * SLAB) {
+        load(a1, b1, k + SLAB);
         compute(a0, b0);
-        if (k + 32 < Kred) load(a0, b0, k + 32);
-        if (has1) compute(a1, b1);
+        load(a0, b0, k + 2 * SLAB);
+        compute(a1, b1);
     }
+    load(a1, b1, k + SLAB);
+    compute(a0, b0);
+    compute(a1, b1);
 }
 
 // ------------------------------------------------------------ plain product
@@ -131,7 +150,7 @@ gemm_tn_store_kernel(int M, int N, int Kred, double alpha, const double* __restr
     const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
     const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
     double4_t acc[TM][TN];
-    gemm_mainloop<double, TM, TN>(Kred, A, lda, B, ldb, row0, col0, acc);
+    gemm_mainloop<double, TM, TN, 4>(Kred, A, lda, B, ldb, row0, col0, acc);
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
@@ -147,7 +166,7 @@ gemm_tn_store_kernel(int M, int N, int Kred, double alpha, const double* __restr
 }
 
 // ------------------------------------------------------------ recursion step
-template <typename T, int TM, int TN, int WM, int WN>
+template <typename T, int TM, int TN, int WM, int WN, int KV>
 __global__ void __launch_bounds__(64 * WM * WN)
 cheb_step_kernel(ChebStepArgs a) {
     typedef typename Mfma<T>::vec_t vec_t;
@@ -158,7 +177,7 @@ cheb_step_kernel(ChebStepArgs a) {
     const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
     const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
     typename Mfma<T>::acc_t acc[TM][TN];
-    gemm_mainloop<T, TM, TN>(a.Kp, static_cast<const T*>(a.HN), a.Kp, static_cast<const T*>(a.Ucur),
+    gemm_mainloop<T, TM, TN, KV>(a.Kp, static_cast<const T*>(a.HN), a.Kp, static_cast<const T*>(a.Ucur),
                              a.Kp, row0, col0, acc);
 
     const int lane = threadIdx.x & 63;
@@ -198,36 +217,51 @@ cheb_step_kernel(ChebStepArgs a) {
 }
 
 struct CfgShape {
-    int tm, tn, wm, wn;
+    int tm, tn, wm, wn, kv;
 };
-// Tile shapes of the recursion step, widest first.
+// Tile shapes of the recursion step (rows x columns per workgroup, k per
+// lane and slab).  The first four suit the compute-bound wide blocks; the
+// last three keep more operator bytes in flight for narrow, memory-bound
+// blocks.  KV = 16 is FP32 only.
 constexpr CfgShape kChebCfgs[] = {
-    {4, 4, 2, 2},  // 128 x 128
-    {4, 2, 2, 2},  // 128 x 64
-    {2, 2, 4, 1},  // 128 x 32
-    {2, 2, 2, 2},  // 64 x 64
+    {4, 4, 2, 2, 4},  // 128 x 128
+    {4, 2, 2, 2, 4},  // 128 x 64
+    {2, 2, 4, 1, 4},  // 128 x 32
+    {2, 2, 2, 2, 4},  // 64 x 64
+    {1, 2, 4, 1, 8},  // 64 x 32, deep
+    {1, 4, 4, 1, 8},  // 64 x 64, deep
+    {1, 2, 4, 1, 16}, // 64 x 32, deeper (FP32)
 };
+
+template <typename T, int TM, int TN, int WM, int WN, int KV>
+hipError_t launch_one(const ChebStepArgs& a, hipStream_t s) {
+    constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    if (a.Kp % BM || a.Bp % BN || a.Kp % (8 * KV)) return hipErrorInvalidValue;
+    const dim3 grid((a.Kp / BM) * (a.Bp / BN));
+    hipLaunchKernelGGL((cheb_step_kernel<T, TM, TN, WM, WN, KV>), grid, dim3(64 * WM * WN), 0, s, a);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_cheb(const ChebStepArgs& a, int cfg, hipStream_t s) {
-    const CfgShape c = kChebCfgs[cfg];
-    const int BM = 16 * c.tm * c.wm, BN = 16 * c.tn * c.wn;
-    if (a.Kp % BM || a.Bp % BN) return hipErrorInvalidValue;
-    const dim3 grid((a.Kp / BM) * (a.Bp / BN));
-    const dim3 block(64 * c.wm * c.wn);
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((cheb_step_kernel<T, 4, 4, 2, 2>), grid, block, 0, s, a); break;
-        case 1: hipLaunchKernelGGL((cheb_step_kernel<T, 4, 2, 2, 2>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((cheb_step_kernel<T, 2, 2, 4, 1>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((cheb_step_kernel<T, 2, 2, 2, 2>), grid, block, 0, s, a); break;
+        case 0: return launch_one<T, 4, 4, 2, 2, 4>(a, s);
+        case 1: return launch_one<T, 4, 2, 2, 2, 4>(a, s);
+        case 2: return launch_one<T, 2, 2, 4, 1, 4>(a, s);
+        case 3: return launch_one<T, 2, 2, 2, 2, 4>(a, s);
+        case 4: return launch_one<T, 1, 2, 4, 1, 8>(a, s);
+        case 5: return launch_one<T, 1, 4, 4, 1, 8>(a, s);
+        case 6:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 1, 2, 4, 1, 16>(a, s);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace
 
 int cheb_num_tile_configs() { return (int)(sizeof(kChebCfgs) / sizeof(kChebCfgs[0])); }
+bool cheb_cfg_supports(int cfg, int precision) { return !(kChebCfgs[cfg].kv == 16 && precision == 0); }
 int cheb_tile_rows(int cfg) { return 16 * kChebCfgs[cfg].tm * kChebCfgs[cfg].wm; }
 int cheb_tile_cols(int cfg) { return 16 * kChebCfgs[cfg].tn * kChebCfgs[cfg].wn; }
 int cheb_num_tiles(int Kp, int Bp, int cfg) {
@@ -245,7 +279,7 @@ hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, lo
                        const double* B, long ldb, double beta, double* C, long ldc,
                        bool upper_only, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    if (M % 64 || N % 64 || Kred % 16 || Kred <= 0) return hipErrorInvalidValue;
+    if (M % 64 || N % 64 || Kred % 32 || Kred <= 0) return hipErrorInvalidValue;
     if (M % 128 == 0 && N % 128 == 0) {
         const dim3 grid((M / 128) * (N / 128));
         hipLaunchKernelGGL((gemm_tn_store_kernel<4, 4, 2, 2>), grid, dim3(256), 0, s, M, N, Kred,

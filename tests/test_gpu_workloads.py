@@ -57,3 +57,66 @@ def test_k4096_fp64_all_columns(k4096):
     assert abs(tr - tr_ref) < 1e-7 and abs(eb - eb_ref) < 1e-5 * max(1.0, abs(eb_ref))
     mu_g = ctx.dm_solve_mu(w["n_electrons"], beta, tol=1e-8)
     assert abs(2.0 * O.trace_poly(sp, N, mu_g, beta, emin, emax)[0] - w["n_electrons"]) < 1e-6
+
+
+def test_k4096_fp32_recursion_error(k4096):
+    """FP32 storage and accumulation of the recursion, FP64 P and moments:
+    error against the FP64 oracle over all 4096 columns (reported)."""
+    c, sp = k4096
+    w = WORKLOADS["K4096_sphere1024_fp64"]
+    N, beta = w["order"], w["beta"]
+    ww = sp.e[-1] - sp.e[0]
+    emin, emax = sp.e[0] - 0.01 * ww, sp.e[-1] + 0.01 * ww
+    mu = O.solve_mu_poly(sp, w["n_electrons"], N, beta, emin, emax, tol=1e-9)
+    say(f"case: K={c.K} FP32 recursion N={N} all columns")
+    ctx = dmlib.Context(precision=dmlib.DM_FP32)
+    ctx.set_cluster(c)
+    ctx.dm_set_bounds(emin, emax)
+    P = np.zeros((c.K, c.K))
+    ctx.dm_chebyshev_block(np.arange(c.K, dtype=np.int64), N, mu, beta, P)
+    ref = O.density_matrix_poly(sp, np.arange(c.K), N, mu, beta, emin, emax)
+    err = np.abs(P.T - ref).max()
+    tr, _ = ctx.dm_trace(mu, beta)
+    tr_ref, _ = O.trace_poly(sp, N, mu, beta, emin, emax)
+    say(f"  FP32 max|dP| = {err:.3e} (max|P| {np.abs(ref).max():.1f}); |dTr[PS]| = {abs(tr - tr_ref):.3e}")
+    # FP32 rounding of H_N and U_l, amplified by cond(S) and beta: a relative
+    # floor near 1e-5 of max|P| (reported, not a parity claim)
+    assert err < 1e-4 * np.abs(ref).max() and abs(tr - tr_ref) < 1e-3 * abs(tr_ref)
+
+
+def test_k32768_fp32_full_size_sampled_columns():
+    """K = 32768 (8192-atom sphere), order 2000, beta 200, FP32 recursion with
+    the autotuned pass width.  The oracle cannot diagonalise this size in test
+    time; checks: FP32 against the (oracle-pinned) FP64 GPU path on 64 sampled
+    columns, symmetry of the sampled 64 x 64 block of P, and m_0 = #columns."""
+    w = WORKLOADS["K32768_sphere8192_fp32"]
+    say("case: K=32768 build inputs")
+    c = workload("K32768_sphere8192_fp32")
+    N, beta = w["order"], w["beta"]
+    cols = np.arange(0, c.K, c.K // 64, dtype=np.int64)
+    say(f"case: K={c.K} nnz/row F,S = {c.nnz_per_row[0]:.0f},{c.nnz_per_row[1]:.0f}; setup")
+    ctx = dmlib.Context(precision=dmlib.DM_FP32)
+    ctx.set_cluster(c)
+    lo, hi = ctx.dm_get_bounds()
+    say(f"  bounds [{lo:.2f}, {hi:.2f}]")
+    bw, cfg, table = ctx.dm_autotune(len(cols), steps=5)
+    for row in table:
+        say(f"  tune width {int(row[0]):4d} tile {int(row[2])}x{int(row[3])}: {row[4]:.3f} ms/step, "
+            f"{row[5]:.0f} column-steps/s")
+    say(f"  chosen width {bw} cfg {cfg}")
+    mu = 0.7  # any fixed mu inside the spectrum
+    P32 = np.zeros((len(cols), c.K))
+    ctx.dm_chebyshev_block(cols, N, mu, beta, P32)
+    m32, _ = ctx.dm_moments(N + 1)
+    ctx.dm_set_precision(dmlib.DM_FP64)
+    P64 = np.zeros((len(cols), c.K))
+    ctx.dm_chebyshev_block(cols, N, mu, beta, P64)
+    m64, _ = ctx.dm_moments(N + 1)
+    err = np.abs(P32 - P64).max()
+    blk = P64[:, cols]  # rows = sampled columns, columns = sampled rows
+    asym = np.abs(blk - blk.T).max()
+    say(f"  FP32 vs FP64 max|dP| = {err:.3e} (max|P| {np.abs(P64).max():.1f}); "
+        f"FP64 block asymmetry {asym:.3e}; m0 = {m64[0]:.12f}")
+    assert asym < 1e-9 * max(1.0, np.abs(blk).max())
+    assert abs(m64[0] - len(cols)) < 1e-9 and abs(m32[0] - len(cols)) < 1e-4 * len(cols)
+    assert err < 5e-2 * max(1.0, np.abs(P64).max())
