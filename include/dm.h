@@ -162,6 +162,51 @@ dm_status dm_reset_moments(dm_ctx* ctx);
 dm_status dm_autotune(dm_ctx* ctx, long long ncols, int steps, double* table, int* ntable,
                       int* best_width, int* best_cfg);
 
+/* ---------------------------------------------------------------- batch
+ * Many independent clusters (the paper distributes unit vectors u_a over
+ * processors, parallelisation section; here uneven clusters share one GPU). */
+typedef struct {
+    long long K;
+    const long long* F_rowptr;
+    const int* F_col;
+    const double* F_val;
+    const long long* S_rowptr;
+    const int* S_col;
+    const double* S_val;
+} dm_csr_pair;
+
+/* Load n clusters (CSR as in dm_set_fock, host or device pointers); each gets
+ * its own operator setup and Lanczos interval in the context's precision.
+ * Replaces any previous batch; independent of the single operator of
+ * dm_set_fock.  Errors: as dm_set_fock (the message names the cluster). */
+dm_status dm_batch_set_focks(dm_ctx* ctx, int n, const dm_csr_pair* clusters);
+
+/* Lanczos interval [Emin, Emax] of batch cluster i. */
+dm_status dm_batch_get_bounds(dm_ctx* ctx, int i, double* emin, double* emax);
+
+enum { DM_BATCH_EAGER = 1 };
+
+/* Full density matrices of every cluster: first a moments-only pass over all
+ * columns of all clusters (one persistent launch: workgroups take
+ * (cluster, column block) items longest first and run all order steps of
+ * their block), then per cluster mu_c by bisection with g Tr[P_c S_c] =
+ * n_e[c] (tolerance tol) from those moments, the coefficients at mu_c, and a
+ * second persistent launch that accumulates P_c.  The whole sequence is
+ * captured once in a hipGraph and replayed while (order, beta, n_e, tol,
+ * precision, tile shape) stay the same; flags = DM_BATCH_EAGER launches it
+ * without the graph.  n_e: host, n values.  mu_out: host, n values or NULL.
+ * P_out: NULL or host array of n pointers (each host or device memory, K_c x
+ * K_c column-major FP64, or NULL to skip that cluster).
+ * Errors: DM_E_STATE (no batch), DM_E_ARG, DM_E_BOUNDS, DM_E_NOCONV (a
+ * bisection stopped at rounding level before tol; mu_out still filled). */
+dm_status dm_batch_run(dm_ctx* ctx, int order, double beta, const double* n_e, double tol,
+                       double* mu_out, double* const* P_out, int flags);
+
+/* Tile shape of the batch kernel: time `steps` recursion steps of the
+ * moments pass for each candidate shape on the loaded batch and keep the
+ * fastest.  table rows: (cfg, tile rows, tile cols, ms). */
+dm_status dm_batch_autotune(dm_ctx* ctx, int steps, double* table, int* ntable, int* best_cfg);
+
 /* Stochastic moments (1/n_vec) sum_s xi_s^T T_l(H_N) xi_s, l < n_mom, with
  * caller-supplied probe vectors xi (host or device, K x n_vec column-major
  * FP64, e.g. independent +-1 entries).  m_out: host, n_mom FP64.

@@ -27,13 +27,29 @@ STATUS_NAMES = {0: "DM_OK", -1: "DM_E_ARG", -2: "DM_E_STATE", -3: "DM_E_HIP", -4
 EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_set_fock",
             "dm_get_bounds", "dm_set_bounds", "dm_get_operator", "dm_set_precision", "dm_chebyshev_block",
             "dm_trace", "dm_solve_mu", "dm_moments", "dm_reset_moments", "dm_stoch_moments",
-            "dm_autotune"]
+            "dm_autotune", "dm_batch_set_focks", "dm_batch_get_bounds", "dm_batch_run",
+            "dm_batch_autotune"]
 
 
 class DMError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
+
+
+DM_BATCH_EAGER = 1
+
+
+class dm_csr_pair(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_longlong),
+        ("F_rowptr", ctypes.c_void_p),
+        ("F_col", ctypes.c_void_p),
+        ("F_val", ctypes.c_void_p),
+        ("S_rowptr", ctypes.c_void_p),
+        ("S_col", ctypes.c_void_p),
+        ("S_val", ctypes.c_void_p),
+    ]
 
 
 class dm_options(ctypes.Structure):
@@ -81,6 +97,10 @@ def load(path: str = LIB_PATH):
         "dm_reset_moments": (_I, [_P]),
         "dm_stoch_moments": (_I, [_P, _I, _I, _P, _P]),
         "dm_autotune": (_I, [_P, _LL, _I, _P, _P, _P, _P]),
+        "dm_batch_set_focks": (_I, [_P, _I, _P]),
+        "dm_batch_get_bounds": (_I, [_P, _I, _P, _P]),
+        "dm_batch_run": (_I, [_P, _I, _D, _P, _D, _P, _P, _I]),
+        "dm_batch_autotune": (_I, [_P, _I, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -230,3 +250,53 @@ class Context:
         self._check(self._lib.dm_autotune(self.h, int(ncols), int(steps), ctypes.c_void_p(table.ctypes.data),
                                           ctypes.byref(n), ctypes.byref(bw), ctypes.byref(bc)))
         return bw.value, bc.value, table[:min(n.value, cap)].copy()
+
+    # ---------------------------------------------------------------- batch
+    def dm_batch_set_focks(self, clusters):
+        """clusters: sequence of objects with K and F_/S_ rowptr, col, val."""
+        keep = []
+        arr = (dm_csr_pair * len(clusters))()
+        for i, c in enumerate(clusters):
+            ptrs = [_ptr(c.F_rowptr, np.int64), _ptr(c.F_col, np.int32), _ptr(c.F_val, np.float64),
+                    _ptr(c.S_rowptr, np.int64), _ptr(c.S_col, np.int32), _ptr(c.S_val, np.float64)]
+            keep.append(ptrs)
+            arr[i] = dm_csr_pair(int(c.K), *[p[0].value for p in ptrs])
+        self._check(self._lib.dm_batch_set_focks(self.h, len(clusters), arr))
+        self.batch_K = [int(c.K) for c in clusters]
+
+    def dm_batch_get_bounds(self, i):
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.dm_batch_get_bounds(self.h, int(i), ctypes.byref(lo), ctypes.byref(hi)))
+        return lo.value, hi.value
+
+    def dm_batch_run(self, order, beta, n_e, tol=1e-6, P_out=None, flags=0):
+        """n_e: per-cluster electron counts.  P_out: None or a list of
+        contiguous float64 buffers (K_c * K_c each, column-major; torch on the
+        GPU or host, or numpy; entries may be None).  Returns mu per cluster."""
+        n = len(self.batch_K)
+        ne = np.ascontiguousarray(n_e, dtype=np.float64)
+        mu = np.zeros(n, dtype=np.float64)
+        keep = []
+        parr = None
+        if P_out is not None:
+            parr = (ctypes.c_void_p * n)()
+            for i, p in enumerate(P_out):
+                if p is None:
+                    parr[i] = None
+                    continue
+                pp, pk = _ptr(p, np.float64)
+                if _numel(pk) < self.batch_K[i] ** 2:
+                    raise ValueError("P_out buffer too small")
+                keep.append(pk)
+                parr[i] = pp.value
+        self._check(self._lib.dm_batch_run(self.h, int(order), float(beta), ctypes.c_void_p(ne.ctypes.data),
+                                           float(tol), ctypes.c_void_p(mu.ctypes.data), parr, int(flags)))
+        return mu
+
+    def dm_batch_autotune(self, steps=8):
+        table = np.zeros((16, 4), dtype=np.float64)
+        n = ctypes.c_int(16)
+        best = ctypes.c_int()
+        self._check(self._lib.dm_batch_autotune(self.h, int(steps), ctypes.c_void_p(table.ctypes.data),
+                                                ctypes.byref(n), ctypes.byref(best)))
+        return best.value, table[:n.value].copy()

@@ -34,6 +34,29 @@ long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
 
 }  // namespace
 
+// One loaded operator: the overlap in CSR, S^-1, H^T = (S^-1 F)^T and H_N in
+// the recursion precision, all padded to Kp, and its spectral interval.
+struct Op {
+    long long K = 0;
+    int Kp = 0;
+    double emin = 0, emax = 0;
+    double lz_emin = 0, lz_emax = 0, lz_resid_lo = 0, lz_resid_hi = 0;
+    int lz_steps_done = 0;
+    DevBuf<long long> S_rowptr;
+    DevBuf<int> S_col;
+    DevBuf<double> S_val;
+    DevBuf<double> Sinv;   // Kp x Kp, S^-1
+    DevBuf<double> HT;     // Kp x Kp, (S^-1 F)^T column-major = H row-major
+    DevBuf<double> HNbuf;  // Kp x Kp of the recursion precision (FP64 slots reused for FP32)
+    void release() {
+        S_rowptr.release(); S_col.release(); S_val.release();
+        Sinv.release(); HT.release(); HNbuf.release();
+        K = 0; Kp = 0;
+    }
+};
+
+struct BatchState;
+
 struct dm_ctx {
     dm_options opt{};
     hipStream_t stream = nullptr;
@@ -43,18 +66,11 @@ struct dm_ctx {
 
     // operator
     bool have_fock = false;
-    long long K = 0;
-    int Kp = 0;
     int precision = DM_FP64;
-    double emin = 0, emax = 0;
-    double lz_emin = 0, lz_emax = 0, lz_resid_lo = 0, lz_resid_hi = 0;
-    int lz_steps_done = 0;
-    DevBuf<long long> S_rowptr;
-    DevBuf<int> S_col;
-    DevBuf<double> S_val;
-    DevBuf<double> Sinv;  // Kp x Kp, S^-1
-    DevBuf<double> HT;    // Kp x Kp, (S^-1 F)^T column-major = H row-major
-    DevBuf<double> HNbuf; // Kp x Kp of precision T (FP64 slots reused for FP32)
+    Op op;
+    // batch of independent operators (dm_batch_set_focks)
+    std::vector<Op> batch;
+    BatchState* bstate = nullptr;
 
     // moments
     DevBuf<double> mom;
@@ -71,6 +87,47 @@ struct dm_ctx {
     DevBuf<double> coef, coef_zero, fk, w, v, out;
     DevBuf<int> flag;
     DevBuf<long long> cols;
+};
+
+// Device buffers and launch tables of a loaded batch.
+struct BatchClusterBufs {
+    DevBuf<double> Ua, Ub, Z, P, coef, partial, pstart, mom, w, v, out, fk;
+    DevBuf<long long> cols;  // 0 .. K-1
+    int Bp = 0;
+};
+
+struct BatchState {
+    std::vector<BatchClusterBufs> cl;
+    DevBuf<BatchCluster> d_clusters;
+    DevBuf<BatchItem> d_items;
+    DevBuf<int> counter;
+    int n_items = 0;
+    int cfg = 0;
+    int table_cfg = -1, table_order = -1, table_prec = -1;
+    // captured graph and the parameters it was captured with
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int g_order = -1, g_prec = -1, g_cfg = -1;
+    double g_beta = 0, g_tol = 0;
+    std::vector<double> g_ne;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        g_order = -1;
+    }
+    ~BatchState() {
+        drop_graph();
+        for (auto& b : cl)
+            for (auto* x : {&b.Ua, &b.Ub, &b.Z, &b.P, &b.coef, &b.partial, &b.pstart, &b.mom, &b.w,
+                            &b.v, &b.out, &b.fk})
+                x->release();
+        for (auto& b : cl) b.cols.release();
+        d_clusters.release();
+        d_items.release();
+        counter.release();
+    }
 };
 
 namespace {
@@ -226,8 +283,8 @@ double tridiag_last_component(const std::vector<double>& a, const std::vector<do
 }
 
 // ------------------------------------------------------------------ Lanczos
-dm_status lanczos_bounds(dm_ctx* c) {
-    const int K = (int)c->K, ld = c->Kp;
+dm_status lanczos_bounds(dm_ctx* c, Op& op) {
+    const int K = (int)op.K, ld = op.Kp;
     const int ksteps = std::max(1, std::min<int>(c->opt.lanczos_steps > 0 ? c->opt.lanczos_steps : 100, K));
     hipStream_t s = c->stream;
     DevBuf<double> V, Q, wv, sw, cc, ab, sc;
@@ -245,9 +302,9 @@ dm_status lanczos_bounds(dm_ctx* c) {
     }
     double* alpha = ab.p;
     double* beta = ab.p + ksteps;
-    const long long* rp = c->S_rowptr.p;
-    const int* ci = c->S_col.p;
-    const double* sv = c->S_val.p;
+    const long long* rp = op.S_rowptr.p;
+    const int* ci = op.S_col.p;
+    const double* sv = op.S_val.p;
 #define LZ(expr)                          \
     do {                                  \
         if ((e = (expr)) != hipSuccess) { \
@@ -262,7 +319,7 @@ dm_status lanczos_bounds(dm_ctx* c) {
     for (int j = 0; j < ksteps; ++j) {
         double* vj = V.p + (size_t)j * ld;
         double* qj = Q.p + (size_t)j * ld;
-        LZ(gemv_rows(K, c->HT.p, ld, vj, wv.p, s));
+        LZ(gemv_rows(K, op.HT.p, ld, vj, wv.p, s));
         LZ(dots_cols(K, 1, qj, ld, wv.p, alpha + j, s));
         LZ(lanczos_three_term(K, wv.p, vj, j ? vj - ld : nullptr, alpha + j, j ? beta + j - 1 : beta, s));
         for (int rep = 0; rep < 2; ++rep) {
@@ -300,19 +357,19 @@ dm_status lanczos_bounds(dm_ctx* c) {
     const double r_hi = beta_last * tridiag_last_component(a, b, th_hi);
     const double margin = c->opt.bound_margin > 0 ? c->opt.bound_margin : 0.01;
     const double width = std::max(th_hi - th_lo, 1e-12 * (std::fabs(th_hi) + 1.0));
-    c->lz_emin = th_lo;
-    c->lz_emax = th_hi;
-    c->lz_resid_lo = r_lo;
-    c->lz_resid_hi = r_hi;
-    c->lz_steps_done = k;
-    c->emin = th_lo - std::fabs(r_lo) - margin * width;
-    c->emax = th_hi + std::fabs(r_hi) + margin * width;
+    op.lz_emin = th_lo;
+    op.lz_emax = th_hi;
+    op.lz_resid_lo = r_lo;
+    op.lz_resid_hi = r_hi;
+    op.lz_steps_done = k;
+    op.emin = th_lo - std::fabs(r_lo) - margin * width;
+    op.emax = th_hi + std::fabs(r_hi) + margin * width;
     return DM_OK;
 }
 
-dm_status normalize(dm_ctx* c) {
-    const double ebar = 0.5 * (c->emax + c->emin), de = 0.5 * (c->emax - c->emin);
-    HIPTRY(c, normalize_operator((int)c->K, c->Kp, c->HT.p, ebar, de, c->precision, c->HNbuf.p, c->stream));
+dm_status normalize(dm_ctx* c, Op& op) {
+    const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
+    HIPTRY(c, normalize_operator((int)op.K, op.Kp, op.HT.p, ebar, de, c->precision, op.HNbuf.p, c->stream));
     return DM_OK;
 }
 
@@ -339,6 +396,133 @@ int pick_cfg(int Kp, int ncols) {
         }
     }
     return best < 0 ? 0 : best;
+}
+
+}  // namespace
+
+namespace {
+
+struct HostCsr {
+    std::vector<long long> rp;
+    std::vector<int> col;
+    std::vector<double> val;
+};
+
+// Copies a CSR pair (host or device pointers) to the host and validates it.
+dm_status load_csr_pair(dm_ctx* c, long long K, const long long* F_rowptr, const int* F_col,
+                        const double* F_val, const long long* S_rowptr, const int* S_col,
+                        const double* S_val, HostCsr& F, HostCsr& S) {
+    if (K <= 0 || K > (1LL << 30)) return set_err(c, DM_E_ARG, "K out of range");
+    if (!F_rowptr || !F_col || !F_val || !S_rowptr || !S_col || !S_val)
+        return set_err(c, DM_E_ARG, "null CSR array");
+    HIPTRY(c, to_host(F.rp, F_rowptr, (size_t)K + 1));
+    HIPTRY(c, to_host(S.rp, S_rowptr, (size_t)K + 1));
+    if (F.rp[K] < 0 || S.rp[K] < 0 || F.rp[0] != 0 || S.rp[0] != 0)
+        return set_err(c, DM_E_ARG, "malformed rowptr");
+    HIPTRY(c, to_host(F.col, F_col, (size_t)F.rp[K]));
+    HIPTRY(c, to_host(F.val, F_val, (size_t)F.rp[K]));
+    HIPTRY(c, to_host(S.col, S_col, (size_t)S.rp[K]));
+    HIPTRY(c, to_host(S.val, S_val, (size_t)S.rp[K]));
+    std::string msg = check_csr("F", K, F.rp, F.col, F.val, false);
+    if (msg.empty()) msg = check_csr("S", K, S.rp, S.col, S.val, true);
+    if (!msg.empty()) return set_err(c, DM_E_ARG, msg);
+    return DM_OK;
+}
+
+// Operator setup for one (F, S): S = U^T U, S^-1, H^T, Lanczos interval, H_N.
+dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const HostCsr& Sh) {
+    const std::vector<long long>& frp = Fh.rp;
+    const std::vector<int>& fcol = Fh.col;
+    const std::vector<double>& fval = Fh.val;
+    const std::vector<long long>& srp = Sh.rp;
+    const std::vector<int>& scol = Sh.col;
+    const std::vector<double>& sval = Sh.val;
+    hipStream_t s = c->stream;
+    op.K = K;
+    op.Kp = (int)round_up(K, kRowPad);
+    const int Kp = op.Kp;
+    const size_t KK = (size_t)Kp * Kp;
+    // ---- device copies of S (kept) and F (temporary)
+    HIPTRY(c, ensure(op.S_rowptr, (size_t)K + 1));
+    HIPTRY(c, ensure(op.S_col, sval.size()));
+    HIPTRY(c, ensure(op.S_val, sval.size()));
+    HIPTRY(c, hipMemcpyAsync(op.S_rowptr.p, srp.data(), srp.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.S_col.p, scol.data(), scol.size() * 4, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.S_val.p, sval.data(), sval.size() * 8, hipMemcpyHostToDevice, s));
+    DevBuf<long long> Frp;
+    DevBuf<int> Fci;
+    DevBuf<double> Fv, Vblk, tmp;
+    auto release_tmp = [&]() { Frp.release(); Fci.release(); Fv.release(); Vblk.release(); tmp.release(); };
+    hipError_t e;
+#define ST(expr)                          \
+    do {                                  \
+        if ((e = (expr)) != hipSuccess) { \
+            release_tmp();                \
+            return fail_hip(c, e, #expr); \
+        }                                 \
+    } while (0)
+    ST(ensure(Frp, (size_t)K + 1));
+    ST(ensure(Fci, fval.size()));
+    ST(ensure(Fv, fval.size()));
+    ST(hipMemcpyAsync(Frp.p, frp.data(), frp.size() * 8, hipMemcpyHostToDevice, s));
+    ST(hipMemcpyAsync(Fci.p, fcol.data(), fcol.size() * 4, hipMemcpyHostToDevice, s));
+    ST(hipMemcpyAsync(Fv.p, fval.data(), fval.size() * 8, hipMemcpyHostToDevice, s));
+    // ---- dense buffers: A (S -> U -> F -> HN), X (U^-T -> H^T), Sinv
+    ST(ensure(op.HNbuf, KK));
+    ST(ensure(op.HT, KK));
+    ST(ensure(op.Sinv, KK));
+    ST(ensure(Vblk, (size_t)Kp * kNb));
+    ST(ensure(tmp, (size_t)Kp * kNb));
+    double* A = op.HNbuf.p;
+    double* X = op.HT.p;
+    const long ld = Kp;
+    ST(fill_f64(A, 0.0, (long long)KK, s));
+    ST(csr_to_dense((int)K, Kp, op.S_rowptr.p, op.S_col.p, op.S_val.p, 1.0, A, s));
+    ST(fill_i32(c->flag.p, 0, 4, s));
+    // ---- blocked Cholesky S = U^T U (upper, right-looking)
+    for (int k = 0; k < Kp; k += kNb) {
+        double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
+        ST(potrf_diag(A + k + (long)k * ld, ld, Vk, c->flag.p, k, s));
+        const int n2 = Kp - k - kNb;
+        if (n2 > 0) {
+            // U12 = U_kk^-T A12, then A22 -= U12^T U12 (upper tiles only)
+            ST(gemm_tn_f64(kNb, n2, kNb, 1.0, Vk, kNb, A + k + (long)(k + kNb) * ld, ld, 0.0, tmp.p,
+                           kNb, false, s));
+            ST(hipMemcpy2DAsync(A + k + (long)(k + kNb) * ld, ld * 8, tmp.p, kNb * 8, kNb * 8, n2,
+                                hipMemcpyDeviceToDevice, s));
+            ST(gemm_tn_f64(n2, n2, kNb, -1.0, tmp.p, kNb, tmp.p, kNb, 1.0,
+                           A + (k + kNb) + (long)(k + kNb) * ld, ld, true, s));
+        }
+    }
+    int info[4] = {0, 0, 0, 0};
+    ST(hipMemcpyAsync(info, c->flag.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    if (info[0] != 0) {
+        release_tmp();
+        return set_err(c, DM_E_NOTSPD, "overlap matrix is not positive definite (pivot " +
+                                           std::to_string(info[0] - 1) + ")");
+    }
+    // ---- X = U^-T (lower) by block forward substitution
+    ST(fill_f64(X, 0.0, (long long)KK, s));
+    for (int k = 0; k < Kp; k += kNb) {
+        const double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
+        if (k > 0) {
+            ST(gemm_tn_f64(kNb, k, k, -1.0, A + (long)k * ld, ld, X, ld, 0.0, tmp.p, kNb, false, s));
+            ST(gemm_tn_f64(kNb, k, kNb, 1.0, Vk, kNb, tmp.p, kNb, 0.0, X + k, ld, false, s));
+        }
+        ST(copy_transpose_block(Vk, kNb, X + k + (long)k * ld, ld, s));
+    }
+    // ---- S^-1 = X^T X, then A := F and H^T = F S^-1
+    ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, X, ld, X, ld, 0.0, op.Sinv.p, ld, false, s));
+    ST(fill_f64(A, 0.0, (long long)KK, s));
+    ST(csr_to_dense((int)K, Kp, Frp.p, Fci.p, Fv.p, 0.0, A, s));
+    ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, A, ld, op.Sinv.p, ld, 0.0, X, ld, false, s));
+    ST(hipStreamSynchronize(s));
+    release_tmp();
+#undef ST
+    dm_status st = lanczos_bounds(c, op);
+    if (st != DM_OK) return st;
+    return normalize(c, op);
 }
 
 }  // namespace
@@ -418,12 +602,13 @@ void dm_destroy(dm_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->opt.device);
     if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
-    for (auto* b : {&c->Sinv, &c->HT, &c->HNbuf, &c->S_val, &c->mom, &c->Ua, &c->Ub, &c->Z, &c->P,
+    for (auto* b : {&c->op.Sinv, &c->op.HT, &c->op.HNbuf, &c->op.S_val, &c->mom, &c->Ua, &c->Ub, &c->Z, &c->P,
                     &c->part_start, &c->part_steps, &c->coef, &c->coef_zero, &c->fk, &c->w, &c->v,
                     &c->out})
         b->release();
-    c->S_rowptr.release();
-    c->S_col.release();
+    c->op.release();
+    for (auto& o : c->batch) o.release();
+    delete c->bstate;
     c->flag.release();
     c->cols.release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -449,116 +634,12 @@ dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const i
     c->tuned_width = 0;
     c->tuned_cfg = -1;
     reset_moments(c);
-    // ---- copy to host and validate
-    std::vector<long long> frp, srp;
-    std::vector<int> fcol, scol;
-    std::vector<double> fval, sval;
-    HIPTRY(c, to_host(frp, F_rowptr, (size_t)K + 1));
-    HIPTRY(c, to_host(srp, S_rowptr, (size_t)K + 1));
-    if (frp[K] < 0 || srp[K] < 0 || frp[0] != 0 || srp[0] != 0)
-        return set_err(c, DM_E_ARG, "malformed rowptr");
-    HIPTRY(c, to_host(fcol, F_col, (size_t)frp[K]));
-    HIPTRY(c, to_host(fval, F_val, (size_t)frp[K]));
-    HIPTRY(c, to_host(scol, S_col, (size_t)srp[K]));
-    HIPTRY(c, to_host(sval, S_val, (size_t)srp[K]));
-    std::string msg = check_csr("F", K, frp, fcol, fval, false);
-    if (msg.empty()) msg = check_csr("S", K, srp, scol, sval, true);
-    if (!msg.empty()) return set_err(c, DM_E_ARG, msg);
-
-    hipStream_t s = c->stream;
-    c->K = K;
-    c->Kp = (int)round_up(K, kRowPad);
-    const int Kp = c->Kp;
-    const size_t KK = (size_t)Kp * Kp;
-    // ---- device copies of S (kept) and F (temporary)
-    HIPTRY(c, ensure(c->S_rowptr, (size_t)K + 1));
-    HIPTRY(c, ensure(c->S_col, sval.size()));
-    HIPTRY(c, ensure(c->S_val, sval.size()));
-    HIPTRY(c, hipMemcpyAsync(c->S_rowptr.p, srp.data(), srp.size() * 8, hipMemcpyHostToDevice, s));
-    HIPTRY(c, hipMemcpyAsync(c->S_col.p, scol.data(), scol.size() * 4, hipMemcpyHostToDevice, s));
-    HIPTRY(c, hipMemcpyAsync(c->S_val.p, sval.data(), sval.size() * 8, hipMemcpyHostToDevice, s));
-    DevBuf<long long> Frp;
-    DevBuf<int> Fci;
-    DevBuf<double> Fv, Vblk, tmp;
-    auto release_tmp = [&]() { Frp.release(); Fci.release(); Fv.release(); Vblk.release(); tmp.release(); };
-    hipError_t e;
-#define ST(expr)                          \
-    do {                                  \
-        if ((e = (expr)) != hipSuccess) { \
-            release_tmp();                \
-            return fail_hip(c, e, #expr); \
-        }                                 \
-    } while (0)
-    ST(ensure(Frp, (size_t)K + 1));
-    ST(ensure(Fci, fval.size()));
-    ST(ensure(Fv, fval.size()));
-    ST(hipMemcpyAsync(Frp.p, frp.data(), frp.size() * 8, hipMemcpyHostToDevice, s));
-    ST(hipMemcpyAsync(Fci.p, fcol.data(), fcol.size() * 4, hipMemcpyHostToDevice, s));
-    ST(hipMemcpyAsync(Fv.p, fval.data(), fval.size() * 8, hipMemcpyHostToDevice, s));
-    // ---- dense buffers: A (S -> U -> F -> HN), X (U^-T -> H^T), Sinv
-    ST(ensure(c->HNbuf, KK));
-    ST(ensure(c->HT, KK));
-    ST(ensure(c->Sinv, KK));
-    ST(ensure(Vblk, (size_t)Kp * kNb));
-    ST(ensure(tmp, (size_t)Kp * kNb));
-    double* A = c->HNbuf.p;
-    double* X = c->HT.p;
-    const long ld = Kp;
-    ST(fill_f64(A, 0.0, (long long)KK, s));
-    ST(csr_to_dense((int)K, Kp, c->S_rowptr.p, c->S_col.p, c->S_val.p, 1.0, A, s));
-    ST(fill_i32(c->flag.p, 0, 4, s));
-    // ---- blocked Cholesky S = U^T U (upper, right-looking)
-    for (int k = 0; k < Kp; k += kNb) {
-        double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
-        ST(potrf_diag(A + k + (long)k * ld, ld, Vk, c->flag.p, k, s));
-        const int n2 = Kp - k - kNb;
-        if (n2 > 0) {
-            // U12 = U_kk^-T A12, then A22 -= U12^T U12 (upper tiles only)
-            ST(gemm_tn_f64(kNb, n2, kNb, 1.0, Vk, kNb, A + k + (long)(k + kNb) * ld, ld, 0.0, tmp.p,
-                           kNb, false, s));
-            ST(hipMemcpy2DAsync(A + k + (long)(k + kNb) * ld, ld * 8, tmp.p, kNb * 8, kNb * 8, n2,
-                                hipMemcpyDeviceToDevice, s));
-            ST(gemm_tn_f64(n2, n2, kNb, -1.0, tmp.p, kNb, tmp.p, kNb, 1.0,
-                           A + (k + kNb) + (long)(k + kNb) * ld, ld, true, s));
-        }
-    }
-    int info[4] = {0, 0, 0, 0};
-    ST(hipMemcpyAsync(info, c->flag.p, sizeof(info), hipMemcpyDeviceToHost, s));
-    ST(hipStreamSynchronize(s));
-    if (info[0] != 0) {
-        release_tmp();
-        return set_err(c, DM_E_NOTSPD, "overlap matrix is not positive definite (pivot " +
-                                           std::to_string(info[0] - 1) + ")");
-    }
-    // ---- X = U^-T (lower) by block forward substitution
-    ST(fill_f64(X, 0.0, (long long)KK, s));
-    for (int k = 0; k < Kp; k += kNb) {
-        const double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
-        if (k > 0) {
-            ST(gemm_tn_f64(kNb, k, k, -1.0, A + (long)k * ld, ld, X, ld, 0.0, tmp.p, kNb, false, s));
-            ST(gemm_tn_f64(kNb, k, kNb, 1.0, Vk, kNb, tmp.p, kNb, 0.0, X + k, ld, false, s));
-        }
-        ST(copy_transpose_block(Vk, kNb, X + k + (long)k * ld, ld, s));
-    }
-    // ---- S^-1 = X^T X, then A := F and H^T = F S^-1
-    ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, X, ld, X, ld, 0.0, c->Sinv.p, ld, false, s));
-    ST(fill_f64(A, 0.0, (long long)KK, s));
-    ST(csr_to_dense((int)K, Kp, Frp.p, Fci.p, Fv.p, 0.0, A, s));
-    ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, A, ld, c->Sinv.p, ld, 0.0, X, ld, false, s));
-    ST(hipStreamSynchronize(s));
-    release_tmp();
-#undef ST
+    HostCsr Fh, Sh;
+    st = load_csr_pair(c, K, F_rowptr, F_col, F_val, S_rowptr, S_col, S_val, Fh, Sh);
+    if (st != DM_OK) return st;
+    st = build_op(c, c->op, K, Fh, Sh);
+    if (st != DM_OK) return st;
     c->have_fock = true;
-    st = lanczos_bounds(c);
-    if (st != DM_OK) {
-        c->have_fock = false;
-        return st;
-    }
-    st = normalize(c);
-    if (st != DM_OK) {
-        c->have_fock = false;
-        return st;
-    }
     return DM_OK;
 }
 
@@ -567,8 +648,8 @@ dm_status dm_get_bounds(dm_ctx* c, double* emin, double* emax) {
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
-    if (emin) *emin = c->emin;
-    if (emax) *emax = c->emax;
+    if (emin) *emin = c->op.emin;
+    if (emax) *emax = c->op.emax;
     return DM_OK;
 }
 
@@ -579,10 +660,10 @@ dm_status dm_set_bounds(dm_ctx* c, double emin, double emax) {
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
     if (!std::isfinite(emin) || !std::isfinite(emax) || !(emin < emax))
         return set_err(c, DM_E_ARG, "need finite emin < emax");
-    c->emin = emin;
-    c->emax = emax;
+    c->op.emin = emin;
+    c->op.emax = emax;
     reset_moments(c);
-    return normalize(c);
+    return normalize(c, c->op);
 }
 
 dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
@@ -591,15 +672,15 @@ dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
     if (st != DM_OK) return st;
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
     if (!out || (which != DM_OP_SINV && which != DM_OP_H)) return set_err(c, DM_E_ARG, "bad operator request");
-    const size_t K = (size_t)c->K, Kp = (size_t)c->Kp;
+    const size_t K = (size_t)c->op.K, Kp = (size_t)c->op.Kp;
     hipStream_t s = c->stream;
     if (which == DM_OP_SINV) {
-        HIPTRY(c, hipMemcpy2DAsync(out, K * 8, c->Sinv.p, Kp * 8, K * 8, K, hipMemcpyDefault, s));
+        HIPTRY(c, hipMemcpy2DAsync(out, K * 8, c->op.Sinv.p, Kp * 8, K * 8, K, hipMemcpyDefault, s));
     } else {
         // HT holds H^T column-major; transpose through a device scratch buffer
         DevBuf<double> t;
         HIPTRY(c, ensure(t, K * K));
-        HIPTRY(c, hipMemcpy2DAsync(t.p, K * 8, c->HT.p, Kp * 8, K * 8, K, hipMemcpyDeviceToDevice, s));
+        HIPTRY(c, hipMemcpy2DAsync(t.p, K * 8, c->op.HT.p, Kp * 8, K * 8, K, hipMemcpyDeviceToDevice, s));
         std::vector<double> h(K * K), ht(K * K);
         hipError_t e = hipMemcpyAsync(ht.data(), t.p, K * K * 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -621,7 +702,7 @@ dm_status dm_set_precision(dm_ctx* c, int precision) {
     c->precision = precision;
     reset_moments(c);
     if (!c->have_fock) return DM_OK;
-    return normalize(c);
+    return normalize(c, c->op);
 }
 
 dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, int order,
@@ -633,9 +714,9 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
     if (order < 2 || order > (1 << 20)) return set_err(c, DM_E_ARG, "order must be >= 2");
     if (!std::isfinite(mu) || !std::isfinite(beta) || !(beta > 0))
         return set_err(c, DM_E_ARG, "need finite mu and beta > 0");
-    if (ncols < 0 || ncols > c->K) return set_err(c, DM_E_ARG, "ncols out of range");
+    if (ncols < 0 || ncols > c->op.K) return set_err(c, DM_E_ARG, "ncols out of range");
     if (ncols > 0 && !cols) return set_err(c, DM_E_ARG, "cols is NULL");
-    const long long K = c->K;
+    const long long K = c->op.K;
     std::vector<long long> hc;
     HIPTRY(c, to_host(hc, cols, (size_t)ncols));
     {
@@ -647,7 +728,7 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
         }
     }
     hipStream_t s = c->stream;
-    const int Kp = c->Kp;
+    const int Kp = c->op.Kp;
     if (order != c->mom_order) {
         HIPTRY(c, ensure(c->mom, (size_t)order + 1));
         HIPTRY(c, fill_f64(c->mom.p, 0.0, order + 1, s));
@@ -655,7 +736,7 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
         c->ncols_done = 0;
     }
     if (ncols == 0) return DM_OK;
-    const double ebar = 0.5 * (c->emax + c->emin), de = 0.5 * (c->emax - c->emin);
+    const double ebar = 0.5 * (c->op.emax + c->op.emin), de = 0.5 * (c->op.emax - c->op.emin);
     const int M = 4 * order;
     HIPTRY(c, ensure(c->coef, (size_t)order + 1));
     HIPTRY(c, ensure(c->fk, (size_t)M));
@@ -689,8 +770,8 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
         HIPTRY(c, hipMemcpyAsync(c->cols.p, hc.data() + off, (size_t)nc * 8, hipMemcpyHostToDevice, s));
         HIPTRY(c, fill_f64(c->Z.p, 0.0, (long long)Kp * Bp, s));
         int nts = 0;
-        HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, c->Sinv.p, c->S_rowptr.p, c->S_col.p,
-                             c->S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p,
+        HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, c->op.Sinv.p, c->op.S_rowptr.p, c->op.S_col.p,
+                             c->op.S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p,
                              c->part_start.p, &nts, s));
         HIPTRY(c, reduce_moments(0, nts, c->part_start.p, c->mom.p, c->flag.p, s));
         void* ucur = c->Ua.p;
@@ -698,7 +779,7 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
         ChebStepArgs a{};
         a.Kp = Kp;
         a.Bp = Bp;
-        a.HN = c->HNbuf.p;
+        a.HN = c->op.HNbuf.p;
         a.coef = c->coef.p;
         a.P = c->P.p;
         a.Z = c->Z.p;
@@ -743,11 +824,11 @@ static dm_status eval_trace(dm_ctx* c, double beta, double target, double tol, d
     if (!std::isfinite(beta) || !(beta > 0)) return set_err(c, DM_E_ARG, "need beta > 0");
     hipStream_t s = c->stream;
     const int N = c->mom_order, M = 4 * N;
-    const double ebar = 0.5 * (c->emax + c->emin), de = 0.5 * (c->emax - c->emin);
+    const double ebar = 0.5 * (c->op.emax + c->op.emin), de = 0.5 * (c->op.emax - c->op.emin);
     HIPTRY(c, ensure(c->w, (size_t)M));
     HIPTRY(c, ensure(c->v, (size_t)M));
     HIPTRY(c, trace_weights(N, M, ebar, de, c->mom.p, c->w.p, c->v.p, s));
-    HIPTRY(c, mu_bisect(M, ebar, de, beta, target, tol, c->emin, c->emax, mu_in, max_iter, c->w.p,
+    HIPTRY(c, mu_bisect(M, ebar, de, beta, target, tol, c->op.emin, c->op.emax, mu_in, max_iter, c->w.p,
                         c->v.p, c->out.p, s));
     HIPTRY(c, hipMemcpyAsync(out, c->out.p, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPTRY(c, hipStreamSynchronize(s));
@@ -813,7 +894,7 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
     if (ncols < 1 || steps < 1) return set_err(c, DM_E_ARG, "need ncols >= 1 and steps >= 1");
     hipStream_t s = c->stream;
-    const int K = (int)c->K, Kp = c->Kp;
+    const int K = (int)c->op.K, Kp = c->op.Kp;
     const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
     const int wmax = (int)std::max<long long>(32, std::min<long long>(ncols, 256));
     struct Cand { int w, cfg; double ms; };
@@ -859,12 +940,12 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
         const int nc = std::min(cd.w, K);
         AT(fill_f64(Zb.p, 0.0, (long long)Kp * cd.w, s));
         int nts = 0;
-        AT(cheb_start(K, Kp, cd.w, nc, colsd.p, c->Sinv.p, c->S_rowptr.p, c->S_col.p, c->S_val.p,
+        AT(cheb_start(K, Kp, cd.w, nc, colsd.p, c->op.Sinv.p, c->op.S_rowptr.p, c->op.S_col.p, c->op.S_val.p,
                       c->precision, U0.p, Zb.p, Pb.p, coef.p, pst.p, &nts, s));
         ChebStepArgs a{};
         a.Kp = Kp;
         a.Bp = cd.w;
-        a.HN = c->HNbuf.p;
+        a.HN = c->op.HNbuf.p;
         a.coef = coef.p;
         a.P = Pb.p;
         a.Z = Zb.p;
@@ -925,7 +1006,7 @@ dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, do
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
     if (n_mom < 1 || n_vec < 1 || !xi || !m_out) return set_err(c, DM_E_ARG, "bad stochastic-moment arguments");
     hipStream_t s = c->stream;
-    const int K = (int)c->K, Kp = c->Kp;
+    const int K = (int)c->op.K, Kp = c->op.Kp;
     const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
     const int cfg = pick_cfg(Kp, n_vec);
     const int BN = cheb_tile_cols(cfg);
@@ -962,7 +1043,7 @@ dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, do
     ChebStepArgs a{};
     a.Kp = Kp;
     a.Bp = Bp;
-    a.HN = c->HNbuf.p;
+    a.HN = c->op.HNbuf.p;
     a.coef = cz.p;
     a.P = Pd.p;
     a.Z = Zs.p;
@@ -986,3 +1067,310 @@ dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, do
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------- batch
+
+namespace {
+
+// (Re)builds the per-cluster buffers and the device tables of the batch
+// kernel for tile shape cfg and `order` steps.  Rebuilding invalidates any
+// captured graph (buffer addresses may change).
+dm_status batch_tables(dm_ctx* c, int cfg, int order) {
+    BatchState& bs = *c->bstate;
+    if (bs.table_cfg == cfg && bs.table_order == order && bs.table_prec == c->precision) return DM_OK;
+    bs.drop_graph();
+    const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
+    const int BN = cheb_tile_cols(cfg);
+    const int n = (int)c->batch.size();
+    const int M = 4 * order;
+    std::vector<BatchCluster> hcl(n);
+    std::vector<std::pair<long long, BatchItem>> items;
+    for (int i = 0; i < n; ++i) {
+        const Op& op = c->batch[i];
+        BatchClusterBufs& b = bs.cl[i];
+        const size_t KB = (size_t)op.Kp * b.Bp;
+        HIPTRY(c, ensure(b.Ua, KB * tsz / 8));
+        HIPTRY(c, ensure(b.Ub, KB * tsz / 8));
+        HIPTRY(c, ensure(b.Z, KB));
+        HIPTRY(c, ensure(b.P, KB));
+        HIPTRY(c, ensure(b.coef, (size_t)order + 1));
+        HIPTRY(c, ensure(b.partial, (size_t)(order + 1) * (b.Bp / 32)));
+        HIPTRY(c, ensure(b.pstart, (size_t)(op.Kp / 64) * (b.Bp / 16)));
+        HIPTRY(c, ensure(b.mom, (size_t)order + 1));
+        HIPTRY(c, ensure(b.w, (size_t)M));
+        HIPTRY(c, ensure(b.v, (size_t)M));
+        HIPTRY(c, ensure(b.fk, (size_t)M));
+        HIPTRY(c, ensure(b.out, 8));
+        BatchCluster& h = hcl[i];
+        h.Kp = op.Kp;
+        h.Bp = b.Bp;
+        h.nblocks = b.Bp / BN;
+        h.HN = op.HNbuf.p;
+        h.Ua = b.Ua.p;
+        h.Ub = b.Ub.p;
+        h.P = b.P.p;
+        h.Z = b.Z.p;
+        h.coef = b.coef.p;
+        h.partial = b.partial.p;
+        for (int blk = 0; blk < h.nblocks; ++blk)
+            items.push_back({(long long)op.Kp * op.Kp, BatchItem{i, blk}});
+    }
+    // longest items first: a workgroup that takes a short item late cannot
+    // hold up the end of the launch by much
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<long long, BatchItem>& x, const std::pair<long long, BatchItem>& y) {
+                         return x.first > y.first;
+                     });
+    std::vector<BatchItem> hitems(items.size());
+    for (size_t k = 0; k < items.size(); ++k) hitems[k] = items[k].second;
+    HIPTRY(c, ensure(bs.d_clusters, (size_t)n));
+    HIPTRY(c, ensure(bs.d_items, hitems.size()));
+    HIPTRY(c, ensure(bs.counter, 4));
+    HIPTRY(c, hipMemcpy(bs.d_clusters.p, hcl.data(), n * sizeof(BatchCluster), hipMemcpyHostToDevice));
+    HIPTRY(c, hipMemcpy(bs.d_items.p, hitems.data(), hitems.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+    bs.n_items = (int)hitems.size();
+    bs.table_cfg = cfg;
+    bs.table_order = order;
+    bs.table_prec = c->precision;
+    return DM_OK;
+}
+
+int batch_grid(dm_ctx* c, int cfg) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->opt.device) != hipSuccess || cus < 1)
+        cus = 256;
+    const int occ = std::max(1, cheb_batch_occupancy(cfg, c->precision));
+    return std::max(1, std::min(c->bstate->n_items, cus * occ));
+}
+
+// Start blocks of every cluster (U_0 = S^-1 columns into U_a, Z = S, P = a_0 U_0).
+hipError_t batch_start(dm_ctx* c, bool zero_moments) {
+    BatchState& bs = *c->bstate;
+    hipStream_t s = c->stream;
+    hipError_t e;
+    for (size_t i = 0; i < c->batch.size(); ++i) {
+        const Op& op = c->batch[i];
+        BatchClusterBufs& b = bs.cl[i];
+        if ((e = fill_f64(b.Z.p, 0.0, (long long)op.Kp * b.Bp, s)) != hipSuccess) return e;
+        int nts = 0;
+        if ((e = cheb_start((int)op.K, op.Kp, b.Bp, (int)op.K, b.cols.p, op.Sinv.p, op.S_rowptr.p,
+                            op.S_col.p, op.S_val.p, c->precision, b.Ua.p, b.Z.p, b.P.p, b.coef.p,
+                            b.pstart.p, &nts, s)) != hipSuccess)
+            return e;
+        if (zero_moments) {
+            if ((e = fill_f64(b.mom.p, 0.0, bs.table_order + 1, s)) != hipSuccess) return e;
+            if ((e = reduce_moments(0, nts, b.pstart.p, b.mom.p, c->flag.p, s)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// The whole batch sequence on c->stream (also recorded under graph capture).
+hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<double>& ne, double tol,
+                         int grid) {
+    BatchState& bs = *c->bstate;
+    hipStream_t s = c->stream;
+    const int n = (int)c->batch.size();
+    const int M = 4 * order;
+    const double g = c->opt.spin;
+    hipError_t e;
+#define BQ(x)                                 \
+    do {                                      \
+        if ((e = (x)) != hipSuccess) return e; \
+    } while (0)
+    BQ(fill_i32(c->flag.p, 0, 4, s));
+    BQ(fill_i32(bs.counter.p, 0, 4, s));
+    for (int i = 0; i < n; ++i) BQ(fill_f64(bs.cl[i].coef.p, 0.0, order + 1, s));
+    // pass 1: moments of every column (coefficients zero: P is not touched)
+    BQ(batch_start(c, true));
+    BatchArgs a{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p, order, 0};
+    BQ(cheb_batch(a, bs.cfg, c->precision, grid, s));
+    const int BN = cheb_tile_cols(bs.cfg);
+    for (int i = 0; i < n; ++i) {
+        const Op& op = c->batch[i];
+        BatchClusterBufs& b = bs.cl[i];
+        const int nb = b.Bp / BN;
+        BQ(reduce_moments(order - 1, nb, b.partial.p + nb, b.mom.p + 1, c->flag.p, s));
+        const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
+        // mu_c from the exact moments, then the coefficients at mu_c
+        BQ(trace_weights(order, M, ebar, de, b.mom.p, b.w.p, b.v.p, s));
+        BQ(mu_bisect(M, ebar, de, beta, ne[i] / g, tol / g, op.emin, op.emax, 0.0, 200, b.w.p, b.v.p,
+                     b.out.p, s));
+        BQ(cheb_coefficients_devmu(order, M, ebar, de, b.out.p, beta, b.fk.p, b.coef.p, s));
+    }
+    // pass 2: P at mu_c
+    BQ(batch_start(c, false));
+    BatchArgs a2{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p + 1, order, 1};
+    BQ(cheb_batch(a2, bs.cfg, c->precision, grid, s));
+#undef BQ
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (n < 1 || !cl) return set_err(c, DM_E_ARG, "need n >= 1 clusters");
+    delete c->bstate;
+    c->bstate = nullptr;
+    for (auto& o : c->batch) o.release();
+    c->batch.clear();
+    c->batch.resize(n);
+    for (int i = 0; i < n; ++i) {
+        HostCsr Fh, Sh;
+        st = load_csr_pair(c, cl[i].K, cl[i].F_rowptr, cl[i].F_col, cl[i].F_val, cl[i].S_rowptr,
+                           cl[i].S_col, cl[i].S_val, Fh, Sh);
+        if (st == DM_OK) st = build_op(c, c->batch[i], cl[i].K, Fh, Sh);
+        if (st != DM_OK) {
+            const std::string m = "cluster " + std::to_string(i) + ": " + c->err;
+            for (auto& o : c->batch) o.release();
+            c->batch.clear();
+            return set_err(c, st, m);
+        }
+        c->batch[i].HT.release();  // H^T is only needed to renormalise; the batch keeps H_N
+    }
+    c->bstate = new BatchState();
+    c->bstate->cl.resize(n);
+    for (int i = 0; i < n; ++i) {
+        BatchClusterBufs& b = c->bstate->cl[i];
+        const long long K = c->batch[i].K;
+        b.Bp = (int)round_up(K, kColPad);
+        std::vector<long long> ar((size_t)K);
+        for (long long j = 0; j < K; ++j) ar[j] = j;
+        HIPTRY(c, ensure(b.cols, (size_t)K));
+        HIPTRY(c, hipMemcpy(b.cols.p, ar.data(), (size_t)K * 8, hipMemcpyHostToDevice));
+    }
+    return DM_OK;
+}
+
+dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, double tol,
+                       double* mu_out, double* const* P_out, int flags) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->bstate || c->batch.empty()) return set_err(c, DM_E_STATE, "no batch loaded");
+    if (order < 2 || !(beta > 0) || !std::isfinite(beta) || !(tol > 0) || !n_e)
+        return set_err(c, DM_E_ARG, "need order >= 2, beta > 0, tol > 0 and n_e");
+    BatchState& bs = *c->bstate;
+    const int n = (int)c->batch.size();
+    std::vector<double> ne(n_e, n_e + n);
+    for (double x : ne)
+        if (!std::isfinite(x)) return set_err(c, DM_E_ARG, "non-finite n_e");
+    st = batch_tables(c, bs.cfg, order);
+    if (st != DM_OK) return st;
+    const int grid = batch_grid(c, bs.cfg);
+    hipStream_t s = c->stream;
+    if (flags & DM_BATCH_EAGER) {
+        HIPTRY(c, batch_enqueue(c, order, beta, ne, tol, grid));
+    } else {
+        const bool same = bs.exec && bs.g_order == order && bs.g_beta == beta && bs.g_tol == tol &&
+                          bs.g_prec == c->precision && bs.g_cfg == bs.cfg && bs.g_ne == ne;
+        if (!same) {
+            bs.drop_graph();
+            HIPTRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            const hipError_t e1 = batch_enqueue(c, order, beta, ne, tol, grid);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (e1 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail_hip(c, e1, "batch capture");
+            }
+            HIPTRY(c, e2);
+            bs.graph = g;
+            HIPTRY(c, hipGraphInstantiate(&bs.exec, bs.graph, nullptr, nullptr, 0));
+            bs.g_order = order;
+            bs.g_beta = beta;
+            bs.g_tol = tol;
+            bs.g_prec = c->precision;
+            bs.g_cfg = bs.cfg;
+            bs.g_ne = ne;
+        }
+        HIPTRY(c, hipGraphLaunch(bs.exec, s));
+    }
+    std::vector<double> outs((size_t)n * 8);
+    for (int i = 0; i < n; ++i)
+        HIPTRY(c, hipMemcpyAsync(outs.data() + 8 * i, bs.cl[i].out.p, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (P_out)
+        for (int i = 0; i < n; ++i)
+            if (P_out[i]) {
+                const size_t K = (size_t)c->batch[i].K, Kp = (size_t)c->batch[i].Kp;
+                HIPTRY(c, hipMemcpy2DAsync(P_out[i], K * 8, bs.cl[i].P.p, Kp * 8, K * 8, K, hipMemcpyDefault, s));
+            }
+    int flag = 0;
+    HIPTRY(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    bool conv = true;
+    for (int i = 0; i < n; ++i) {
+        if (mu_out) mu_out[i] = outs[8 * i];
+        if (outs[8 * i + 3] == 0.0) conv = false;
+    }
+    if (flag) return set_err(c, DM_E_BOUNDS, "batch recursion diverged");
+    if (!conv) return set_err(c, DM_E_NOCONV, "a cluster's mu bisection stopped before the tolerance");
+    return DM_OK;
+}
+
+dm_status dm_batch_get_bounds(dm_ctx* c, int i, double* emin, double* emax) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (i < 0 || i >= (int)c->batch.size()) return set_err(c, DM_E_ARG, "no such batch cluster");
+    if (emin) *emin = c->batch[i].emin;
+    if (emax) *emax = c->batch[i].emax;
+    return DM_OK;
+}
+
+dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, int* best_cfg) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->bstate || c->batch.empty()) return set_err(c, DM_E_STATE, "no batch loaded");
+    if (steps < 2) return set_err(c, DM_E_ARG, "steps must be >= 2");
+    BatchState& bs = *c->bstate;
+    hipStream_t s = c->stream;
+    hipEvent_t e0, e1;
+    HIPTRY(c, hipEventCreate(&e0));
+    HIPTRY(c, hipEventCreate(&e1));
+    std::vector<std::pair<int, double>> res;
+    for (int cfg = 0; cfg < 4; ++cfg) {
+        st = batch_tables(c, cfg, steps);
+        if (st != DM_OK) break;
+        for (size_t i = 0; i < c->batch.size(); ++i) HIPTRY(c, fill_f64(bs.cl[i].coef.p, 0.0, steps + 1, s));
+        HIPTRY(c, batch_start(c, false));
+        HIPTRY(c, fill_i32(bs.counter.p, 0, 4, s));
+        const int grid = batch_grid(c, cfg);
+        BatchArgs a{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p, steps, 0};
+        HIPTRY(c, hipEventRecord(e0, s));
+        HIPTRY(c, cheb_batch(a, cfg, c->precision, grid, s));
+        HIPTRY(c, hipEventRecord(e1, s));
+        HIPTRY(c, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPTRY(c, hipEventElapsedTime(&ms, e0, e1));
+        res.push_back({cfg, ms});
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != DM_OK) return st;
+    int best = 0;
+    for (size_t i = 1; i < res.size(); ++i)
+        if (res[i].second < res[best].second) best = (int)i;
+    bs.cfg = res[best].first;
+    if (best_cfg) *best_cfg = bs.cfg;
+    if (ntable) {
+        if (table)
+            for (int i = 0; i < (int)res.size() && i < *ntable; ++i) {
+                table[4 * i] = res[i].first;
+                table[4 * i + 1] = cheb_tile_rows(res[i].first);
+                table[4 * i + 2] = cheb_tile_cols(res[i].first);
+                table[4 * i + 3] = res[i].second;
+            }
+        *ntable = (int)res.size();
+    }
+    return DM_OK;
+}
+
+}  // extern "C"
+

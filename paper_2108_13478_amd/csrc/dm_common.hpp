@@ -58,6 +58,42 @@ hipError_t cheb_step_f64(const ChebStepArgs& a, int cfg, hipStream_t s);
 hipError_t cheb_step_f32(const ChebStepArgs& a, int cfg, hipStream_t s);
 int cheb_num_tiles(int Kp, int Bp, int cfg);
 
+// Persistent batch recursion.  Each workgroup repeatedly takes the next work
+// item (cluster, column block) from an atomic counter and runs all `order`
+// steps of that block by itself (row tile after row tile, one workgroup
+// barrier between steps), so no workgroup ever waits for another.  Items
+// are listed longest first.  Per cluster: U_a holds U_0 on entry; U_a, U_b
+// alternate (U_{l+1} overwrites U_{l-1}); with_P adds coef[l] U_l to P;
+// partial[l * nblocks + block] receives the block's moment sum of step l.
+struct BatchCluster {
+    int Kp, Bp, nblocks;
+    const void* HN;
+    void* Ua;
+    void* Ub;
+    double* P;
+    const double* Z;
+    const double* coef;
+    double* partial;
+};
+struct BatchItem {
+    int cluster, block;
+};
+struct BatchArgs {
+    const BatchCluster* clusters;
+    const BatchItem* items;
+    int n_items;
+    int* counter;
+    int order;
+    int with_P;
+};
+hipError_t cheb_batch(const BatchArgs& a, int cfg, int precision, int grid, hipStream_t s);
+// Workgroups of tile shape cfg that fit on one CU at once.
+int cheb_batch_occupancy(int cfg, int precision);
+
+// Chebyshev coefficients with mu read from device memory (mu_dev[0]).
+hipError_t cheb_coefficients_devmu(int N, int M, double ebar, double de, const double* mu_dev,
+                                   double beta, double* fk_scratch, double* a, hipStream_t s);
+
 // U0[:, j] = Sinv[:, cols[j]] (rounded to T), Z[:, j] = column cols[j] of S
 // (from its CSR rows; S is symmetric), P[:, j] = coef[0] * Sinv[:, cols[j]],
 // partial[t] = per-tile sums of Z .* U0 for t < ntiles(start).  Columns

@@ -216,6 +216,73 @@ cheb_step_kernel(ChebStepArgs a) {
     }
 }
 
+// ------------------------------------------------------------ persistent batch
+template <typename T, int TM, int TN, int WM, int WN, int KV>
+__global__ void __launch_bounds__(64 * WM * WN)
+cheb_batch_kernel(BatchArgs a) {
+    typedef typename Mfma<T>::vec_t vec_t;
+    constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    __shared__ int item_s;
+    __shared__ double red[WM * WN];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lq = lane >> 4;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = item_s;
+        __syncthreads();
+        if (it >= a.n_items) break;  // every wave of the workgroup leaves together
+        const BatchItem item = a.items[it];
+        const BatchCluster cl = a.clusters[item.cluster];
+        const int Kp = cl.Kp;
+        const T* HN = static_cast<const T*>(cl.HN);
+        T* ua = static_cast<T*>(cl.Ua);
+        T* ub = static_cast<T*>(cl.Ub);
+        const int col0 = item.block * BN + (wave / WM) * TN * 16;
+        for (int l = 1; l <= a.order; ++l) {
+            // odd l: U_{l-1} in ua, U_l -> ub; even l: U_{l-1} in ub, U_l -> ua (over U_{l-2})
+            const T* ucur = (l & 1) ? ua : ub;
+            T* unext = (l & 1) ? ub : ua;
+            const double c = a.with_P ? cl.coef[l] : 0.0;
+            const T alpha = static_cast<T>(l == 1 ? 1.0 : 2.0);
+            double msum = 0.0;
+            for (int r0 = 0; r0 < Kp; r0 += BM) {
+                const int row0 = r0 + (wave % WM) * TM * 16;
+                typename Mfma<T>::acc_t acc[TM][TN];
+                gemm_mainloop<T, TM, TN, KV>(Kp, HN, Kp, ucur, Kp, row0, col0, acc);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        const long idx = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * Kp;
+                        vec_t out = alpha * acc[i][j];
+                        if (l > 1) out -= *reinterpret_cast<const vec_t*>(unext + idx);
+                        *reinterpret_cast<vec_t*>(unext + idx) = out;
+                        const double4_t z = *reinterpret_cast<const double4_t*>(cl.Z + idx);
+                        double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
+                        msum += z[0] * od[0] + z[1] * od[1] + z[2] * od[2] + z[3] * od[3];
+                        if (c != 0.0) {
+                            double4_t* p = reinterpret_cast<double4_t*>(cl.P + idx);
+                            *p = *p + c * od;
+                        }
+                    }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) msum += __shfl_xor(msum, off, 64);
+            if (lane == 0) red[wave] = msum;
+            // also orders this step's U writes before the next step's reads
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double s = 0.0;
+#pragma unroll
+                for (int w = 0; w < WM * WN; ++w) s += red[w];
+                cl.partial[(long)l * cl.nblocks + item.block] = s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 struct CfgShape {
     int tm, tn, wm, wn, kv;
 };
@@ -258,7 +325,43 @@ hipError_t launch_cheb(const ChebStepArgs& a, int cfg, hipStream_t s) {
     }
 }
 
+template <typename T, int TM, int TN, int WM, int WN, int KV>
+hipError_t launch_batch_one(const BatchArgs& a, int grid, hipStream_t s, int* occ) {
+    if (occ) {
+        *occ = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            occ, reinterpret_cast<const void*>(&cheb_batch_kernel<T, TM, TN, WM, WN, KV>), 64 * WM * WN, 0);
+    }
+    hipLaunchKernelGGL((cheb_batch_kernel<T, TM, TN, WM, WN, KV>), dim3(grid), dim3(64 * WM * WN), 0, s, a);
+    return hipGetLastError();
+}
+
+// occ != nullptr: report the occupancy instead of launching
+template <typename T>
+hipError_t launch_batch(const BatchArgs& a, int cfg, int grid, hipStream_t s, int* occ) {
+    switch (cfg) {
+        case 0: return launch_batch_one<T, 4, 4, 2, 2, 4>(a, grid, s, occ);
+        case 1: return launch_batch_one<T, 4, 2, 2, 2, 4>(a, grid, s, occ);
+        case 2: return launch_batch_one<T, 2, 2, 4, 1, 4>(a, grid, s, occ);
+        case 3: return launch_batch_one<T, 2, 2, 2, 2, 4>(a, grid, s, occ);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+hipError_t cheb_batch(const BatchArgs& a, int cfg, int precision, int grid, hipStream_t s) {
+    if (grid < 1) return hipErrorInvalidValue;
+    return precision == 0 ? launch_batch<double>(a, cfg, grid, s, nullptr)
+                          : launch_batch<float>(a, cfg, grid, s, nullptr);
+}
+
+int cheb_batch_occupancy(int cfg, int precision) {
+    int occ = 0;
+    hipError_t e = precision == 0 ? launch_batch<double>(BatchArgs{}, cfg, 1, nullptr, &occ)
+                                  : launch_batch<float>(BatchArgs{}, cfg, 1, nullptr, &occ);
+    return e == hipSuccess ? occ : 0;
+}
 
 int cheb_num_tile_configs() { return (int)(sizeof(kChebCfgs) / sizeof(kChebCfgs[0])); }
 bool cheb_cfg_supports(int cfg, int precision) { return !(kChebCfgs[cfg].kv == 16 && precision == 0); }

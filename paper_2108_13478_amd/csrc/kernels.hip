@@ -232,10 +232,11 @@ __global__ void reduce_moments_kernel(int lmax, int ntiles, const double* __rest
 
 // ------------------------------------------------------------------ coefficients
 // f_k = f_FD(ebar + de cos theta_k), theta_k = pi (k + 1/2) / M
-__global__ void fermi_at_nodes_kernel(int M, double ebar, double de, double mu, double beta,
-                                      double* fk) {
+__global__ void fermi_at_nodes_kernel(int M, double ebar, double de, double mu, const double* mu_dev,
+                                      double beta, double* fk) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
+    if (mu_dev) mu = mu_dev[0];
     const double th = kPi * (k + 0.5) / M;
     fk[k] = fermi_dirac(ebar + de * cos(th), mu, beta);
 }
@@ -508,7 +509,15 @@ hipError_t reduce_moments(int lmax, int ntiles, const double* partial, double* m
 hipError_t cheb_coefficients(int N, int M, double ebar, double de, double mu, double beta,
                              double* fk_scratch, double* a, hipStream_t s) {
     hipLaunchKernelGGL(fermi_at_nodes_kernel, dim3((M + 255) / 256), dim3(256), 0, s, M, ebar, de,
-                       mu, beta, fk_scratch);
+                       mu, (const double*)nullptr, beta, fk_scratch);
+    hipLaunchKernelGGL(dct_coefficients_kernel, dim3(N + 1), dim3(256), 0, s, N, M, fk_scratch, a);
+    return hipGetLastError();
+}
+
+hipError_t cheb_coefficients_devmu(int N, int M, double ebar, double de, const double* mu_dev,
+                                   double beta, double* fk_scratch, double* a, hipStream_t s) {
+    hipLaunchKernelGGL(fermi_at_nodes_kernel, dim3((M + 255) / 256), dim3(256), 0, s, M, ebar, de,
+                       0.0, mu_dev, beta, fk_scratch);
     hipLaunchKernelGGL(dct_coefficients_kernel, dim3(N + 1), dim3(256), 0, s, N, M, fk_scratch, a);
     return hipGetLastError();
 }

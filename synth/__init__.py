@@ -13,6 +13,7 @@ from .clusters import (  # noqa: F401
     WORKLOADS,
     batch_cluster_sizes,
     cube_sites,
+    make_batch,
     make_cluster,
     rademacher,
     s_gaussian_pair_integrals,

@@ -209,6 +209,22 @@ def batch_cluster_sizes(n_clusters: int = 64, lo: int = 125, hi: int = 1000, see
     return np.random.default_rng(seed).integers(lo, hi + 1, size=n_clusters)
 
 
+def _make_one(args):
+    n, seed = args
+    return make_cluster(int(n), seed=int(seed), geometry="sphere")
+
+
+def make_batch(sizes, seeds, processes: int = 8):
+    """Clusters of the given atom counts and seeds (spheres), built in parallel."""
+    import concurrent.futures
+
+    jobs = list(zip(sizes, seeds))
+    if processes <= 1 or len(jobs) < 4:
+        return [_make_one(j) for j in jobs]
+    with concurrent.futures.ProcessPoolExecutor(max_workers=processes) as ex:
+        return list(ex.map(_make_one, jobs))
+
+
 # Workloads with the shapes of the paper's scaling systems (silicon
 # nanocrystals and water clusters of a few thousand to ~10^5 basis functions).
 # beta in 1/hartree; order = number of Chebyshev terms N.

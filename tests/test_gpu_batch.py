@@ -1,0 +1,125 @@
+"""Batch of uneven clusters through one persistent, graph-captured launch
+sequence (dm_batch_*), against the oracle and against the single-cluster path.
+
+Per cluster c the batch finds mu_c with g Tr[P_c S_c] = N_e,c (eq. Ne) from
+exact moments, then forms every column of P_c = p_N(S_c^-1 F_c) S_c^-1."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2108_13478_amd as dmlib
+from synth import batch_cluster_sizes, make_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_batch(ctx, clusters, N, beta, tol, flags=0):
+    P = [np.zeros(c.K * c.K) for c in clusters]
+    mu = ctx.dm_batch_run(N, beta, [c.n_electrons for c in clusters], tol=tol, P_out=P, flags=flags)
+    return mu, [p.reshape(c.K, c.K).T for p, c in zip(P, clusters)]
+
+
+def test_fp64_batch_matches_oracle():
+    sizes = batch_cluster_sizes(6, lo=25, hi=150, seed=3)  # K = 100 .. 600
+    clusters = make_batch(sizes, range(100, 106), processes=1)
+    say(f"case: FP64 batch K = {[c.K for c in clusters]}")
+    ctx = dmlib.Context(precision=dmlib.DM_FP64)
+    ctx.dm_batch_set_focks(clusters)
+    N, beta = 200, 20.0
+    mu, P = run_batch(ctx, clusters, N, beta, tol=1e-9)
+    for i, c in enumerate(clusters):
+        sp = O.spectrum(c)
+        lo, hi = ctx.dm_batch_get_bounds(i)
+        assert lo <= sp.e[0] and hi >= sp.e[-1]
+        tr = O.trace_poly(sp, N, mu[i], beta, lo, hi)[0]
+        ref = O.density_matrix_poly(sp, np.arange(c.K), N, mu[i], beta, lo, hi)
+        err = np.abs(P[i] - ref).max()
+        say(f"  cluster {i} K={c.K}: mu={mu[i]:.9f} 2Tr-N_e={2 * tr - c.n_electrons:.2e} max|dP|={err:.2e}")
+        assert abs(2.0 * tr - c.n_electrons) < 1e-7
+        assert err <= 1e-9
+
+
+def test_graph_replays_match_eager_run():
+    import torch
+
+    sizes = batch_cluster_sizes(5, lo=40, hi=200, seed=4)
+    clusters = make_batch(sizes, range(200, 205), processes=1)
+    say(f"case: graph replay K = {[c.K for c in clusters]}")
+    ctx = dmlib.Context(precision=dmlib.DM_FP32)
+    ctx.dm_batch_set_focks(clusters)
+    N, beta = 120, 30.0
+    mu_e, P_e = run_batch(ctx, clusters, N, beta, tol=1e-6, flags=dmlib.DM_BATCH_EAGER)
+    for rep in range(3):
+        # eager work of the program between replays
+        x = torch.randn(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert torch.isfinite(x.sum())
+        mu_g, P_g = run_batch(ctx, clusters, N, beta, tol=1e-6)
+        assert np.array_equal(mu_g, mu_e)
+        for a, b in zip(P_g, P_e):
+            assert np.array_equal(a, b)
+        say(f"  replay {rep}: identical to the eager run")
+
+
+def test_batch64_fp32_full_configuration():
+    """64 clusters, K uniform in [500, 4000], beta 100, order 400, FP32
+    recursion with FP64 P and moments, tile shape from the batch autotuner."""
+    import torch
+
+    sizes = batch_cluster_sizes()
+    t0 = time.perf_counter()
+    clusters = make_batch(sizes, range(64))
+    Ks = np.array([c.K for c in clusters])
+    say(f"case: batch of 64, K in [{Ks.min()}, {Ks.max()}], sum K = {Ks.sum()}, inputs {time.perf_counter() - t0:.1f} s")
+    ctx = dmlib.Context(precision=dmlib.DM_FP32)
+    t0 = time.perf_counter()
+    ctx.dm_batch_set_focks(clusters)
+    say(f"  setup of 64 operators {time.perf_counter() - t0:.1f} s")
+    best, table = ctx.dm_batch_autotune(steps=8)
+    for row in table:
+        say(f"  tune tile {int(row[1])}x{int(row[2])}: {row[3]:.2f} ms for 8 steps")
+    say(f"  chosen cfg {best}")
+    N, beta = 400, 100.0
+    ne = [c.n_electrons for c in clusters]
+    P = [torch.empty(c.K * c.K, dtype=torch.float64, device="cuda") for c in clusters]
+    mu = ctx.dm_batch_run(N, beta, ne, tol=1e-6, P_out=P)  # captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mu2 = ctx.dm_batch_run(N, beta, ne, tol=1e-6, P_out=P)  # replay
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    say(f"  replay: {dt:.2f} s for {Ks.sum()} columns (two passes) = {Ks.sum() / dt:.0f} columns/s")
+    assert np.array_equal(mu, mu2)
+    # the single-cluster path at the same mu gives the same P
+    j = int(np.argmax(Ks))
+    c = clusters[j]
+    one = dmlib.Context(precision=dmlib.DM_FP32)
+    one.set_cluster(c)
+    assert one.dm_get_bounds() == ctx.dm_batch_get_bounds(j)
+    P1 = np.zeros((c.K, c.K))
+    one.dm_chebyshev_block(np.arange(c.K, dtype=np.int64), N, mu[j], beta, P1)
+    Pb = P[j].cpu().numpy().reshape(c.K, c.K)
+    d = np.abs(P1 - Pb).max()
+    say(f"  largest cluster K={c.K}: batch vs single-cluster path max|dP| = {d:.3e}")
+    assert d <= 1e-12 * np.abs(P1).max()
+    # sampled clusters against the oracle (FP32 recursion error is reported)
+    for i in sorted({int(np.argmin(Ks)), j, 10, 40}):
+        c = clusters[i]
+        sp = O.spectrum(c)
+        lo, hi = ctx.dm_batch_get_bounds(i)
+        ref = O.density_matrix_poly(sp, np.arange(c.K), N, mu[i], beta, lo, hi)
+        Pi = P[i].cpu().numpy().reshape(c.K, c.K).T
+        err = np.abs(Pi - ref).max()
+        ne_err = 2.0 * O.trace_poly(sp, N, mu[i], beta, lo, hi)[0] - c.n_electrons
+        say(f"  cluster {i} K={c.K}: FP32 max|dP| = {err:.2e} (max|P| {np.abs(ref).max():.1f}), "
+            f"oracle 2Tr - N_e at mu = {ne_err:.2e}")
+        assert err < 1e-4 * np.abs(ref).max()
+        assert abs(ne_err) < 1e-3 * c.n_electrons
