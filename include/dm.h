@@ -184,7 +184,15 @@ dm_status dm_batch_set_focks(dm_ctx* ctx, int n, const dm_csr_pair* clusters);
 /* Lanczos interval [Emin, Emax] of batch cluster i. */
 dm_status dm_batch_get_bounds(dm_ctx* ctx, int i, double* emin, double* emax);
 
-enum { DM_BATCH_EAGER = 1 };
+/* flags of dm_batch_run: launch without the graph; stop after the moments
+ * pass and the mu bisection (no P pass, P_out ignored) */
+enum { DM_BATCH_EAGER = 1, DM_BATCH_MOMENTS_ONLY = 2 };
+
+/* Stochastic moments (as dm_stoch_moments) of every batch cluster: xi[c] is
+ * cluster c's K_c x n_vec probe block (host or device, column-major);
+ * m_out (host) receives n x n_mom values, cluster-major. */
+dm_status dm_batch_stoch_moments(dm_ctx* ctx, int n_mom, int n_vec, const double* const* xi,
+                                 double* m_out);
 
 /* Full density matrices of every cluster: first a moments-only pass over all
  * columns of all clusters (one persistent launch: workgroups take
@@ -206,6 +214,44 @@ dm_status dm_batch_run(dm_ctx* ctx, int order, double beta, const double* n_e, d
  * moments pass for each candidate shape on the loaded batch and keep the
  * fastest.  table rows: (cfg, tile rows, tile cols, ms). */
 dm_status dm_batch_autotune(dm_ctx* ctx, int steps, double* table, int* ntable, int* best_cfg);
+
+/* Smallest expansion order N <= max_order whose coefficient tail
+ * sum_{l >= N} |a_l| (coefficients of f_FD(.; mu, beta) on [emin, emax],
+ * supplement "Chebyshev expansion") is at most tol; bounds the error of
+ * the truncated polynomial on the interval.  *order = max_order + 1 when even
+ * max_order terms do not reach tol.  No operator needs to be loaded. */
+dm_status dm_cheb_order(dm_ctx* ctx, double emin, double emax, double mu, double beta, double tol,
+                        int max_order, int* order);
+
+/* ---------------------------------------------------------------- predictor
+ * A small multilayer perceptron: n_layers affine maps sizes[j] -> sizes[j+1]
+ * with tanh between them and a linear output, FP32 weights, mean-squared
+ * error, Adam (b1 0.9, b2 0.999, eps 1e-8).  Weights W_j (sizes[j+1] x
+ * sizes[j], row-major) and biases b_j are stored flat as W_0, b_0, W_1, ...
+ * Inputs X and targets T are row-major (batch x features), host or device. */
+dm_status dm_mlp_init(dm_ctx* ctx, int n_layers, const int* sizes, unsigned long long seed);
+dm_status dm_mlp_num_params(dm_ctx* ctx, long long* n);
+dm_status dm_mlp_get_params(dm_ctx* ctx, float* out);
+dm_status dm_mlp_set_params(dm_ctx* ctx, const float* in);
+dm_status dm_mlp_forward(dm_ctx* ctx, const float* X, int batch, float* Y);
+/* loss = mean (Y - T)^2 and its gradient with respect to every parameter
+ * (layout of the parameters); either output may be NULL */
+dm_status dm_mlp_gradients(dm_ctx* ctx, const float* X, const float* T, int batch, float* loss,
+                           float* grads);
+dm_status dm_mlp_train_step(dm_ctx* ctx, const float* X, const float* T, int batch, float lr,
+                            float* loss);
+/* Input row for one problem from n_mom stochastic moments m~ (host or device):
+ * x = (m~_l / K for l < n_mom, Ebar/dE, log10 dE, log10(beta dE)/4,
+ *      4 n_e/(g K) - 2), n_mom + 4 floats (host or device). */
+dm_status dm_mlp_features(dm_ctx* ctx, const double* m_stoch, int n_mom, double emin, double emax,
+                          double beta, double n_e, long long K, float* x);
+/* mu and expansion order for the loaded operator from its stochastic
+ * moments: features as dm_mlp_features with the operator's interval, one
+ * forward pass (network n_mom + 4 -> ... -> 2), decoded as
+ * mu = Ebar + dE y_0 / 10 and order = round(2^(10 (y_1 + 1))), clamped to
+ * [16, max_order]. */
+dm_status dm_mlp_predict(dm_ctx* ctx, const double* m_stoch, int n_mom, double beta, double n_e,
+                         int max_order, double* mu, int* order);
 
 /* Stochastic moments (1/n_vec) sum_s xi_s^T T_l(H_N) xi_s, l < n_mom, with
  * caller-supplied probe vectors xi (host or device, K x n_vec column-major

@@ -28,7 +28,9 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_get_bounds", "dm_set_bounds", "dm_get_operator", "dm_set_precision", "dm_chebyshev_block",
             "dm_trace", "dm_solve_mu", "dm_moments", "dm_reset_moments", "dm_stoch_moments",
             "dm_autotune", "dm_batch_set_focks", "dm_batch_get_bounds", "dm_batch_run",
-            "dm_batch_autotune"]
+            "dm_batch_autotune", "dm_batch_stoch_moments", "dm_cheb_order", "dm_mlp_init",
+            "dm_mlp_num_params", "dm_mlp_get_params", "dm_mlp_set_params", "dm_mlp_forward",
+            "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict"]
 
 
 class DMError(RuntimeError):
@@ -38,6 +40,7 @@ class DMError(RuntimeError):
 
 
 DM_BATCH_EAGER = 1
+DM_BATCH_MOMENTS_ONLY = 2
 
 
 class dm_csr_pair(ctypes.Structure):
@@ -79,6 +82,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is missing: build it with python -m paper_2108_13478_amd.build")
+    # PyTorch ships its own HIP runtime with the same soname (libamdhip64.so.7)
+    # as the one libdm.so links.  Loading torch first makes libdm bind to that
+    # runtime, so torch tensors, torch streams and libdm share one runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     sig = {
         "dm_default_options": (None, [_P]),
@@ -101,6 +111,17 @@ def load(path: str = LIB_PATH):
         "dm_batch_get_bounds": (_I, [_P, _I, _P, _P]),
         "dm_batch_run": (_I, [_P, _I, _D, _P, _D, _P, _P, _I]),
         "dm_batch_autotune": (_I, [_P, _I, _P, _P, _P]),
+        "dm_batch_stoch_moments": (_I, [_P, _I, _I, _P, _P]),
+        "dm_cheb_order": (_I, [_P, _D, _D, _D, _D, _D, _I, _P]),
+        "dm_mlp_init": (_I, [_P, _I, _P, ctypes.c_ulonglong]),
+        "dm_mlp_num_params": (_I, [_P, _P]),
+        "dm_mlp_get_params": (_I, [_P, _P]),
+        "dm_mlp_set_params": (_I, [_P, _P]),
+        "dm_mlp_forward": (_I, [_P, _P, _I, _P]),
+        "dm_mlp_gradients": (_I, [_P, _P, _P, _I, _P, _P]),
+        "dm_mlp_train_step": (_I, [_P, _P, _P, _I, ctypes.c_float, _P]),
+        "dm_mlp_features": (_I, [_P, _P, _I, _D, _D, _D, _D, _LL, _P]),
+        "dm_mlp_predict": (_I, [_P, _P, _I, _D, _D, _I, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -300,3 +321,78 @@ class Context:
         self._check(self._lib.dm_batch_autotune(self.h, int(steps), ctypes.c_void_p(table.ctypes.data),
                                                 ctypes.byref(n), ctypes.byref(best)))
         return best.value, table[:n.value].copy()
+
+    def dm_batch_stoch_moments(self, n_mom, xis):
+        """xis: list of K_c x n_vec probe blocks (numpy); returns n x n_mom."""
+        n = len(xis)
+        n_vec = int(xis[0].shape[1])
+        keep = [np.ascontiguousarray(np.asarray(x, dtype=np.float64).T) for x in xis]
+        arr = (ctypes.c_void_p * n)(*[k.ctypes.data for k in keep])
+        m = np.zeros((n, n_mom), dtype=np.float64)
+        self._check(self._lib.dm_batch_stoch_moments(self.h, int(n_mom), n_vec, arr,
+                                                     ctypes.c_void_p(m.ctypes.data)))
+        return m
+
+    def dm_cheb_order(self, emin, emax, mu, beta, tol, max_order):
+        o = ctypes.c_int()
+        self._check(self._lib.dm_cheb_order(self.h, float(emin), float(emax), float(mu), float(beta),
+                                            float(tol), int(max_order), ctypes.byref(o)))
+        return o.value
+
+    # ---------------------------------------------------------------- predictor
+    def dm_mlp_init(self, sizes, seed=0):
+        arr = (ctypes.c_int * len(sizes))(*[int(x) for x in sizes])
+        self._check(self._lib.dm_mlp_init(self.h, len(sizes) - 1, arr, int(seed)))
+        self.mlp_sizes = list(sizes)
+
+    def dm_mlp_num_params(self):
+        n = ctypes.c_longlong()
+        self._check(self._lib.dm_mlp_num_params(self.h, ctypes.byref(n)))
+        return n.value
+
+    def dm_mlp_get_params(self):
+        out = np.zeros(self.dm_mlp_num_params(), dtype=np.float32)
+        self._check(self._lib.dm_mlp_get_params(self.h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def dm_mlp_set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(self._lib.dm_mlp_set_params(self.h, ctypes.c_void_p(a.ctypes.data)))
+
+    def dm_mlp_forward(self, X):
+        xp, xk = _ptr(X, np.float32) if not hasattr(X, "data_ptr") else (ctypes.c_void_p(X.data_ptr()), X)
+        B = int(X.shape[0])
+        Y = np.zeros((B, self.mlp_sizes[-1]), dtype=np.float32)
+        self._check(self._lib.dm_mlp_forward(self.h, xp, B, ctypes.c_void_p(Y.ctypes.data)))
+        return Y
+
+    def dm_mlp_gradients(self, X, T):
+        xa = np.ascontiguousarray(X, dtype=np.float32)
+        ta = np.ascontiguousarray(T, dtype=np.float32)
+        loss = ctypes.c_float()
+        g = np.zeros(self.dm_mlp_num_params(), dtype=np.float32)
+        self._check(self._lib.dm_mlp_gradients(self.h, ctypes.c_void_p(xa.ctypes.data), ctypes.c_void_p(ta.ctypes.data),
+                                               int(xa.shape[0]), ctypes.byref(loss), ctypes.c_void_p(g.ctypes.data)))
+        return loss.value, g
+
+    def dm_mlp_train_step(self, X, T, lr):
+        """X, T: contiguous float32 (numpy, or torch tensors on the GPU)."""
+        xp, xk = (ctypes.c_void_p(X.data_ptr()), X) if hasattr(X, "data_ptr") else _ptr(X, np.float32)
+        tp, tk = (ctypes.c_void_p(T.data_ptr()), T) if hasattr(T, "data_ptr") else _ptr(T, np.float32)
+        loss = ctypes.c_float()
+        self._check(self._lib.dm_mlp_train_step(self.h, xp, tp, int(X.shape[0]), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def dm_mlp_features(self, m_stoch, emin, emax, beta, n_e, K):
+        m = np.ascontiguousarray(m_stoch, dtype=np.float64)
+        x = np.zeros(len(m) + 4, dtype=np.float32)
+        self._check(self._lib.dm_mlp_features(self.h, ctypes.c_void_p(m.ctypes.data), len(m), float(emin), float(emax),
+                                              float(beta), float(n_e), int(K), ctypes.c_void_p(x.ctypes.data)))
+        return x
+
+    def dm_mlp_predict(self, m_stoch, beta, n_e, max_order=8192):
+        m = np.ascontiguousarray(m_stoch, dtype=np.float64)
+        mu, order = ctypes.c_double(), ctypes.c_int()
+        self._check(self._lib.dm_mlp_predict(self.h, ctypes.c_void_p(m.ctypes.data), len(m), float(beta), float(n_e),
+                                             int(max_order), ctypes.byref(mu), ctypes.byref(order)))
+        return mu.value, order.value

@@ -56,6 +56,7 @@ struct Op {
 };
 
 struct BatchState;
+struct MlpState;
 
 struct dm_ctx {
     dm_options opt{};
@@ -71,6 +72,7 @@ struct dm_ctx {
     // batch of independent operators (dm_batch_set_focks)
     std::vector<Op> batch;
     BatchState* bstate = nullptr;
+    MlpState* mlp = nullptr;
 
     // moments
     DevBuf<double> mom;
@@ -109,6 +111,7 @@ struct BatchState {
     hipGraphExec_t exec = nullptr;
     int g_order = -1, g_prec = -1, g_cfg = -1;
     double g_beta = 0, g_tol = 0;
+    bool g_with_P = true;
     std::vector<double> g_ne;
     void drop_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -127,6 +130,23 @@ struct BatchState {
         d_clusters.release();
         d_items.release();
         counter.release();
+    }
+};
+
+// Parameters (one flat FP32 buffer: W_0, b_0, W_1, b_1, ...), gradients,
+// Adam moments and activations of the predictor network.
+struct MlpState {
+    std::vector<int> sizes;
+    std::vector<long> w_off, b_off;
+    long n_params = 0;
+    int t = 0;
+    DevBuf<float> params, grads, m, v;
+    DevBuf<float> acts;  // H_0 (input) .. H_{L-1}, then Y: B x sizes[j] each
+    std::vector<long> act_off;
+    DevBuf<float> T, G0, G1, partial, loss;
+    int cap_B = 0;
+    ~MlpState() {
+        for (auto* b : {&params, &grads, &m, &v, &acts, &T, &G0, &G1, &partial, &loss}) b->release();
     }
 };
 
@@ -609,6 +629,7 @@ void dm_destroy(dm_ctx* c) {
     c->op.release();
     for (auto& o : c->batch) o.release();
     delete c->bstate;
+    delete c->mlp;
     c->flag.release();
     c->cols.release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -999,14 +1020,39 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
     return DM_OK;
 }
 
+namespace {
+dm_status stoch_moments_op(dm_ctx* c, Op& op, int n_mom, int n_vec, const double* xi, double* m_out);
+}
+
 dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, double* m_out) {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
     if (n_mom < 1 || n_vec < 1 || !xi || !m_out) return set_err(c, DM_E_ARG, "bad stochastic-moment arguments");
+    return stoch_moments_op(c, c->op, n_mom, n_vec, xi, m_out);
+}
+
+dm_status dm_batch_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* const* xi, double* m_out) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (c->batch.empty()) return set_err(c, DM_E_STATE, "no batch loaded");
+    if (n_mom < 1 || n_vec < 1 || !xi || !m_out) return set_err(c, DM_E_ARG, "bad stochastic-moment arguments");
+    for (size_t i = 0; i < c->batch.size(); ++i) {
+        if (!xi[i]) return set_err(c, DM_E_ARG, "null probe block");
+        st = stoch_moments_op(c, c->batch[i], n_mom, n_vec, xi[i], m_out + i * (size_t)n_mom);
+        if (st != DM_OK) return st;
+    }
+    return DM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+dm_status stoch_moments_op(dm_ctx* c, Op& op, int n_mom, int n_vec, const double* xi, double* m_out) {
     hipStream_t s = c->stream;
-    const int K = (int)c->op.K, Kp = c->op.Kp;
+    const int K = (int)op.K, Kp = op.Kp;
     const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
     const int cfg = pick_cfg(Kp, n_vec);
     const int BN = cheb_tile_cols(cfg);
@@ -1043,7 +1089,7 @@ dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, do
     ChebStepArgs a{};
     a.Kp = Kp;
     a.Bp = Bp;
-    a.HN = c->op.HNbuf.p;
+    a.HN = op.HNbuf.p;
     a.coef = cz.p;
     a.P = Pd.p;
     a.Z = Zs.p;
@@ -1065,6 +1111,9 @@ dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, do
     rel();
     return DM_OK;
 }
+}  // namespace
+
+extern "C" {
 
 }  // extern "C"
 
@@ -1167,7 +1216,7 @@ hipError_t batch_start(dm_ctx* c, bool zero_moments) {
 
 // The whole batch sequence on c->stream (also recorded under graph capture).
 hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<double>& ne, double tol,
-                         int grid) {
+                         int grid, bool with_P) {
     BatchState& bs = *c->bstate;
     hipStream_t s = c->stream;
     const int n = (int)c->batch.size();
@@ -1198,6 +1247,7 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
                      b.out.p, s));
         BQ(cheb_coefficients_devmu(order, M, ebar, de, b.out.p, beta, b.fk.p, b.coef.p, s));
     }
+    if (!with_P) return hipSuccess;
     // pass 2: P at mu_c
     BQ(batch_start(c, false));
     BatchArgs a2{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p + 1, order, 1};
@@ -1263,16 +1313,18 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
     st = batch_tables(c, bs.cfg, order);
     if (st != DM_OK) return st;
     const int grid = batch_grid(c, bs.cfg);
+    const bool with_P = !(flags & DM_BATCH_MOMENTS_ONLY);
     hipStream_t s = c->stream;
     if (flags & DM_BATCH_EAGER) {
-        HIPTRY(c, batch_enqueue(c, order, beta, ne, tol, grid));
+        HIPTRY(c, batch_enqueue(c, order, beta, ne, tol, grid, with_P));
     } else {
         const bool same = bs.exec && bs.g_order == order && bs.g_beta == beta && bs.g_tol == tol &&
-                          bs.g_prec == c->precision && bs.g_cfg == bs.cfg && bs.g_ne == ne;
+                          bs.g_prec == c->precision && bs.g_cfg == bs.cfg && bs.g_ne == ne &&
+                          bs.g_with_P == with_P;
         if (!same) {
             bs.drop_graph();
             HIPTRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            const hipError_t e1 = batch_enqueue(c, order, beta, ne, tol, grid);
+            const hipError_t e1 = batch_enqueue(c, order, beta, ne, tol, grid, with_P);
             hipGraph_t g = nullptr;
             const hipError_t e2 = hipStreamEndCapture(s, &g);
             if (e1 != hipSuccess) {
@@ -1288,13 +1340,14 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
             bs.g_prec = c->precision;
             bs.g_cfg = bs.cfg;
             bs.g_ne = ne;
+            bs.g_with_P = with_P;
         }
         HIPTRY(c, hipGraphLaunch(bs.exec, s));
     }
     std::vector<double> outs((size_t)n * 8);
     for (int i = 0; i < n; ++i)
         HIPTRY(c, hipMemcpyAsync(outs.data() + 8 * i, bs.cl[i].out.p, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (P_out)
+    if (P_out && with_P)
         for (int i = 0; i < n; ++i)
             if (P_out[i]) {
                 const size_t K = (size_t)c->batch[i].K, Kp = (size_t)c->batch[i].Kp;
@@ -1374,3 +1427,275 @@ dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, in
 
 }  // extern "C"
 
+// --------------------------------------------------------------------- MLP
+namespace {
+
+dm_status mlp_reserve(dm_ctx* c, int B) {
+    MlpState& M = *c->mlp;
+    if (B <= M.cap_B) return DM_OK;
+    const int L = (int)M.sizes.size() - 1;
+    M.act_off.assign(L + 2, 0);
+    long tot = 0;
+    int wmax = 0;
+    for (int j = 0; j <= L; ++j) {
+        M.act_off[j] = tot;
+        tot += (long)B * M.sizes[j];
+        wmax = std::max(wmax, M.sizes[j]);
+    }
+    M.act_off[L + 1] = tot;
+    HIPTRY(c, ensure(M.acts, (size_t)tot));
+    HIPTRY(c, ensure(M.T, (size_t)B * M.sizes[L]));
+    HIPTRY(c, ensure(M.G0, (size_t)B * wmax));
+    HIPTRY(c, ensure(M.G1, (size_t)B * wmax));
+    HIPTRY(c, ensure(M.partial, (size_t)(B * M.sizes[L] + 255) / 256 + 1));
+    HIPTRY(c, ensure(M.loss, 1));
+    M.cap_B = B;
+    return DM_OK;
+}
+
+// forward pass of B rows of X (host or device) into the activation buffers
+dm_status mlp_fwd(dm_ctx* c, const float* X, int B) {
+    MlpState& M = *c->mlp;
+    dm_status st = mlp_reserve(c, B);
+    if (st != DM_OK) return st;
+    hipStream_t s = c->stream;
+    const int L = (int)M.sizes.size() - 1;
+    HIPTRY(c, hipMemcpyAsync(M.acts.p, X, (size_t)B * M.sizes[0] * 4, hipMemcpyDefault, s));
+    for (int j = 0; j < L; ++j)
+        HIPTRY(c, mlp_linear_fwd(B, M.sizes[j], M.sizes[j + 1], M.acts.p + M.act_off[j],
+                                 M.params.p + M.w_off[j], M.params.p + M.b_off[j], j < L - 1,
+                                 M.acts.p + M.act_off[j + 1], s));
+    return DM_OK;
+}
+
+// loss and gradients of the batch (X, T) into M.grads
+dm_status mlp_grad(dm_ctx* c, const float* X, const float* T, int B) {
+    MlpState& M = *c->mlp;
+    dm_status st = mlp_fwd(c, X, B);
+    if (st != DM_OK) return st;
+    hipStream_t s = c->stream;
+    const int L = (int)M.sizes.size() - 1;
+    const int nout = M.sizes[L];
+    HIPTRY(c, hipMemcpyAsync(M.T.p, T, (size_t)B * nout * 4, hipMemcpyDefault, s));
+    HIPTRY(c, mlp_mse_grad(B * nout, M.acts.p + M.act_off[L], M.T.p, M.G0.p, M.partial.p, M.loss.p, s));
+    float* G = M.G0.p;
+    float* Gn = M.G1.p;
+    for (int j = L - 1; j >= 0; --j) {
+        HIPTRY(c, mlp_linear_bwd(B, M.sizes[j], M.sizes[j + 1], G, M.acts.p + M.act_off[j],
+                                 M.params.p + M.w_off[j], M.grads.p + M.w_off[j], M.grads.p + M.b_off[j],
+                                 j > 0 ? Gn : nullptr, s));
+        std::swap(G, Gn);
+    }
+    return DM_OK;
+}
+
+dm_status mlp_ready(dm_ctx* c) {
+    if (!c->mlp) return set_err(c, DM_E_STATE, "no network: call dm_mlp_init first");
+    return DM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dm_status dm_mlp_init(dm_ctx* c, int n_layers, const int* sizes, unsigned long long seed) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (n_layers < 1 || n_layers > 16 || !sizes) return set_err(c, DM_E_ARG, "need 1..16 layers");
+    for (int j = 0; j <= n_layers; ++j)
+        if (sizes[j] < 1 || sizes[j] > 4096) return set_err(c, DM_E_ARG, "layer width out of range");
+    delete c->mlp;
+    c->mlp = new MlpState();
+    MlpState& M = *c->mlp;
+    M.sizes.assign(sizes, sizes + n_layers + 1);
+    long off = 0;
+    for (int j = 0; j < n_layers; ++j) {
+        M.w_off.push_back(off);
+        off += (long)sizes[j] * sizes[j + 1];
+        M.b_off.push_back(off);
+        off += sizes[j + 1];
+    }
+    M.n_params = off;
+    HIPTRY(c, ensure(M.params, (size_t)off));
+    HIPTRY(c, ensure(M.grads, (size_t)off));
+    HIPTRY(c, ensure(M.m, (size_t)off));
+    HIPTRY(c, ensure(M.v, (size_t)off));
+    for (int j = 0; j < n_layers; ++j)
+        HIPTRY(c, mlp_init_layer(sizes[j], sizes[j + 1], seed * 1315423911ull + (unsigned long long)j,
+                                 M.params.p + M.w_off[j], M.params.p + M.b_off[j], c->stream));
+    HIPTRY(c, hipMemsetAsync(M.m.p, 0, (size_t)off * 4, c->stream));
+    HIPTRY(c, hipMemsetAsync(M.v.p, 0, (size_t)off * 4, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return DM_OK;
+}
+
+dm_status dm_mlp_num_params(dm_ctx* c, long long* n) {
+    if (!c || !n) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if ((st = mlp_ready(c)) != DM_OK) return st;
+    *n = c->mlp->n_params;
+    return DM_OK;
+}
+
+dm_status dm_mlp_get_params(dm_ctx* c, float* out) {
+    if (!c || !out) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if ((st = mlp_ready(c)) != DM_OK) return st;
+    HIPTRY(c, hipMemcpyAsync(out, c->mlp->params.p, (size_t)c->mlp->n_params * 4, hipMemcpyDefault, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return DM_OK;
+}
+
+dm_status dm_mlp_set_params(dm_ctx* c, const float* in) {
+    if (!c || !in) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if ((st = mlp_ready(c)) != DM_OK) return st;
+    HIPTRY(c, hipMemcpyAsync(c->mlp->params.p, in, (size_t)c->mlp->n_params * 4, hipMemcpyDefault, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    c->mlp->t = 0;
+    HIPTRY(c, hipMemsetAsync(c->mlp->m.p, 0, (size_t)c->mlp->n_params * 4, c->stream));
+    HIPTRY(c, hipMemsetAsync(c->mlp->v.p, 0, (size_t)c->mlp->n_params * 4, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return DM_OK;
+}
+
+dm_status dm_mlp_forward(dm_ctx* c, const float* X, int batch, float* Y) {
+    if (!c || !X || !Y || batch < 1) return c ? set_err(c, DM_E_ARG, "bad forward arguments") : DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if ((st = mlp_ready(c)) != DM_OK) return st;
+    if ((st = mlp_fwd(c, X, batch)) != DM_OK) return st;
+    MlpState& M = *c->mlp;
+    const int L = (int)M.sizes.size() - 1;
+    HIPTRY(c, hipMemcpyAsync(Y, M.acts.p + M.act_off[L], (size_t)batch * M.sizes[L] * 4, hipMemcpyDefault, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return DM_OK;
+}
+
+dm_status dm_mlp_gradients(dm_ctx* c, const float* X, const float* T, int batch, float* loss,
+                           float* grads) {
+    if (!c || !X || !T || batch < 1) return c ? set_err(c, DM_E_ARG, "bad gradient arguments") : DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if ((st = mlp_ready(c)) != DM_OK) return st;
+    if ((st = mlp_grad(c, X, T, batch)) != DM_OK) return st;
+    if (loss) HIPTRY(c, hipMemcpyAsync(loss, c->mlp->loss.p, 4, hipMemcpyDefault, c->stream));
+    if (grads)
+        HIPTRY(c, hipMemcpyAsync(grads, c->mlp->grads.p, (size_t)c->mlp->n_params * 4, hipMemcpyDefault, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return DM_OK;
+}
+
+dm_status dm_mlp_train_step(dm_ctx* c, const float* X, const float* T, int batch, float lr,
+                            float* loss) {
+    if (!c || !X || !T || batch < 1 || !(lr > 0)) return c ? set_err(c, DM_E_ARG, "bad training arguments") : DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if ((st = mlp_ready(c)) != DM_OK) return st;
+    if ((st = mlp_grad(c, X, T, batch)) != DM_OK) return st;
+    MlpState& M = *c->mlp;
+    M.t += 1;
+    HIPTRY(c, mlp_adam(M.n_params, M.params.p, M.grads.p, M.m.p, M.v.p, lr, M.t, c->stream));
+    if (loss) {
+        HIPTRY(c, hipMemcpyAsync(loss, M.loss.p, 4, hipMemcpyDefault, c->stream));
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+    }
+    return DM_OK;
+}
+
+dm_status dm_mlp_features(dm_ctx* c, const double* m_stoch, int n_mom, double emin, double emax,
+                          double beta, double n_e, long long K, float* x) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!m_stoch || !x || n_mom < 1 || n_mom > 1020 || !(emax > emin) || !(beta > 0) || K < 1)
+        return set_err(c, DM_E_ARG, "bad feature arguments");
+    DevBuf<double> md;
+    DevBuf<float> xd;
+    HIPTRY(c, ensure(md, (size_t)n_mom));
+    HIPTRY(c, ensure(xd, (size_t)n_mom + 4));
+    hipError_t e = hipMemcpyAsync(md.p, m_stoch, (size_t)n_mom * 8, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess)
+        e = mlp_features(n_mom, md.p, emin, emax, beta, n_e, c->opt.spin, (double)K, xd.p, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(x, xd.p, (size_t)(n_mom + 4) * 4, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    md.release();
+    xd.release();
+    if (e != hipSuccess) return fail_hip(c, e, "features");
+    return DM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+dm_status dm_cheb_order(dm_ctx* c, double emin, double emax, double mu, double beta, double tol,
+                        int max_order, int* order) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!order || !(emax > emin) || !std::isfinite(mu) || !(beta > 0) || !(tol > 0) || max_order < 2 ||
+        max_order > (1 << 16))
+        return set_err(c, DM_E_ARG, "bad order-estimate arguments");
+    // twice as many coefficients as the cap, so the tail beyond the cap is seen
+    const int n = 2 * max_order, M = 4 * n;
+    DevBuf<double> a, fk;
+    DevBuf<int> o;
+    hipError_t e = ensure(a, (size_t)n + 1);
+    if (e == hipSuccess) e = ensure(fk, (size_t)M);
+    if (e == hipSuccess) e = ensure(o, 1);
+    if (e == hipSuccess)
+        e = cheb_coefficients(n, M, 0.5 * (emax + emin), 0.5 * (emax - emin), mu, beta, fk.p, a.p, c->stream);
+    if (e == hipSuccess) e = coef_tail_order(n, max_order, a.p, tol, o.p, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(order, o.p, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    a.release();
+    fk.release();
+    o.release();
+    if (e != hipSuccess) return fail_hip(c, e, "order estimate");
+    return DM_OK;
+}
+
+dm_status dm_mlp_predict(dm_ctx* c, const double* m_stoch, int n_mom, double beta, double n_e,
+                         int max_order, double* mu, int* order) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if ((st = mlp_ready(c)) != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    MlpState& M = *c->mlp;
+    if (!m_stoch || !mu || !order || n_mom < 1 || M.sizes.front() != n_mom + 4 || M.sizes.back() != 2 ||
+        max_order < 16)
+        return set_err(c, DM_E_ARG, "network shape does not match n_mom + 4 -> 2, or bad arguments");
+    if ((st = mlp_reserve(c, 1)) != DM_OK) return st;
+    DevBuf<double> md;
+    HIPTRY(c, ensure(md, (size_t)n_mom));
+    hipError_t e = hipMemcpyAsync(md.p, m_stoch, (size_t)n_mom * 8, hipMemcpyDefault, c->stream);
+    if (e == hipSuccess)
+        e = mlp_features(n_mom, md.p, c->op.emin, c->op.emax, beta, n_e, c->opt.spin, (double)c->op.K,
+                         M.acts.p, c->stream);
+    if (e != hipSuccess) {
+        md.release();
+        return fail_hip(c, e, "predict features");
+    }
+    const int L = (int)M.sizes.size() - 1;
+    for (int j = 0; j < L && e == hipSuccess; ++j)
+        e = mlp_linear_fwd(1, M.sizes[j], M.sizes[j + 1], M.acts.p + M.act_off[j], M.params.p + M.w_off[j],
+                           M.params.p + M.b_off[j], j < L - 1, M.acts.p + M.act_off[j + 1], c->stream);
+    float y[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(y, M.acts.p + M.act_off[L], 2 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    md.release();
+    if (e != hipSuccess) return fail_hip(c, e, "predict");
+    const double ebar = 0.5 * (c->op.emax + c->op.emin), de = 0.5 * (c->op.emax - c->op.emin);
+    *mu = ebar + de * (double)y[0] / 10.0;
+    const double N = std::pow(2.0, 10.0 * ((double)y[1] + 1.0));
+    *order = (int)std::lround(std::min<double>(std::max<double>(N, 16.0), (double)max_order));
+    return DM_OK;
+}
+
+}  // extern "C"

@@ -118,6 +118,11 @@ hipError_t reduce_moments(int lmax, int ntiles, const double* partial, double* m
 hipError_t cheb_coefficients(int N, int M, double ebar, double de, double mu, double beta,
                              double* fk_scratch, double* a, hipStream_t s);
 
+// order[0] = smallest N with sum_{l >= N} |a_l| <= tol over a[0..n), or
+// max_order + 1 if that N exceeds max_order
+hipError_t coef_tail_order(int n, int max_order, const double* a, double tol, int* order,
+                           hipStream_t s);
+
 // Trace quadrature weights from moments m[0..N] (N terms, m[N] used for the
 // band energy): w_k, v_k for k < M.
 hipError_t trace_weights(int N, int M, double ebar, double de, const double* m, double* w,
@@ -129,6 +134,23 @@ hipError_t trace_weights(int N, int M, double ebar, double de, const double* m, 
 hipError_t mu_bisect(int M, double ebar, double de, double beta, double target, double tol,
                      double lo, double hi, double mu_in, int max_iter, const double* w,
                      const double* v, double* out, hipStream_t s);
+
+// ----------------------------------------------------------------- MLP (FP32)
+hipError_t mlp_linear_fwd(int B, int nin, int nout, const float* X, const float* W, const float* b,
+                          bool use_tanh, float* Y, hipStream_t s);
+// G = d(mean (Y-T)^2)/dY, *loss = mean (Y-T)^2 (partial: (n+255)/256 floats)
+hipError_t mlp_mse_grad(int n, const float* Y, const float* T, float* G, float* partial,
+                        float* loss, hipStream_t s);
+// weight/bias gradients of one layer; Gin (may be null) = input gradient
+// through the tanh that produced H
+hipError_t mlp_linear_bwd(int B, int nin, int nout, const float* G, const float* H, const float* W,
+                          float* dW, float* db, float* Gin, hipStream_t s);
+hipError_t mlp_adam(long n, float* w, const float* g, float* m, float* v, float lr, int t,
+                    hipStream_t s);
+hipError_t mlp_init_layer(int nin, int nout, unsigned long long seed, float* W, float* b,
+                          hipStream_t s);
+hipError_t mlp_features(int n_mom, const double* m, double emin, double emax, double beta,
+                        double n_e, double spin, double K, float* x, hipStream_t s);
 
 // ----------------------------------------------------------------- setup
 hipError_t fill_f64(double* x, double v, long long n, hipStream_t s);

@@ -334,6 +334,23 @@ mu_bisect_kernel(int M, double ebar, double de, double beta, double target, doub
     }
 }
 
+// Smallest N <= max_order with sum_{max_order > l >= N} ... : the coefficient
+// tail sum_{l >= N} |a_l| over the n available coefficients is <= tol;
+// max_order + 1 when the tail at max_order is already above tol.
+__global__ void coef_tail_order_kernel(int n, int max_order, const double* a, double tol, int* order) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double tail = 0.0;
+    int N = 0;
+    for (int l = n - 1; l >= 0; --l) {
+        tail += fabs(a[l]);
+        if (tail > tol) {
+            N = l + 1;
+            break;
+        }
+    }
+    order[0] = N > max_order ? max_order + 1 : N;
+}
+
 // ------------------------------------------------------------------ Lanczos
 __device__ inline unsigned long long splitmix64(unsigned long long x) {
     x += 0x9E3779B97F4A7C15ull;
@@ -533,6 +550,12 @@ hipError_t mu_bisect(int M, double ebar, double de, double beta, double target, 
                      const double* v, double* out, hipStream_t s) {
     hipLaunchKernelGGL(mu_bisect_kernel, dim3(1), dim3(1024), 0, s, M, ebar, de, beta, target, tol,
                        lo, hi, mu_in, max_iter, w, v, out);
+    return hipGetLastError();
+}
+
+hipError_t coef_tail_order(int n, int max_order, const double* a, double tol, int* order,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(coef_tail_order_kernel, dim3(1), dim3(64), 0, s, n, max_order, a, tol, order);
     return hipGetLastError();
 }
 

@@ -11,7 +11,11 @@ structure (atom-centred, non-orthogonal, sparse S and F):
 * S_ab = (2 sqrt(ab)/(a+b))^(3/2) exp(-mu R^2), mu = ab/(a+b)  (textbook
   closed form of the overlap of two normalised s-Gaussians);
 * T_ab = mu (3 - 2 mu R^2) S_ab  (closed form of <g_a| -1/2 lap |g_b>);
-* F = T + diag(eps), eps ~ N(0, 0.5) drawn once per basis function;
+* F = T + diag(eps), eps ~ N(0, 0.5) drawn once per basis function
+  (onsite="diagonal", the default); or, with onsite="scaled", F_ab = T_ab +
+  (eps_a + eps_b) S_ab / 2, the same energies applied through the overlap,
+  which keeps the spectrum of S^-1 F near that of S^-1 T instead of
+  creating near-null-space states with energies of +-1000 hartree;
 * entries with |S_ij| < drop (resp. |F_ij| < drop) are removed from S
   (resp. F) independently; diagonals are always kept.
 
@@ -132,6 +136,7 @@ def make_cluster(
     onsite_sd: float = ONSITE_SD,
     drop: float = DROP,
     n_electrons: float | None = None,
+    onsite: str = "diagonal",
 ) -> Cluster:
     """Build the CSR Fock and overlap matrices of one model cluster.
 
@@ -139,6 +144,9 @@ def make_cluster(
     nearest lattice sites to the origin.  n_electrons defaults to two per
     atom.
     """
+    if onsite not in ("diagonal", "scaled"):
+        raise ValueError(f"unknown onsite mode {onsite!r}")
+    onsite_mode = onsite
     if geometry == "cube":
         n_side = int(round(n_atoms ** (1.0 / 3.0)))
         if n_side ** 3 != n_atoms:
@@ -175,7 +183,10 @@ def make_cluster(
         T = T.ravel()
         same = np.repeat(Ic == Jc, nb * nb)
         diag = r == c
-        T = T + np.where(diag, onsite[r], 0.0)
+        if onsite_mode == "diagonal":
+            T = T + np.where(diag, onsite[r], 0.0)
+        else:
+            T = T + 0.5 * (onsite[r] + onsite[c]) * S
         keepS = (np.abs(S) >= drop) | diag
         keepF = (np.abs(T) >= drop) | diag
         # atom pairs are stored once (i <= j); mirror the off-atom blocks
@@ -210,15 +221,15 @@ def batch_cluster_sizes(n_clusters: int = 64, lo: int = 125, hi: int = 1000, see
 
 
 def _make_one(args):
-    n, seed = args
-    return make_cluster(int(n), seed=int(seed), geometry="sphere")
+    n, seed, onsite = args
+    return make_cluster(int(n), seed=int(seed), geometry="sphere", onsite=onsite)
 
 
-def make_batch(sizes, seeds, processes: int = 8):
+def make_batch(sizes, seeds, processes: int = 8, onsite: str = "diagonal"):
     """Clusters of the given atom counts and seeds (spheres), built in parallel."""
     import concurrent.futures
 
-    jobs = list(zip(sizes, seeds))
+    jobs = [(n, s, onsite) for n, s in zip(sizes, seeds)]
     if processes <= 1 or len(jobs) < 4:
         return [_make_one(j) for j in jobs]
     with concurrent.futures.ProcessPoolExecutor(max_workers=processes) as ex:
