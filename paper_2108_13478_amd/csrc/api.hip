@@ -399,12 +399,13 @@ dm_status reset_moments(dm_ctx* c) {
     return DM_OK;
 }
 
-// Tile shape for a pass when nothing was tuned: among the four standard
-// shapes, the widest tile whose grid still gives every CU two workgroups,
-// else the one with the most workgroups.
+// Tile shape for a pass when nothing was tuned: among the standard shapes
+// (128 x 128 with three slabs in flight, 128 x 64, 128 x 32, 64 x 64), the
+// widest tile whose grid still gives every CU two workgroups, else the one
+// with the most workgroups.
 int pick_cfg(int Kp, int ncols) {
     int best = -1, best_tiles = -1;
-    for (int cfg = 0; cfg < 4; ++cfg) {
+    for (int cfg : {12, 1, 2, 3}) {
         const int BN = cheb_tile_cols(cfg);
         const int Bp = (int)round_up(std::max(ncols, 1), BN);
         if (Bp > round_up(std::max(ncols, 1), 32) && BN > 32) continue;  // padding beyond 32
@@ -920,13 +921,17 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
     const int wmax = (int)std::max<long long>(32, std::min<long long>(ncols, 256));
     struct Cand { int w, cfg; double ms; };
     std::vector<Cand> cands;
-    for (int w : {32, 64, 128, 256}) {
-        if (w > wmax) continue;
+    std::vector<int> widths = {32, 64, 128, 256};
+    // the full pass width as well, when the caller advances more columns
+    const int wfull = (int)std::min<long long>(round_up(ncols, 128), 1 << 14);
+    if (wfull > 256) widths.push_back(wfull);
+    for (int w : widths) {
+        if (w > wmax && w != wfull) continue;
         for (int cfg = 0; cfg < cheb_num_tile_configs(); ++cfg)
             if (w % cheb_tile_cols(cfg) == 0 && cheb_cfg_supports(cfg, c->precision))
                 cands.push_back({w, cfg, 0.0});
     }
-    const int W = 256;
+    const int W = std::max(256, wfull);
     DevBuf<double> U0, U1, Zb, Pb, part, pst, coef;
     DevBuf<long long> colsd;
     auto rel = [&]() { U0.release(); U1.release(); Zb.release(); Pb.release(); part.release(); pst.release(); coef.release(); colsd.release(); };

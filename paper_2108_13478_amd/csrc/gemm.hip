@@ -86,7 +86,7 @@ template <> struct VecOf<double, 8> { typedef double type __attribute__((ext_vec
 template <> struct VecOf<float, 8> { typedef float type __attribute__((ext_vector_type(8))); };
 template <> struct VecOf<float, 16> { typedef float type __attribute__((ext_vector_type(16))); };
 
-template <typename T, int TM, int TN, int KV>
+template <typename T, int TM, int TN, int KV, int DEPTH = 2>
 __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda,
                                      const T* __restrict__ B, long ldb, int row0, int col0,
                                      typename Mfma<T>::acc_t (&acc)[TM][TN]) {
@@ -120,21 +120,42 @@ __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda
 #pragma unroll
                 for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i][s], b[j][s], acc[i][j]);
     };
-    // Kred is a multiple of 2 SLAB (checked by the launchers).  The steady
-    // state has no branch between a load and the MFMAs that follow it, so the
-    // compiler can wait for exactly the older buffer's loads instead of for
-    // every load in flight.
-    load(a0, b0, 0);
-    int k = 0;
-    for (; k < Kred - 2 * SLAB; k += 2 * SLAB) {
+    if constexpr (DEPTH == 2) {
+        // Kred is a multiple of 2 SLAB (checked by the launchers).  The steady
+        // state has no branch between a load and the MFMAs that follow it, so
+        // the compiler can wait for exactly the older buffer's loads instead
+        // of for every load in flight.
+        load(a0, b0, 0);
+        int k = 0;
+        for (; k < Kred - 2 * SLAB; k += 2 * SLAB) {
+            load(a1, b1, k + SLAB);
+            compute(a0, b0);
+            load(a0, b0, k + 2 * SLAB);
+            compute(a1, b1);
+        }
         load(a1, b1, k + SLAB);
         compute(a0, b0);
-        load(a0, b0, k + 2 * SLAB);
         compute(a1, b1);
+    } else {
+        // Ring of four buffers: three slabs stay in flight while one is
+        // consumed (Kred is a multiple of 4 SLAB).  For memory-bound narrow
+        // blocks one slab of MFMA work is far shorter than an HBM round trip.
+        (void)a0; (void)b0; (void)a1; (void)b1;
+        vec_t ra[4][TM], rb[4][TN];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) load(ra[d], rb[d], d * SLAB);
+        int k = 0;
+        for (; k < Kred - 4 * SLAB; k += 4 * SLAB) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                load(ra[(d + 3) & 3], rb[(d + 3) & 3], k + (d + 3) * SLAB);
+                compute(ra[d], rb[d]);
+            }
+        }
+        load(ra[3], rb[3], k + 3 * SLAB);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) compute(ra[d], rb[d]);
     }
-    load(a1, b1, k + SLAB);
-    compute(a0, b0);
-    compute(a1, b1);
 }
 
 // ------------------------------------------------------------ plain product
@@ -166,7 +187,7 @@ gemm_tn_store_kernel(int M, int N, int Kred, double alpha, const double* __restr
 }
 
 // ------------------------------------------------------------ recursion step
-template <typename T, int TM, int TN, int WM, int WN, int KV>
+template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH>
 __global__ void __launch_bounds__(64 * WM * WN)
 cheb_step_kernel(ChebStepArgs a) {
     typedef typename Mfma<T>::vec_t vec_t;
@@ -177,7 +198,7 @@ cheb_step_kernel(ChebStepArgs a) {
     const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
     const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
     typename Mfma<T>::acc_t acc[TM][TN];
-    gemm_mainloop<T, TM, TN, KV>(a.Kp, static_cast<const T*>(a.HN), a.Kp, static_cast<const T*>(a.Ucur),
+    gemm_mainloop<T, TM, TN, KV, DEPTH>(a.Kp, static_cast<const T*>(a.HN), a.Kp, static_cast<const T*>(a.Ucur),
                              a.Kp, row0, col0, acc);
 
     const int lane = threadIdx.x & 63;
@@ -284,28 +305,34 @@ cheb_batch_kernel(BatchArgs a) {
 }
 
 struct CfgShape {
-    int tm, tn, wm, wn, kv;
+    int tm, tn, wm, wn, kv, depth;
 };
 // Tile shapes of the recursion step (rows x columns per workgroup, k per
 // lane and slab).  The first four suit the compute-bound wide blocks; the
 // last three keep more operator bytes in flight for narrow, memory-bound
 // blocks.  KV = 16 is FP32 only.
 constexpr CfgShape kChebCfgs[] = {
-    {4, 4, 2, 2, 4},  // 128 x 128
-    {4, 2, 2, 2, 4},  // 128 x 64
-    {2, 2, 4, 1, 4},  // 128 x 32
-    {2, 2, 2, 2, 4},  // 64 x 64
-    {1, 2, 4, 1, 8},  // 64 x 32, deep
-    {1, 4, 4, 1, 8},  // 64 x 64, deep
-    {1, 2, 4, 1, 16}, // 64 x 32, deeper (FP32)
+    {4, 4, 2, 2, 4, 2},   // 128 x 128
+    {4, 2, 2, 2, 4, 2},   // 128 x 64
+    {2, 2, 4, 1, 4, 2},   // 128 x 32
+    {2, 2, 2, 2, 4, 2},   // 64 x 64
+    {1, 2, 4, 1, 8, 2},   // 64 x 32, 8 k per lane
+    {1, 4, 4, 1, 8, 2},   // 64 x 64, 8 k per lane
+    {1, 2, 4, 1, 16, 2},  // 64 x 32, 16 k per lane (FP32)
+    {2, 2, 4, 1, 4, 4},   // 128 x 32, three slabs in flight
+    {4, 2, 2, 2, 4, 4},   // 128 x 64, three slabs in flight
+    {1, 2, 4, 1, 4, 4},   // 64 x 32, three slabs in flight
+    {4, 2, 2, 4, 4, 2},   // 128 x 128, 8 waves: two waves per SIMD
+    {2, 4, 4, 2, 4, 2},   // 128 x 128, 8 waves, 32 x 64 per wave
+    {4, 4, 2, 2, 4, 4},   // 128 x 128, three slabs in flight
 };
 
-template <typename T, int TM, int TN, int WM, int WN, int KV>
+template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH = 2>
 hipError_t launch_one(const ChebStepArgs& a, hipStream_t s) {
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
-    if (a.Kp % BM || a.Bp % BN || a.Kp % (8 * KV)) return hipErrorInvalidValue;
+    if (a.Kp % BM || a.Bp % BN || a.Kp % (4 * DEPTH * KV)) return hipErrorInvalidValue;
     const dim3 grid((a.Kp / BM) * (a.Bp / BN));
-    hipLaunchKernelGGL((cheb_step_kernel<T, TM, TN, WM, WN, KV>), grid, dim3(64 * WM * WN), 0, s, a);
+    hipLaunchKernelGGL((cheb_step_kernel<T, TM, TN, WM, WN, KV, DEPTH>), grid, dim3(64 * WM * WN), 0, s, a);
     return hipGetLastError();
 }
 
@@ -321,6 +348,12 @@ hipError_t launch_cheb(const ChebStepArgs& a, int cfg, hipStream_t s) {
         case 6:
             if constexpr (sizeof(T) == 4) return launch_one<float, 1, 2, 4, 1, 16>(a, s);
             return hipErrorInvalidValue;
+        case 7: return launch_one<T, 2, 2, 4, 1, 4, 4>(a, s);
+        case 8: return launch_one<T, 4, 2, 2, 2, 4, 4>(a, s);
+        case 9: return launch_one<T, 1, 2, 4, 1, 4, 4>(a, s);
+        case 10: return launch_one<T, 4, 2, 2, 4, 4>(a, s);
+        case 11: return launch_one<T, 2, 4, 4, 2, 4>(a, s);
+        case 12: return launch_one<T, 4, 4, 2, 2, 4, 4>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
