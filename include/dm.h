@@ -151,16 +151,35 @@ dm_status dm_reset_moments(dm_ctx* ctx);
 
 /* Pick the pass width and tile shape of the recursion for this operator and
  * precision by timing `steps` recursion steps of every candidate (widths 32,
- * 64, 128, 256 columns, capped at max(ncols, 32); every tile shape whose
- * column tile divides the width).  The fastest in columns x steps per
- * second is kept in the context and used by dm_chebyshev_block while the
- * block_width option is 0.  table (host, may be NULL) receives up to
- * *ntable rows of (width, tile config, tile rows, tile cols, ms per step,
- * column-steps per second); *ntable returns the number of candidates.
- * Chooses nothing across Fock matrices: dm_set_fock forgets the choice.
- * Errors: DM_E_STATE (no Fock matrix), DM_E_ARG (ncols < 1, steps < 1). */
+ * 64, 128, 256 columns, capped at max(ncols, 32), plus ncols rounded up to
+ * 128 (at most 16384) when that is wider; every tile shape that fits the
+ * width and the operator, split-reduction shapes up to 512 columns).  The
+ * fastest in columns x steps per second is kept in the context and used by
+ * dm_chebyshev_block while the block_width option is 0.  table (host, may
+ * be NULL) receives up to *ntable rows of (width, tile config, tile rows,
+ * tile cols, ms per step, column-steps per second); *ntable returns the
+ * number of candidates.  dm_set_fock and dm_set_precision forget the
+ * choice.  Errors: DM_E_STATE (no Fock matrix), DM_E_ARG (ncols < 1,
+ * steps < 1). */
 dm_status dm_autotune(dm_ctx* ctx, long long ncols, int steps, double* table, int* ntable,
                       int* best_width, int* best_cfg);
+
+/* Pin the pass width (columns advanced together, >= 1; a pass is padded to
+ * the shape's column tile) and tile shape (an index below
+ * dm_num_tile_shapes()) instead of timing them; used by dm_chebyshev_block
+ * while the block_width option is 0.  dm_set_fock and dm_set_precision
+ * forget the choice.  Errors: DM_E_STATE (no Fock matrix), DM_E_ARG
+ * (width < 1, unknown shape, or a shape that does not fit the loaded
+ * operator's padded dimension, this width or the current precision). */
+dm_status dm_set_pass_shape(dm_ctx* ctx, int width, int cfg);
+
+/* Number of compiled recursion tile shapes, and the rows and columns of one
+ * workgroup tile and the number of reduction chunks of shape cfg (split > 1:
+ * the recursion step runs as chunked partial products plus a combine kernel
+ * that applies the epilogue).  Host outputs may be NULL.
+ * Errors: DM_E_ARG (cfg out of range). */
+int dm_num_tile_shapes(void);
+dm_status dm_tile_shape(int cfg, int* rows, int* cols, int* split);
 
 /* ---------------------------------------------------------------- batch
  * Many independent clusters (the paper distributes unit vectors u_a over

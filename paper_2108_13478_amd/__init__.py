@@ -30,7 +30,8 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_autotune", "dm_batch_set_focks", "dm_batch_get_bounds", "dm_batch_run",
             "dm_batch_autotune", "dm_batch_stoch_moments", "dm_cheb_order", "dm_mlp_init",
             "dm_mlp_num_params", "dm_mlp_get_params", "dm_mlp_set_params", "dm_mlp_forward",
-            "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict"]
+            "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict",
+            "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape"]
 
 
 class DMError(RuntimeError):
@@ -107,6 +108,9 @@ def load(path: str = LIB_PATH):
         "dm_reset_moments": (_I, [_P]),
         "dm_stoch_moments": (_I, [_P, _I, _I, _P, _P]),
         "dm_autotune": (_I, [_P, _LL, _I, _P, _P, _P, _P]),
+        "dm_set_pass_shape": (_I, [_P, _I, _I]),
+        "dm_num_tile_shapes": (_I, []),
+        "dm_tile_shape": (_I, [_I, _P, _P, _P]),
         "dm_batch_set_focks": (_I, [_P, _I, _P]),
         "dm_batch_get_bounds": (_I, [_P, _I, _P, _P]),
         "dm_batch_run": (_I, [_P, _I, _D, _P, _D, _P, _P, _I]),
@@ -146,6 +150,18 @@ def _ptr(x, dtype):
         pass
     a = np.ascontiguousarray(x, dtype=dtype)
     return ctypes.c_void_p(a.ctypes.data), a
+
+
+def tile_shapes():
+    """[(rows, cols, split)] of every compiled recursion tile shape, by index."""
+    lib = load()
+    out = []
+    for cfg in range(lib.dm_num_tile_shapes()):
+        r, c, sp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        if lib.dm_tile_shape(cfg, ctypes.byref(r), ctypes.byref(c), ctypes.byref(sp)) != DM_OK:
+            raise DMError(DM_E_ARG, f"tile shape {cfg}")
+        out.append((r.value, c.value, sp.value))
+    return out
 
 
 def _numel(x):
@@ -264,13 +280,16 @@ class Context:
     def dm_autotune(self, ncols, steps=5):
         """Returns (best_width, best_cfg, table) with table rows (width, cfg,
         tile_rows, tile_cols, ms_per_step, column_steps_per_s)."""
-        cap = 64
+        cap = 256
         table = np.zeros((cap, 6), dtype=np.float64)
         n = ctypes.c_int(cap)
         bw, bc = ctypes.c_int(), ctypes.c_int()
         self._check(self._lib.dm_autotune(self.h, int(ncols), int(steps), ctypes.c_void_p(table.ctypes.data),
                                           ctypes.byref(n), ctypes.byref(bw), ctypes.byref(bc)))
         return bw.value, bc.value, table[:min(n.value, cap)].copy()
+
+    def dm_set_pass_shape(self, width, cfg):
+        self._check(self._lib.dm_set_pass_shape(self.h, int(width), int(cfg)))
 
     # ---------------------------------------------------------------- batch
     def dm_batch_set_focks(self, clusters):

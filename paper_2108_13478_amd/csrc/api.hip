@@ -86,6 +86,7 @@ struct dm_ctx {
     // workspace
     DevBuf<double> Ua, Ub, Z, P;  // sized in bytes via double slots
     DevBuf<double> part_start, part_steps;
+    DevBuf<double> work;  // partial products of the split-reduction shapes (byte size via double slots)
     DevBuf<double> coef, coef_zero, fk, w, v, out;
     DevBuf<int> flag;
     DevBuf<long long> cols;
@@ -624,8 +625,8 @@ void dm_destroy(dm_ctx* c) {
     (void)hipSetDevice(c->opt.device);
     if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
     for (auto* b : {&c->op.Sinv, &c->op.HT, &c->op.HNbuf, &c->op.S_val, &c->mom, &c->Ua, &c->Ub, &c->Z, &c->P,
-                    &c->part_start, &c->part_steps, &c->coef, &c->coef_zero, &c->fk, &c->w, &c->v,
-                    &c->out})
+                    &c->part_start, &c->part_steps, &c->work, &c->coef, &c->coef_zero, &c->fk, &c->w,
+                    &c->v, &c->out})
         b->release();
     c->op.release();
     for (auto& o : c->batch) o.release();
@@ -722,6 +723,8 @@ dm_status dm_set_precision(dm_ctx* c, int precision) {
     if (st != DM_OK) return st;
     if (precision != DM_FP64 && precision != DM_FP32) return set_err(c, DM_E_ARG, "bad precision");
     c->precision = precision;
+    c->tuned_width = 0;  // shapes were timed (or fit) for the other precision
+    c->tuned_cfg = -1;
     reset_moments(c);
     if (!c->have_fock) return DM_OK;
     return normalize(c, c->op);
@@ -774,9 +777,12 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
     bw = std::min<long long>(bw, std::max<long long>(128, (long long)(budget / per_col) / 128 * 128));
     bw = std::min(bw, ncols);
     int cfg = pick_cfg(Kp, (int)bw);
-    if (tuned && bw % cheb_tile_cols(c->tuned_cfg) == 0) cfg = c->tuned_cfg;
+    if (tuned && cheb_cfg_fits(c->tuned_cfg, c->precision, Kp, (int)round_up(bw, cheb_tile_cols(c->tuned_cfg))))
+        cfg = c->tuned_cfg;
     const int BN = cheb_tile_cols(cfg);
     const int Bp_max = (int)round_up(bw, std::max(BN, 16));
+    const size_t wbytes = cheb_work_bytes(Kp, Bp_max, cfg, c->precision);
+    if (wbytes) HIPTRY(c, ensure(c->work, (wbytes + 7) / 8));
     HIPTRY(c, ensure(c->Ua, (size_t)Kp * Bp_max * tsz / 8));
     HIPTRY(c, ensure(c->Ub, (size_t)Kp * Bp_max * tsz / 8));
     HIPTRY(c, ensure(c->Z, (size_t)Kp * Bp_max));
@@ -806,6 +812,7 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
         a.P = c->P.p;
         a.Z = c->Z.p;
         a.partial = c->part_steps.p;
+        a.work = c->work.p;
         const int ntl = cheb_num_tiles(Kp, Bp, cfg);
         for (int l = 1; l <= order; ++l) {
             a.Ucur = ucur;
@@ -908,6 +915,29 @@ dm_status dm_reset_moments(dm_ctx* c) {
     return reset_moments(c);
 }
 
+dm_status dm_set_pass_shape(dm_ctx* c, int width, int cfg) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (width < 1 || cfg < 0 || cfg >= cheb_num_tile_configs() ||
+        !cheb_cfg_fits(cfg, c->precision, c->op.Kp, (int)round_up(width, cheb_tile_cols(cfg))))
+        return set_err(c, DM_E_ARG, "pass width must be >= 1 and the tile shape one that fits this operator and precision");
+    c->tuned_width = width;
+    c->tuned_cfg = cfg;
+    return DM_OK;
+}
+
+int dm_num_tile_shapes(void) { return cheb_num_tile_configs(); }
+
+dm_status dm_tile_shape(int cfg, int* rows, int* cols, int* split) {
+    if (cfg < 0 || cfg >= cheb_num_tile_configs()) return DM_E_ARG;
+    if (rows) *rows = cheb_tile_rows(cfg);
+    if (cols) *cols = cheb_tile_cols(cfg);
+    if (split) *split = cheb_cfg_split(cfg);
+    return DM_OK;
+}
+
 dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int* ntable,
                       int* best_width, int* best_cfg) {
     if (!c) return DM_E_ARG;
@@ -928,13 +958,12 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
     for (int w : widths) {
         if (w > wmax && w != wfull) continue;
         for (int cfg = 0; cfg < cheb_num_tile_configs(); ++cfg)
-            if (w % cheb_tile_cols(cfg) == 0 && cheb_cfg_supports(cfg, c->precision))
-                cands.push_back({w, cfg, 0.0});
+            if (cheb_cfg_fits(cfg, c->precision, Kp, w)) cands.push_back({w, cfg, 0.0});
     }
     const int W = std::max(256, wfull);
-    DevBuf<double> U0, U1, Zb, Pb, part, pst, coef;
+    DevBuf<double> U0, U1, Zb, Pb, part, pst, coef, work;
     DevBuf<long long> colsd;
-    auto rel = [&]() { U0.release(); U1.release(); Zb.release(); Pb.release(); part.release(); pst.release(); coef.release(); colsd.release(); };
+    auto rel = [&]() { U0.release(); U1.release(); Zb.release(); Pb.release(); part.release(); pst.release(); coef.release(); work.release(); colsd.release(); };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e;
 #define AT(expr)                                         \
@@ -955,8 +984,13 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
     AT(ensure(pst, (size_t)(Kp / 64) * (W / 16)));
     AT(ensure(coef, (size_t)steps + 4));
     int max_tiles = 0;
-    for (const Cand& cd : cands) max_tiles = std::max(max_tiles, cheb_num_tiles(Kp, cd.w, cd.cfg));
+    size_t max_work = 0;
+    for (const Cand& cd : cands) {
+        max_tiles = std::max(max_tiles, cheb_num_tiles(Kp, cd.w, cd.cfg));
+        max_work = std::max(max_work, cheb_work_bytes(Kp, cd.w, cd.cfg, c->precision));
+    }
     AT(ensure(part, (size_t)(steps + 4) * max_tiles));
+    if (max_work) AT(ensure(work, (max_work + 7) / 8));
     std::vector<long long> hc(W);
     for (int j = 0; j < W; ++j) hc[j] = j % K;
     AT(ensure(colsd, (size_t)W));
@@ -976,6 +1010,7 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
         a.P = Pb.p;
         a.Z = Zb.p;
         a.partial = part.p;
+        a.work = work.p;
         void* ucur = U0.p;
         void* uoth = U1.p;
         for (int l = 1; l <= steps + 2; ++l) {

@@ -36,6 +36,10 @@ hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, lo
 // HN: Kp x Kp, row-major (row m contiguous); U*, P, Z: Kp x Bp column-major
 // (ld = Kp).  Unext may alias Uprev.  `cfg` selects the tile shape
 // (see cheb_tile_configs); Bp must be a multiple of that shape's column tile.
+// Split-reduction shapes (cheb_cfg_split(cfg) > 1) first write one partial
+// product per reduction chunk into `work` (cheb_work_bytes(Kp, Bp, cfg,
+// precision) bytes), then a second kernel sums the chunks in fixed order and
+// applies the epilogue; `ntiles` is then the second kernel's workgroup count.
 struct ChebStepArgs {
     int Kp, Bp;
     const void* HN;
@@ -49,9 +53,15 @@ struct ChebStepArgs {
     double* P;
     const double* Z;
     double* partial;
+    void* work;
 };
 int cheb_num_tile_configs();
 bool cheb_cfg_supports(int cfg, int precision);
+// The shape runs on this operator size and pass width (divisibility of the
+// reduction chunks, width limit of the split shapes).
+bool cheb_cfg_fits(int cfg, int precision, int Kp, int Bp);
+int cheb_cfg_split(int cfg);
+size_t cheb_work_bytes(int Kp, int Bp, int cfg, int precision);
 int cheb_tile_cols(int cfg);
 int cheb_tile_rows(int cfg);
 hipError_t cheb_step_f64(const ChebStepArgs& a, int cfg, hipStream_t s);

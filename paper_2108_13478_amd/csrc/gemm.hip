@@ -86,7 +86,7 @@ template <> struct VecOf<double, 8> { typedef double type __attribute__((ext_vec
 template <> struct VecOf<float, 8> { typedef float type __attribute__((ext_vector_type(8))); };
 template <> struct VecOf<float, 16> { typedef float type __attribute__((ext_vector_type(16))); };
 
-template <typename T, int TM, int TN, int KV, int DEPTH = 2>
+template <typename T, int TM, int TN, int KV, int DEPTH = 2, bool NT = false>
 __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda,
                                      const T* __restrict__ B, long ldb, int row0, int col0,
                                      typename Mfma<T>::acc_t (&acc)[TM][TN]) {
@@ -106,9 +106,16 @@ __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda
         for (int j = 0; j < TN; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
 
     vec_t a0[TM], b0[TN], a1[TM], b1[TN];
+    // NT: the A operand is read once per launch, so its loads carry the
+    // non-temporal hint and leave the cache to the reused B panel.
     auto load = [&](vec_t(&a)[TM], vec_t(&b)[TN], int k) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const vec_t*>(pa[i] + k);
+        for (int i = 0; i < TM; ++i) {
+            if constexpr (NT)
+                a[i] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(pa[i] + k));
+            else
+                a[i] = *reinterpret_cast<const vec_t*>(pa[i] + k);
+        }
 #pragma unroll
         for (int j = 0; j < TN; ++j) b[j] = *reinterpret_cast<const vec_t*>(pb[j] + k);
     };
@@ -130,31 +137,39 @@ __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda
         for (; k < Kred - 2 * SLAB; k += 2 * SLAB) {
             load(a1, b1, k + SLAB);
             compute(a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
             load(a0, b0, k + 2 * SLAB);
             compute(a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
         }
         load(a1, b1, k + SLAB);
         compute(a0, b0);
         compute(a1, b1);
     } else {
-        // Ring of four buffers: three slabs stay in flight while one is
-        // consumed (Kred is a multiple of 4 SLAB).  For memory-bound narrow
-        // blocks one slab of MFMA work is far shorter than an HBM round trip.
+        // Ring of DEPTH buffers: DEPTH - 1 slabs stay in flight while one is
+        // consumed (Kred is a multiple of DEPTH SLAB).  One slab of MFMA work
+        // is far shorter than an HBM or Infinity Cache round trip.
+        static_assert((DEPTH & (DEPTH - 1)) == 0, "ring depth is a power of two");
         (void)a0; (void)b0; (void)a1; (void)b1;
-        vec_t ra[4][TM], rb[4][TN];
+        vec_t ra[DEPTH][TM], rb[DEPTH][TN];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) load(ra[d], rb[d], d * SLAB);
+        for (int d = 0; d < DEPTH - 1; ++d) load(ra[d], rb[d], d * SLAB);
         int k = 0;
-        for (; k < Kred - 4 * SLAB; k += 4 * SLAB) {
+        for (; k < Kred - DEPTH * SLAB; k += DEPTH * SLAB) {
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                load(ra[(d + 3) & 3], rb[(d + 3) & 3], k + (d + 3) * SLAB);
+            for (int d = 0; d < DEPTH; ++d) {
+                const int n = (d + DEPTH - 1) & (DEPTH - 1);
+                load(ra[n], rb[n], k + (d + DEPTH - 1) * SLAB);
                 compute(ra[d], rb[d]);
+                // Keep the stages in program order: left alone, the scheduler
+                // sinks every load of the next ring turn to the end of the loop
+                // body, and each turn then waits for all of them at its start.
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
-        load(ra[3], rb[3], k + 3 * SLAB);
+        load(ra[DEPTH - 1], rb[DEPTH - 1], k + (DEPTH - 1) * SLAB);
 #pragma unroll
-        for (int d = 0; d < 4; ++d) compute(ra[d], rb[d]);
+        for (int d = 0; d < DEPTH; ++d) compute(ra[d], rb[d]);
     }
 }
 
@@ -237,6 +252,74 @@ cheb_step_kernel(ChebStepArgs a) {
     }
 }
 
+// ------------------------------------------------------------ split reduction
+// Narrow column blocks leave too few tiles to keep enough operator bytes in
+// flight.  The reduction is cut into NSPLIT chunks: workgroup b takes chunk
+// b % NSPLIT, and since workgroups are dispatched round-robin over the 8
+// XCDs, with NSPLIT = 8 each XCD streams its own slice of every operator row
+// and keeps only its slice of the column block (BN x Kp/8) hot in its L2.
+// Each workgroup stores its partial product; cheb_combine_kernel sums the
+// chunks in chunk order and applies the recursion epilogue.
+template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH, int NSPLIT, bool NT>
+__global__ void __launch_bounds__(64 * WM * WN)
+cheb_partial_kernel(ChebStepArgs a) {
+    typedef typename Mfma<T>::vec_t vec_t;
+    constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    const int ntm = a.Kp / BM;
+    const int chunk = blockIdx.x % NSPLIT;
+    const int t = blockIdx.x / NSPLIT;
+    const int kc = a.Kp / NSPLIT;
+    const int wave = threadIdx.x >> 6;
+    const int row0 = (t % ntm) * BM + (wave % WM) * TM * 16;
+    const int col0 = (t / ntm) * BN + (wave / WM) * TN * 16;
+    typename Mfma<T>::acc_t acc[TM][TN];
+    const long k0 = (long)chunk * kc;
+    gemm_mainloop<T, TM, TN, KV, DEPTH, NT>(kc, static_cast<const T*>(a.HN) + k0, a.Kp,
+                                            static_cast<const T*>(a.Ucur) + k0, a.Kp, row0, col0, acc);
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    T* W = static_cast<T*>(a.work) + (long)chunk * a.Kp * a.Bp;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const long idx = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * a.Kp;
+            *reinterpret_cast<vec_t*>(W + idx) = acc[i][j];
+        }
+}
+
+// One thread per four consecutive rows of one column (column-major index
+// 4q); 256 threads per workgroup, Kp * Bp / 1024 workgroups.
+template <typename T, int NSPLIT>
+__global__ void __launch_bounds__(256) cheb_combine_kernel(ChebStepArgs a) {
+    typedef typename Mfma<T>::vec_t vec_t;
+    const long idx = 4 * ((long)blockIdx.x * 256 + threadIdx.x);
+    const long plane = (long)a.Kp * a.Bp;
+    const T* W = static_cast<const T*>(a.work);
+    vec_t sum = *reinterpret_cast<const vec_t*>(W + idx);
+#pragma unroll
+    for (int c = 1; c < NSPLIT; ++c) sum += *reinterpret_cast<const vec_t*>(W + c * plane + idx);
+    vec_t out = static_cast<T>(a.alpha) * sum;
+    if (a.has_prev) out -= *reinterpret_cast<const vec_t*>(static_cast<const T*>(a.Uprev) + idx);
+    *reinterpret_cast<vec_t*>(static_cast<T*>(a.Unext) + idx) = out;
+    const double4_t z = *reinterpret_cast<const double4_t*>(a.Z + idx);
+    double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
+    double msum = z[0] * od[0] + z[1] * od[1] + z[2] * od[2] + z[3] * od[3];
+    const double c = a.coef[a.l];
+    if (c != 0.0) {
+        double4_t* p = reinterpret_cast<double4_t*>(a.P + idx);
+        *p = *p + c * od;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) msum += __shfl_xor(msum, off, 64);
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = msum;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        a.partial[(long)a.l * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 // ------------------------------------------------------------ persistent batch
 template <typename T, int TM, int TN, int WM, int WN, int KV>
 __global__ void __launch_bounds__(64 * WM * WN)
@@ -306,7 +389,13 @@ cheb_batch_kernel(BatchArgs a) {
 
 struct CfgShape {
     int tm, tn, wm, wn, kv, depth;
+    int split = 1;    // reduction chunks (one per XCD)
+    bool nt = false;  // non-temporal operator loads
+    bool fp32_only = false;  // the FP64 build of the register ring would spill
 };
+// Split shapes serve narrow passes only (the partial products take
+// split x Kp x Bp elements).
+constexpr int kSplitMaxCols = 512;
 // Tile shapes of the recursion step (rows x columns per workgroup, k per
 // lane and slab).  The first four suit the compute-bound wide blocks; the
 // last three keep more operator bytes in flight for narrow, memory-bound
@@ -318,13 +407,29 @@ constexpr CfgShape kChebCfgs[] = {
     {2, 2, 2, 2, 4, 2},   // 64 x 64
     {1, 2, 4, 1, 8, 2},   // 64 x 32, 8 k per lane
     {1, 4, 4, 1, 8, 2},   // 64 x 64, 8 k per lane
-    {1, 2, 4, 1, 16, 2},  // 64 x 32, 16 k per lane (FP32)
+    {1, 2, 4, 1, 16, 2, 1, false, true},  // 64 x 32, 16 k per lane (FP32)
     {2, 2, 4, 1, 4, 4},   // 128 x 32, three slabs in flight
     {4, 2, 2, 2, 4, 4},   // 128 x 64, three slabs in flight
     {1, 2, 4, 1, 4, 4},   // 64 x 32, three slabs in flight
     {4, 2, 2, 4, 4, 2},   // 128 x 128, 8 waves: two waves per SIMD
     {2, 4, 4, 2, 4, 2},   // 128 x 128, 8 waves, 32 x 64 per wave
     {4, 4, 2, 2, 4, 4},   // 128 x 128, three slabs in flight
+    {1, 2, 4, 1, 4, 4, 8, false},  // 64 x 32, 8 reduction chunks
+    {2, 2, 4, 1, 4, 4, 8, false},  // 128 x 32, 8 reduction chunks
+    {1, 2, 4, 1, 8, 2, 8, false},  // 64 x 32, 8 chunks, 8 k per lane
+    {1, 2, 4, 1, 4, 4, 8, true},   // 64 x 32, 8 chunks, non-temporal operator
+    {1, 4, 4, 1, 4, 4, 8, false},  // 64 x 64, 8 chunks
+    {2, 4, 4, 1, 4, 4, 8, true},   // 128 x 64, 8 chunks, non-temporal operator
+    {1, 2, 4, 1, 4, 4, 16, false}, // 64 x 32, 16 chunks (two per XCD)
+    {2, 2, 4, 1, 4, 8},   // 128 x 32, seven slabs in flight
+    {1, 2, 4, 1, 4, 8},   // 64 x 32, seven slabs in flight
+    {2, 2, 4, 1, 8, 4, 1, false, true},   // 128 x 32, 8 k per lane, three slabs in flight (FP32)
+    {2, 2, 4, 1, 4, 16, 1, false, true},  // 128 x 32, fifteen slabs in flight (FP32)
+    {4, 2, 2, 2, 4, 8, 1, false, true},   // 128 x 64, seven slabs in flight (FP32)
+    {2, 2, 4, 1, 8, 8, 1, false, true},   // 128 x 32, 8 k per lane, seven slabs in flight (FP32)
+    {1, 2, 8, 1, 8, 4, 1, false, true},   // 128 x 32, 8 waves, 8 k per lane (FP32)
+    {4, 4, 2, 2, 8, 4, 1, false, true},   // 128 x 128, 8 k per lane, three slabs in flight (FP32)
+    {4, 2, 2, 2, 8, 4, 1, false, true},   // 128 x 64, 8 k per lane, three slabs in flight (FP32)
 };
 
 template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH = 2>
@@ -333,6 +438,20 @@ hipError_t launch_one(const ChebStepArgs& a, hipStream_t s) {
     if (a.Kp % BM || a.Bp % BN || a.Kp % (4 * DEPTH * KV)) return hipErrorInvalidValue;
     const dim3 grid((a.Kp / BM) * (a.Bp / BN));
     hipLaunchKernelGGL((cheb_step_kernel<T, TM, TN, WM, WN, KV, DEPTH>), grid, dim3(64 * WM * WN), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH, int NSPLIT, bool NT>
+hipError_t launch_split(const ChebStepArgs& a, hipStream_t s) {
+    constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    if (a.Kp % BM || a.Bp % BN || a.Bp > kSplitMaxCols || a.Kp % (NSPLIT * 4 * DEPTH * KV) || !a.work)
+        return hipErrorInvalidValue;
+    const dim3 grid(NSPLIT * (a.Kp / BM) * (a.Bp / BN));
+    hipLaunchKernelGGL((cheb_partial_kernel<T, TM, TN, WM, WN, KV, DEPTH, NSPLIT, NT>), grid,
+                       dim3(64 * WM * WN), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((cheb_combine_kernel<T, NSPLIT>), dim3((long)a.Kp * a.Bp / 1024), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -354,6 +473,36 @@ hipError_t launch_cheb(const ChebStepArgs& a, int cfg, hipStream_t s) {
         case 10: return launch_one<T, 4, 2, 2, 4, 4>(a, s);
         case 11: return launch_one<T, 2, 4, 4, 2, 4>(a, s);
         case 12: return launch_one<T, 4, 4, 2, 2, 4, 4>(a, s);
+        case 13: return launch_split<T, 1, 2, 4, 1, 4, 4, 8, false>(a, s);
+        case 14: return launch_split<T, 2, 2, 4, 1, 4, 4, 8, false>(a, s);
+        case 15: return launch_split<T, 1, 2, 4, 1, 8, 2, 8, false>(a, s);
+        case 16: return launch_split<T, 1, 2, 4, 1, 4, 4, 8, true>(a, s);
+        case 17: return launch_split<T, 1, 4, 4, 1, 4, 4, 8, false>(a, s);
+        case 18: return launch_split<T, 2, 4, 4, 1, 4, 4, 8, true>(a, s);
+        case 19: return launch_split<T, 1, 2, 4, 1, 4, 4, 16, false>(a, s);
+        case 20: return launch_one<T, 2, 2, 4, 1, 4, 8>(a, s);
+        case 21: return launch_one<T, 1, 2, 4, 1, 4, 8>(a, s);
+        case 22:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 2, 2, 4, 1, 8, 4>(a, s);
+            return hipErrorInvalidValue;
+        case 23:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 2, 2, 4, 1, 4, 16>(a, s);
+            return hipErrorInvalidValue;
+        case 24:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 4, 2, 2, 2, 4, 8>(a, s);
+            return hipErrorInvalidValue;
+        case 25:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 2, 2, 4, 1, 8, 8>(a, s);
+            return hipErrorInvalidValue;
+        case 26:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 1, 2, 8, 1, 8, 4>(a, s);
+            return hipErrorInvalidValue;
+        case 27:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 4, 4, 2, 2, 8, 4>(a, s);
+            return hipErrorInvalidValue;
+        case 28:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 4, 2, 2, 2, 8, 4>(a, s);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -397,10 +546,23 @@ int cheb_batch_occupancy(int cfg, int precision) {
 }
 
 int cheb_num_tile_configs() { return (int)(sizeof(kChebCfgs) / sizeof(kChebCfgs[0])); }
-bool cheb_cfg_supports(int cfg, int precision) { return !(kChebCfgs[cfg].kv == 16 && precision == 0); }
+bool cheb_cfg_supports(int cfg, int precision) { return !(kChebCfgs[cfg].fp32_only && precision == 0); }
 int cheb_tile_rows(int cfg) { return 16 * kChebCfgs[cfg].tm * kChebCfgs[cfg].wm; }
 int cheb_tile_cols(int cfg) { return 16 * kChebCfgs[cfg].tn * kChebCfgs[cfg].wn; }
+int cheb_cfg_split(int cfg) { return kChebCfgs[cfg].split; }
+bool cheb_cfg_fits(int cfg, int precision, int Kp, int Bp) {
+    if (cfg < 0 || cfg >= cheb_num_tile_configs() || !cheb_cfg_supports(cfg, precision)) return false;
+    const CfgShape& c = kChebCfgs[cfg];
+    if (Kp % cheb_tile_rows(cfg) || Bp % cheb_tile_cols(cfg)) return false;
+    if (Kp % (c.split * 4 * c.depth * c.kv)) return false;
+    return c.split == 1 || Bp <= kSplitMaxCols;
+}
+size_t cheb_work_bytes(int Kp, int Bp, int cfg, int precision) {
+    const int sp = kChebCfgs[cfg].split;
+    return sp == 1 ? 0 : (size_t)sp * Kp * Bp * (precision == 0 ? 8 : 4);
+}
 int cheb_num_tiles(int Kp, int Bp, int cfg) {
+    if (kChebCfgs[cfg].split > 1) return (int)((long)Kp * Bp / 1024);
     return (Kp / cheb_tile_rows(cfg)) * (Bp / cheb_tile_cols(cfg));
 }
 

@@ -62,3 +62,14 @@ def test_invalid_options_rejected_before_device_query(lib):
     opt.precision = 0
     opt.spin = -1.0
     assert lib.dm_init(ctypes.byref(h), ctypes.byref(opt)) == dmlib.DM_E_ARG
+
+
+def test_tile_shape_table_without_hip(lib):
+    shapes = dmlib.tile_shapes()
+    assert len(shapes) == lib.dm_num_tile_shapes() >= 13
+    for rows, cols, split in shapes:
+        assert rows % 16 == 0 and cols % 16 == 0 and split in (1, 8, 16)
+    assert any(s > 1 for _, _, s in shapes)  # split-reduction shapes for narrow passes
+    assert lib.dm_tile_shape(len(shapes), None, None, None) == dmlib.DM_E_ARG
+    assert lib.dm_tile_shape(-1, None, None, None) == dmlib.DM_E_ARG
+    assert lib.dm_set_pass_shape(None, 32, 0) == dmlib.DM_E_ARG
