@@ -400,24 +400,40 @@ dm_status reset_moments(dm_ctx* c) {
     return DM_OK;
 }
 
-// Tile shape for a pass when nothing was tuned: among the standard shapes
-// (128 x 128 with three slabs in flight, 128 x 64, 128 x 32, 64 x 64), the
-// widest tile whose grid still gives every CU two workgroups, else the one
-// with the most workgroups.
-int pick_cfg(int Kp, int ncols) {
-    int best = -1, best_tiles = -1;
-    for (int cfg : {12, 1, 2, 3}) {
-        const int BN = cheb_tile_cols(cfg);
-        const int Bp = (int)round_up(std::max(ncols, 1), BN);
-        if (Bp > round_up(std::max(ncols, 1), 32) && BN > 32) continue;  // padding beyond 32
-        const int tiles = cheb_num_tiles(Kp, Bp, cfg);
-        if (tiles >= 512) return cfg;
-        if (tiles > best_tiles) {
-            best_tiles = tiles;
+// Tile shape for a pass when nothing was tuned.  Shapes are tried in order
+// of measured speed on MI355X (128 x 128 with three k-slabs in flight for
+// wide passes; the LDS-shared panel shapes for 64- and 32-column passes);
+// the first that fits, pads the pass by less than 32 columns and still
+// gives 256 workgroups (one per CU) wins.  Narrow passes over small
+// operators, which have too few row tiles, take a split-reduction shape.
+int pick_cfg(int Kp, int ncols, int precision) {
+    static const int kPrefF64[] = {12, 36, 33, 32, 1, 2, 3};
+    static const int kPrefF32[] = {12, 31, 29, 30, 1, 2, 3};
+    static const int kSplit[] = {18, 14, 13};
+    const int n = std::max(ncols, 1);
+    const int n32 = (int)round_up(n, 32);
+    const int* pref = precision == DM_FP64 ? kPrefF64 : kPrefF32;
+    const int npref = precision == DM_FP64 ? (int)(sizeof(kPrefF64) / sizeof(int)) : (int)(sizeof(kPrefF32) / sizeof(int));
+    for (int i = 0; i < npref; ++i) {
+        const int cfg = pref[i];
+        const int Bp = (int)round_up(n, cheb_tile_cols(cfg));
+        if (Bp > n32 || !cheb_cfg_fits(cfg, precision, Kp, Bp)) continue;
+        if (cheb_num_tiles(Kp, Bp, cfg) >= 256) return cfg;
+    }
+    for (int cfg : kSplit) {
+        const int Bp = (int)round_up(n, cheb_tile_cols(cfg));
+        if (Bp <= n32 && cheb_cfg_fits(cfg, precision, Kp, Bp)) return cfg;
+    }
+    int best = 3, best_tiles = -1;
+    for (int cfg : {2, 3}) {
+        const int Bp = (int)round_up(n, cheb_tile_cols(cfg));
+        const int t = cheb_num_tiles(Kp, Bp, cfg);
+        if (Bp <= n32 && t > best_tiles) {
             best = cfg;
+            best_tiles = t;
         }
     }
-    return best < 0 ? 0 : best;
+    return best;
 }
 
 }  // namespace
@@ -776,7 +792,7 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
     const size_t per_col = (size_t)Kp * (2 * tsz + 16);
     bw = std::min<long long>(bw, std::max<long long>(128, (long long)(budget / per_col) / 128 * 128));
     bw = std::min(bw, ncols);
-    int cfg = pick_cfg(Kp, (int)bw);
+    int cfg = pick_cfg(Kp, (int)bw, c->precision);
     if (tuned && cheb_cfg_fits(c->tuned_cfg, c->precision, Kp, (int)round_up(bw, cheb_tile_cols(c->tuned_cfg))))
         cfg = c->tuned_cfg;
     const int BN = cheb_tile_cols(cfg);
@@ -1094,11 +1110,11 @@ dm_status stoch_moments_op(dm_ctx* c, Op& op, int n_mom, int n_vec, const double
     hipStream_t s = c->stream;
     const int K = (int)op.K, Kp = op.Kp;
     const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
-    const int cfg = pick_cfg(Kp, n_vec);
+    const int cfg = pick_cfg(Kp, n_vec, c->precision);
     const int BN = cheb_tile_cols(cfg);
     const int Bp = (int)round_up(n_vec, std::max(BN, 16));
-    DevBuf<double> X, U0, U1, Zs, Pd, pst, pss, ms, cz;
-    auto rel = [&]() { X.release(); U0.release(); U1.release(); Zs.release(); Pd.release(); pst.release(); pss.release(); ms.release(); cz.release(); };
+    DevBuf<double> X, U0, U1, Zs, Pd, pst, pss, ms, cz, W;
+    auto rel = [&]() { X.release(); U0.release(); U1.release(); Zs.release(); Pd.release(); pst.release(); pss.release(); ms.release(); cz.release(); W.release(); };
     hipError_t e;
 #define SM(expr)                          \
     do {                                  \
@@ -1117,6 +1133,8 @@ dm_status stoch_moments_op(dm_ctx* c, Op& op, int n_mom, int n_vec, const double
     SM(ensure(pss, (size_t)std::max(n_mom, 1) * ntl));
     SM(ensure(ms, (size_t)n_mom));
     SM(ensure(cz, (size_t)n_mom + 1));
+    const size_t wbytes = cheb_work_bytes(Kp, Bp, cfg, c->precision);
+    if (wbytes) SM(ensure(W, (wbytes + 7) / 8));
     SM(hipMemcpyAsync(X.p, xi, (size_t)K * n_vec * 8, hipMemcpyDefault, s));
     SM(fill_f64(ms.p, 0.0, n_mom, s));
     SM(fill_f64(cz.p, 0.0, n_mom + 1, s));
@@ -1134,6 +1152,7 @@ dm_status stoch_moments_op(dm_ctx* c, Op& op, int n_mom, int n_vec, const double
     a.P = Pd.p;
     a.Z = Zs.p;
     a.partial = pss.p;
+    a.work = W.p;
     for (int l = 1; l < n_mom; ++l) {
         a.Ucur = ucur;
         a.Uprev = (l == 1) ? nullptr : uoth;

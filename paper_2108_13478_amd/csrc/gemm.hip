@@ -173,6 +173,98 @@ __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda
     }
 }
 
+// The main loop with the B panel shared through LDS.  All WM waves of the
+// workgroup cover the same 16 TN columns, so instead of every wave reading
+// the panel from the cache hierarchy (which halves the operator stream when
+// the panel is as wide as the wave's row block), the workgroup fetches each
+// slab of it once: 16-byte pieces, one (or R) per thread, staged through
+// registers in the same ring as the operator, written to one of two LDS
+// buffers and read back as MFMA fragments after a barrier.  Piece p of a
+// slab holds lane p % 64 of chunk p / 64 = (column group, 16-byte part), so a
+// wave reads its fragment of column group j, part h at ((j H + h) 64 + lane)
+// * 16 bytes with no bank conflicts.  The barrier waits only for LDS
+// traffic; the operator loads of later slabs stay in flight across it.
+template <typename T, int TM, int TN, int WM, int KV, int DEPTH>
+__device__ inline void gemm_mainloop_ldsb(int Kred, const T* __restrict__ A, long lda,
+                                          const T* __restrict__ B, long ldb, int row0, int col0,
+                                          typename Mfma<T>::acc_t (&acc)[TM][TN]) {
+    typedef typename VecOf<T, KV>::type vec_t;
+    typedef float piece_t __attribute__((ext_vector_type(4)));
+    constexpr int SLAB = 4 * KV;
+    constexpr int H = KV * (int)sizeof(T) / 16;          // 16-byte parts per lane and column group
+    constexpr int NPIECE = TN * H * 64;                   // pieces per slab
+    constexpr int NT = 64 * WM;
+    constexpr int R = NPIECE / NT;                        // pieces per thread and slab
+    constexpr int EPP = 16 / (int)sizeof(T);              // elements per piece
+    static_assert(NPIECE % NT == 0 && R >= 1, "every thread loads whole pieces");
+    static_assert(DEPTH >= 2 && (DEPTH & (DEPTH - 1)) == 0, "ring depth is a power of two");
+    __shared__ piece_t lds[2][NPIECE];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    const T* pa[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) pa[i] = A + (long)(row0 + 16 * i + Mfma<T>::a_row(li)) * lda + KV * lq;
+    const T* pp[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+        const int c = (tid + e * NT) >> 6;  // chunk: column group c / H, part c % H
+        pp[e] = B + (long)(col0 + 16 * (c / H) + li) * ldb + KV * lq + EPP * (c % H);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+
+    vec_t ra[DEPTH][TM];
+    piece_t rs[DEPTH][R];
+    auto load = [&](vec_t(&a)[TM], piece_t(&st)[R], int k) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = *reinterpret_cast<const vec_t*>(pa[i] + k);
+#pragma unroll
+        for (int e = 0; e < R; ++e) st[e] = *reinterpret_cast<const piece_t*>(pp[e] + k);
+    };
+    auto compute = [&](const vec_t(&a)[TM], const piece_t(&st)[R], int buf) {
+#pragma unroll
+        for (int e = 0; e < R; ++e) lds[buf][tid + e * NT] = st[e];
+        __syncthreads();
+        vec_t b[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            T* bj = reinterpret_cast<T*>(&b[j]);
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const piece_t v = lds[buf][(j * H + h) * 64 + lane];
+                __builtin_memcpy(bj + h * EPP, &v, 16);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < KV; ++s)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i][s], b[j][s], acc[i][j]);
+    };
+    // Slab n uses LDS buffer n & 1 (DEPTH is even, so that is d & 1 below).
+    // A buffer is rewritten two slabs later, after every wave has passed the
+    // barrier of the slab in between, i.e. after it finished reading.
+#pragma unroll
+    for (int d = 0; d < DEPTH - 1; ++d) load(ra[d], rs[d], d * SLAB);
+    int k = 0;
+    for (; k < Kred - DEPTH * SLAB; k += DEPTH * SLAB) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            const int n = (d + DEPTH - 1) & (DEPTH - 1);
+            load(ra[n], rs[n], k + (d + DEPTH - 1) * SLAB);
+            compute(ra[d], rs[d], d & 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    load(ra[DEPTH - 1], rs[DEPTH - 1], k + (DEPTH - 1) * SLAB);
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) compute(ra[d], rs[d], d & 1);
+}
+
 // ------------------------------------------------------------ plain product
 template <int TM, int TN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
@@ -202,7 +294,7 @@ gemm_tn_store_kernel(int M, int N, int Kred, double alpha, const double* __restr
 }
 
 // ------------------------------------------------------------ recursion step
-template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH>
+template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH, bool LDSB = false>
 __global__ void __launch_bounds__(64 * WM * WN)
 cheb_step_kernel(ChebStepArgs a) {
     typedef typename Mfma<T>::vec_t vec_t;
@@ -213,8 +305,14 @@ cheb_step_kernel(ChebStepArgs a) {
     const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
     const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
     typename Mfma<T>::acc_t acc[TM][TN];
-    gemm_mainloop<T, TM, TN, KV, DEPTH>(a.Kp, static_cast<const T*>(a.HN), a.Kp, static_cast<const T*>(a.Ucur),
-                             a.Kp, row0, col0, acc);
+    if constexpr (LDSB) {
+        static_assert(WN == 1, "the shared panel needs every wave on the same columns");
+        gemm_mainloop_ldsb<T, TM, TN, WM, KV, DEPTH>(a.Kp, static_cast<const T*>(a.HN), a.Kp,
+                                                     static_cast<const T*>(a.Ucur), a.Kp, row0, col0, acc);
+    } else {
+        gemm_mainloop<T, TM, TN, KV, DEPTH>(a.Kp, static_cast<const T*>(a.HN), a.Kp,
+                                            static_cast<const T*>(a.Ucur), a.Kp, row0, col0, acc);
+    }
 
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
@@ -391,7 +489,8 @@ struct CfgShape {
     int tm, tn, wm, wn, kv, depth;
     int split = 1;    // reduction chunks (one per XCD)
     bool nt = false;  // non-temporal operator loads
-    bool fp32_only = false;  // the FP64 build of the register ring would spill
+    int precs = 3;     // built for FP64 (bit 0) and/or FP32 (bit 1)
+    bool ldsb = false; // B panel shared through LDS
 };
 // Split shapes serve narrow passes only (the partial products take
 // split x Kp x Bp elements).
@@ -407,7 +506,7 @@ constexpr CfgShape kChebCfgs[] = {
     {2, 2, 2, 2, 4, 2},   // 64 x 64
     {1, 2, 4, 1, 8, 2},   // 64 x 32, 8 k per lane
     {1, 4, 4, 1, 8, 2},   // 64 x 64, 8 k per lane
-    {1, 2, 4, 1, 16, 2, 1, false, true},  // 64 x 32, 16 k per lane (FP32)
+    {1, 2, 4, 1, 16, 2, 1, false, 2},  // 64 x 32, 16 k per lane (FP32)
     {2, 2, 4, 1, 4, 4},   // 128 x 32, three slabs in flight
     {4, 2, 2, 2, 4, 4},   // 128 x 64, three slabs in flight
     {1, 2, 4, 1, 4, 4},   // 64 x 32, three slabs in flight
@@ -423,21 +522,29 @@ constexpr CfgShape kChebCfgs[] = {
     {1, 2, 4, 1, 4, 4, 16, false}, // 64 x 32, 16 chunks (two per XCD)
     {2, 2, 4, 1, 4, 8},   // 128 x 32, seven slabs in flight
     {1, 2, 4, 1, 4, 8},   // 64 x 32, seven slabs in flight
-    {2, 2, 4, 1, 8, 4, 1, false, true},   // 128 x 32, 8 k per lane, three slabs in flight (FP32)
-    {2, 2, 4, 1, 4, 16, 1, false, true},  // 128 x 32, fifteen slabs in flight (FP32)
-    {4, 2, 2, 2, 4, 8, 1, false, true},   // 128 x 64, seven slabs in flight (FP32)
-    {2, 2, 4, 1, 8, 8, 1, false, true},   // 128 x 32, 8 k per lane, seven slabs in flight (FP32)
-    {1, 2, 8, 1, 8, 4, 1, false, true},   // 128 x 32, 8 waves, 8 k per lane (FP32)
-    {4, 4, 2, 2, 8, 4, 1, false, true},   // 128 x 128, 8 k per lane, three slabs in flight (FP32)
-    {4, 2, 2, 2, 8, 4, 1, false, true},   // 128 x 64, 8 k per lane, three slabs in flight (FP32)
+    {2, 2, 4, 1, 8, 4, 1, false, 2},   // 128 x 32, 8 k per lane, three slabs in flight (FP32)
+    {2, 2, 4, 1, 4, 16, 1, false, 2},  // 128 x 32, fifteen slabs in flight (FP32)
+    {4, 2, 2, 2, 4, 8, 1, false, 2},   // 128 x 64, seven slabs in flight (FP32)
+    {2, 2, 4, 1, 8, 8, 1, false, 2},   // 128 x 32, 8 k per lane, seven slabs in flight (FP32)
+    {1, 2, 8, 1, 8, 4, 1, false, 2},   // 128 x 32, 8 waves, 8 k per lane (FP32)
+    {4, 4, 2, 2, 8, 4, 1, false, 2},   // 128 x 128, 8 k per lane, three slabs in flight (FP32)
+    {4, 2, 2, 2, 8, 4, 1, false, 2},   // 128 x 64, 8 k per lane, three slabs in flight (FP32)
+    {2, 2, 4, 1, 8, 8, 1, false, 2, true},   // 128 x 32, panel in LDS, seven slabs (FP32)
+    {2, 2, 4, 1, 8, 4, 1, false, 2, true},   // 128 x 32, panel in LDS, three slabs (FP32)
+    {2, 4, 4, 1, 8, 4, 1, false, 2, true},   // 128 x 64, panel in LDS, three slabs (FP32)
+    {2, 2, 4, 1, 4, 4, 1, false, 1, true},  // 128 x 32, panel in LDS, three slabs (FP64)
+    {2, 2, 4, 1, 4, 8, 1, false, 1, true},  // 128 x 32, panel in LDS, seven slabs (FP64)
+    {2, 8, 4, 1, 4, 4, 1, false, 3, true},  // 128 x 128, panel in LDS, three slabs
+    {2, 8, 4, 1, 8, 4, 1, false, 2, true},  // 128 x 128, panel in LDS, 8 k per lane (FP32)
+    {2, 4, 4, 1, 4, 4, 1, false, 1, true},  // 128 x 64, panel in LDS, three slabs (FP64)
 };
 
-template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH = 2>
+template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH = 2, bool LDSB = false>
 hipError_t launch_one(const ChebStepArgs& a, hipStream_t s) {
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
     if (a.Kp % BM || a.Bp % BN || a.Kp % (4 * DEPTH * KV)) return hipErrorInvalidValue;
     const dim3 grid((a.Kp / BM) * (a.Bp / BN));
-    hipLaunchKernelGGL((cheb_step_kernel<T, TM, TN, WM, WN, KV, DEPTH>), grid, dim3(64 * WM * WN), 0, s, a);
+    hipLaunchKernelGGL((cheb_step_kernel<T, TM, TN, WM, WN, KV, DEPTH, LDSB>), grid, dim3(64 * WM * WN), 0, s, a);
     return hipGetLastError();
 }
 
@@ -503,6 +610,28 @@ hipError_t launch_cheb(const ChebStepArgs& a, int cfg, hipStream_t s) {
         case 28:
             if constexpr (sizeof(T) == 4) return launch_one<float, 4, 2, 2, 2, 8, 4>(a, s);
             return hipErrorInvalidValue;
+        case 29:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 2, 2, 4, 1, 8, 8, true>(a, s);
+            return hipErrorInvalidValue;
+        case 30:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 2, 2, 4, 1, 8, 4, true>(a, s);
+            return hipErrorInvalidValue;
+        case 31:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 2, 4, 4, 1, 8, 4, true>(a, s);
+            return hipErrorInvalidValue;
+        case 32:
+            if constexpr (sizeof(T) == 8) return launch_one<double, 2, 2, 4, 1, 4, 4, true>(a, s);
+            return hipErrorInvalidValue;
+        case 33:
+            if constexpr (sizeof(T) == 8) return launch_one<double, 2, 2, 4, 1, 4, 8, true>(a, s);
+            return hipErrorInvalidValue;
+        case 34: return launch_one<T, 2, 8, 4, 1, 4, 4, true>(a, s);
+        case 35:
+            if constexpr (sizeof(T) == 4) return launch_one<float, 2, 8, 4, 1, 8, 4, true>(a, s);
+            return hipErrorInvalidValue;
+        case 36:
+            if constexpr (sizeof(T) == 8) return launch_one<double, 2, 4, 4, 1, 4, 4, true>(a, s);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -546,7 +675,7 @@ int cheb_batch_occupancy(int cfg, int precision) {
 }
 
 int cheb_num_tile_configs() { return (int)(sizeof(kChebCfgs) / sizeof(kChebCfgs[0])); }
-bool cheb_cfg_supports(int cfg, int precision) { return !(kChebCfgs[cfg].fp32_only && precision == 0); }
+bool cheb_cfg_supports(int cfg, int precision) { return (kChebCfgs[cfg].precs >> (precision == 0 ? 0 : 1)) & 1; }
 int cheb_tile_rows(int cfg) { return 16 * kChebCfgs[cfg].tm * kChebCfgs[cfg].wm; }
 int cheb_tile_cols(int cfg) { return 16 * kChebCfgs[cfg].tn * kChebCfgs[cfg].wn; }
 int cheb_cfg_split(int cfg) { return kChebCfgs[cfg].split; }

@@ -98,11 +98,13 @@ def test_batch64_fp32_full_configuration():
     dt = time.perf_counter() - t0
     say(f"  replay: {dt:.2f} s for {Ks.sum()} columns (two passes) = {Ks.sum() / dt:.0f} columns/s")
     assert np.array_equal(mu, mu2)
-    # the single-cluster path at the same mu gives the same P
+    # the single-cluster path at the same mu, on the batch's tile shape (same
+    # summation order), gives the same P
     j = int(np.argmax(Ks))
     c = clusters[j]
     one = dmlib.Context(precision=dmlib.DM_FP32)
     one.set_cluster(c)
+    one.dm_set_pass_shape(c.K, best)
     assert one.dm_get_bounds() == ctx.dm_batch_get_bounds(j)
     P1 = np.zeros((c.K, c.K))
     one.dm_chebyshev_block(np.arange(c.K, dtype=np.int64), N, mu[j], beta, P1)
