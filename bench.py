@@ -35,8 +35,16 @@ PEAK_HBM_GBS = 8000.0
 # workload (KiB), and the scale factors from a plain 1 GiB copy (FETCH_SIZE
 # counts half of the bytes a copy reads on this part, WRITE_SIZE all of them).
 # Valid only for the kernel source they were taken with.
-COUNTERS = {"kernel_source_sha256_16": "0d8b8f805e1e4598", "fetch_kib": 1002536.4,
-            "write_kib": 262022.5, "fetch_scale": 2.0, "write_scale": 1.0}
+COUNTERS = {"kernel_source_sha256_16": "319cad8cd7de3db4", "fetch_kib": 996909.7,
+            "write_kib": 262022.3, "fetch_scale": 2.0, "write_scale": 1.0}
+
+
+HBM_WORKLOAD = "K32768_sphere8192_fp32"
+HBM_COLUMNS = 32
+HBM_ORDER = 200
+# the same counters for the recursion launch of the HBM point (FP32, 32 columns)
+COUNTERS_HBM = {"kernel_source_sha256_16": "319cad8cd7de3db4", "fetch_kib": 2124355.1, "write_kib": 12298.9,
+                "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def kernel_source_hash():
@@ -72,12 +80,59 @@ def cpu_baseline(cluster, order, beta, n_e, budget_s=30.0):
                       f"C diag(p_N) C^T for all columns, numpy/scipy FP64, {el:.1f} s"}
 
 
+def hbm_point(stream):
+    """The memory-bound point of the recursion: the FP32 operator of the
+    K = 32768 workload streamed against a 32-column block (arithmetic
+    intensity 16 flop/B, below the FP32 ridge of 19.7), timed live with HIP
+    events on the library's stream."""
+    import numpy as np
+    import torch
+
+    import paper_2108_13478_amd as dmlib
+    from synth import WORKLOADS, workload
+
+    w = WORKLOADS[HBM_WORKLOAD]
+    print(f"[bench] building inputs {HBM_WORKLOAD}", file=sys.stderr, flush=True)
+    c = workload(HBM_WORKLOAD)
+    K = c.K
+    ctx = dmlib.Context(device=0, stream=stream.cuda_stream, precision=dmlib.DM_FP32)
+    ctx.set_cluster(c)
+    cols = torch.arange(HBM_COLUMNS, dtype=torch.int64, device="cuda:0")
+    ctx.dm_chebyshev_block(cols, 20, 0.0, w["beta"], None)  # warm-up pass
+    ctx.dm_reset_moments()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.dm_chebyshev_block(cols, HBM_ORDER, 0.0, w["beta"], None)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = e0.elapsed_time(e1) / HBM_ORDER
+    ctx.close()
+    # per launch: the FP32 operator once, U_l, U_{l-1} read and U_{l+1} written
+    # (FP32), Z read (FP64), P read and written (FP64)
+    alg_bytes = 4.0 * K * K + K * HBM_COLUMNS * (3 * 4 + 8 + 16)
+    flops = 2.0 * K * K * HBM_COLUMNS
+    gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = None
+    if kernel_source_hash() == COUNTERS_HBM["kernel_source_sha256_16"]:
+        traffic = 1024.0 * (COUNTERS_HBM["fetch_kib"] * COUNTERS_HBM["fetch_scale"]
+                            + COUNTERS_HBM["write_kib"] * COUNTERS_HBM["write_scale"])
+    return {"workload": HBM_WORKLOAD, "K": K, "columns": HBM_COLUMNS, "steps_timed": HBM_ORDER,
+            "precision": "fp32", "bound": "hbm", "kernel": "cheb_step_kernel<float,2,2,4,1,8,8,true>",
+            "launch_ms": launch_ms, "algorithmic_bytes": alg_bytes, "achieved": gbs, "unit": "GB/s",
+            "peak": PEAK_HBM_GBS, "frac": gbs / PEAK_HBM_GBS, "traffic": traffic,
+            "counter_GBps": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
+            "tflops": flops / (launch_ms * 1e-3) / 1e12}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-point", action="store_true",
+                    help="skip the memory-bound FP32 K=32768 / 32-column measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -176,7 +231,7 @@ def main():
                    "nnz_per_row_F_S": [round(x, 1) for x in c.nnz_per_row]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "cheb_step_kernel<double,4,4,2,2,4,4>", "launch_ms": launch_ms,
+                     "kernel": "cheb_step_kernel<double,4,4,2,2,4,4,false>", "launch_ms": launch_ms,
                      "algorithmic_bytes": alg_bytes,
                      "algorithmic_GBps": alg_bytes / (launch_ms * 1e-3) / 1e9,
                      "counter_GBps": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
@@ -186,6 +241,8 @@ def main():
         "band_energy": state["eband"],
     }
     ctx.close()
+    if not args.no_hbm_point:
+        out["hbm_point"] = hbm_point(stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(c, order, beta, n_e)
