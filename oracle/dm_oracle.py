@@ -41,6 +41,12 @@ import scipy.fft
 import scipy.linalg
 
 __all__ = [
+    "gaussian",
+    "dos_exact",
+    "gaussian_coefficients",
+    "dos_poly",
+    "jackson_kernel",
+    "kpm_dos",
     "fermi",
     "generalized_eigh",
     "spectral_scale",
@@ -233,3 +239,67 @@ def stochastic_moments(sp, xi, n, emin, emax):
     w = (y * z).sum(axis=1) / xi.shape[1]
     T = chebyshev_T(n, (sp.e - ebar) / de)
     return T @ w
+
+
+# ---------------------------------------------------------------- density of states
+def gaussian(e, sigma):
+    """Normalised Gaussian exp(-e^2 / (2 sigma^2)) / (sqrt(2 pi) sigma)."""
+    e = np.asarray(e, dtype=np.float64)
+    return np.exp(-0.5 * (e / sigma) ** 2) / (np.sqrt(2.0 * np.pi) * sigma)
+
+
+def dos_exact(sp, energies, sigma, spin=2.0):
+    """Broadened density of states g sum_n G_sigma(E - e_n) over the
+    eigenvalues (the DOS function of the water-cluster validation figure,
+    sigma = 0.01 hartree there, g = 2)."""
+    E = np.asarray(energies, dtype=np.float64)
+    return spin * gaussian(E[:, None] - sp.e[None, :], sigma).sum(axis=1)
+
+
+def gaussian_coefficients(E, sigma, emin, emax, N, M=None):
+    """Chebyshev coefficients of x -> G_sigma(E - (Ebar + dE x)) on [-1, 1],
+    from the same node DCT as the Fermi function (M = 4N nodes)."""
+    if M is None:
+        M = 4 * N
+    ebar, de = spectral_scale(emin, emax)
+    th = chebyshev_nodes(M)
+    return chebyshev_coefficients(gaussian(E - (ebar + de * np.cos(th)), sigma), N)
+
+
+def dos_poly(sp, energies, sigma, N, emin, emax, spin=2.0, M=None):
+    """The broadened DOS with the Gaussian truncated to N Chebyshev terms:
+    g sum_n sum_{l<N} c_l(E) T_l(x_n) = g sum_l c_l(E) m_l, i.e. what the
+    moments of an order-N pass give (same reading of order and nodes as for
+    the Fermi function)."""
+    m = moments_from_eigs(sp.e, N, emin, emax)
+    out = []
+    for E in np.asarray(energies, dtype=np.float64):
+        out.append(spin * gaussian_coefficients(E, sigma, emin, emax, N, M) @ m)
+    return np.array(out)
+
+
+def jackson_kernel(N):
+    """Jackson damping factors g_0..g_{N-1} of the kernel polynomial method
+    (Weisse, Wellein, Alvermann and Fehske, Rev. Mod. Phys. 78, 275 (2006)):
+    g_l = [(N - l + 1) cos(pi l / (N+1)) + sin(pi l / (N+1)) cot(pi / (N+1))] / (N+1)."""
+    l = np.arange(N, dtype=np.float64)
+    q = np.pi / (N + 1)
+    return ((N - l + 1) * np.cos(q * l) + np.sin(q * l) / np.tan(q)) / (N + 1)
+
+
+def kpm_dos(sp, energies, N, emin, emax, spin=2.0):
+    """Kernel-polynomial DOS from N moments with the Jackson kernel:
+    rho(E) = g [g_0 m_0 + 2 sum_{l>=1} g_l m_l T_l(x)] / (pi dE sqrt(1 - x^2)),
+    x = (E - Ebar) / dE, zero outside (-1, 1).  Integrates to g K."""
+    ebar, de = spectral_scale(emin, emax)
+    m = moments_from_eigs(sp.e, N, emin, emax)
+    gk = jackson_kernel(N)
+    x = (np.asarray(energies, dtype=np.float64) - ebar) / de
+    inside = np.abs(x) < 1.0
+    xi = np.where(inside, x, 0.0)
+    T = chebyshev_T(N, xi)
+    w = gk * m
+    w[1:] *= 2.0
+    series = np.tensordot(w, T, axes=(0, 0))
+    rho = spin * series / (np.pi * de * np.sqrt(1.0 - xi ** 2))
+    return np.where(inside, rho, 0.0)

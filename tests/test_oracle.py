@@ -274,3 +274,76 @@ def test_stochastic_moments(small):
     # with all K unit vectors the estimate is exact: K * m~ = m
     m = O.moments_from_eigs(sp.e, n, emin, emax)
     assert np.allclose(K * O.stochastic_moments(sp, np.eye(K), n, emin, emax), m, atol=1e-9)
+
+
+# ---------------------------------------------------------------- density of states
+def test_broadened_dos_normalisation_and_single_level(small):
+    """The broadened DOS integrates to g K; one level gives g times a Gaussian
+    centred on it (textbook normal density)."""
+    c, sp = small
+    sigma = 0.3
+    E = np.linspace(sp.e[0] - 12 * sigma, sp.e[-1] + 12 * sigma, 200001)
+    rho = O.dos_exact(sp, E, sigma, spin=2.0)
+    assert abs(np.trapezoid(rho, E) - 2.0 * c.K) < 1e-6 * c.K
+    one = type("Sp", (), {"e": np.array([0.7])})()
+    x = np.array([0.7, 0.7 + sigma, 0.7 - 2 * sigma])
+    ref = 2.0 * np.exp(-0.5 * ((x - 0.7) / sigma) ** 2) / (np.sqrt(2 * np.pi) * sigma)
+    assert np.allclose(O.dos_exact(one, x, sigma), ref, rtol=1e-14)
+
+
+def test_gaussian_coefficients_against_quadrature():
+    """Node-DCT coefficients of the Gaussian agree with direct integrals
+    (2/pi) int_0^pi G(E - Ebar - dE cos t) cos(l t) dt (halved for l = 0)."""
+    from scipy.integrate import quad
+
+    emin, emax, sigma, N = -3.0, 5.0, 0.4, 60
+    ebar, de = 1.0, 4.0
+    for E in (-1.2, 0.5, 3.9):
+        a = O.gaussian_coefficients(E, sigma, emin, emax, N)
+        for l in (0, 1, 7, 30):
+            v = quad(lambda t: O.gaussian(E - ebar - de * np.cos(t), sigma) * np.cos(l * t), 0, np.pi,
+                     limit=400, epsabs=1e-13)[0] * 2 / np.pi
+            if l == 0:
+                v *= 0.5
+            assert abs(a[l] - v) < 1e-11
+
+
+def test_truncated_dos_converges_to_broadened(small):
+    """With N far above dE / sigma the truncated Gaussian is exact to rounding."""
+    c, sp = small
+    w = sp.e[-1] - sp.e[0]
+    emin, emax = sp.e[0] - 0.01 * w, sp.e[-1] + 0.01 * w
+    sigma = 0.05 * (emax - emin) / 2
+    E = np.linspace(emin, emax, 37)
+    ref = O.dos_exact(sp, E, sigma)
+    got = O.dos_poly(sp, E, sigma, 400, emin, emax)
+    assert np.abs(got - ref).max() < 1e-9 * ref.max()
+    coarse = O.dos_poly(sp, E, sigma, 20, emin, emax)
+    assert np.abs(coarse - ref).max() > 1e-3 * ref.max()  # too few terms: visibly different
+
+
+def test_jackson_kernel_and_kpm_dos_properties(small):
+    """g_0 = 1 and g_l decreasing to ~0; the KPM DOS is non-negative,
+    integrates to g K, and counts the levels in windows wide compared with
+    its resolution pi dE / N."""
+    c, sp = small
+    N = 400
+    g = O.jackson_kernel(N)
+    assert abs(g[0] - 1.0) < 1e-14 and np.all(np.diff(g) < 0) and g[-1] < 1e-3
+    w = sp.e[-1] - sp.e[0]
+    emin, emax = sp.e[0] - 0.01 * w, sp.e[-1] + 0.01 * w
+    ebar, de = O.spectral_scale(emin, emax)
+    # Gauss-Chebyshev quadrature of rho dE = (g/pi) series dtheta: exact for the polynomial
+    th = O.chebyshev_nodes(4 * N)
+    rho = O.kpm_dos(sp, ebar + de * np.cos(th), N, emin, emax)
+    integral = np.sum(rho * np.pi * de * np.sin(th)) * (np.pi / len(th)) / np.pi
+    assert abs(integral - 2.0 * c.K) < 1e-8 * c.K
+    E = np.linspace(emin, emax, 20001)[1:-1]
+    r = O.kpm_dos(sp, E, N, emin, emax)
+    assert r.min() > -1e-9 * r.max()
+    res = np.pi * de / N
+    edges = np.linspace(sp.e[0] - 5 * res, sp.e[-1] + 5 * res, 5)
+    for a, b in zip(edges[:-1], edges[1:]):
+        sel = (E >= a) & (E < b)
+        count = 2.0 * np.sum((sp.e >= a) & (sp.e < b))
+        assert abs(np.trapezoid(r[sel], E[sel]) - count) < 0.05 * c.K + 2.0
