@@ -136,6 +136,41 @@ dm_status dm_chebyshev_block(dm_ctx* ctx, const long long* cols, long long ncols
  * Errors: DM_E_STATE (no moments), DM_E_ARG. */
 dm_status dm_trace(dm_ctx* ctx, double mu, double beta, double* tr_PS, double* e_band);
 
+/* One recursion pass over `cols` that accumulates n_sets density-matrix
+ * blocks, block q with the coefficients a_l(mu[q], beta[q]) (the supplement's
+ * a_l(T, mu) depend on temperature and chemical potential; the recursion
+ * vectors T_l(H_N) S^-1 u_a do not, so every set shares them).  mu, beta:
+ * host arrays of n_sets values (1 <= n_sets <= DM_MAX_SETS); P_out: host
+ * array of n_sets pointers (host or device, each K x ncols column-major
+ * FP64 as for dm_chebyshev_block, any may be NULL; P_out itself may be
+ * NULL).  Block q equals dm_chebyshev_block with (mu[q], beta[q]) bit for
+ * bit; the moments are accumulated once.  Each extra set adds one FP64 read
+ * and write of the block per step.  Errors as dm_chebyshev_block, and
+ * DM_E_ARG for n_sets out of range or NULL mu / beta. */
+enum { DM_MAX_SETS = 16 };
+dm_status dm_chebyshev_block_multi(dm_ctx* ctx, const long long* cols, long long ncols, int order,
+                                   int n_sets, const double* mu, const double* beta,
+                                   double* const* P_out);
+
+/* Density of states from the accumulated moments (those of all K columns
+ * give the DOS of H), at n energies (host or device in, host or device
+ * out, n values each):
+ * kind DM_DOS_GAUSSIAN: g sum_n G_sigma(E - e_n), the broadened DOS of the
+ *   paper's DOS comparison figure (g the spin option, G_sigma a normalised
+ *   Gaussian, sigma > 0), with the Gaussian expanded in the same N terms and
+ *   4N-node cosine transform as f_FD: g sum_k w_k G_sigma(E - Ebar - dE
+ *   cos theta_k), w_k the trace quadrature weights of the moments.  Accurate
+ *   when N >> dE / sigma;
+ * kind DM_DOS_KPM: the kernel-polynomial estimate with the Jackson kernel
+ *   g_l (Weisse et al., Rev. Mod. Phys. 78, 275 (2006)): g [g_0 m_0 + 2
+ *   sum_{0<l<N} g_l m_l T_l(x)] / (pi dE sqrt(1 - x^2)), x = (E - Ebar)/dE,
+ *   zero outside the spectral interval (sigma ignored).  Non-negative,
+ *   integrates to g K, resolution about pi dE / N.
+ * Errors: DM_E_STATE (no moments), DM_E_ARG (n < 0, NULL arrays with n > 0,
+ * unknown kind, sigma <= 0 for DM_DOS_GAUSSIAN). */
+enum { DM_DOS_GAUSSIAN = 0, DM_DOS_KPM = 1 };
+dm_status dm_dos(dm_ctx* ctx, int kind, int n, const double* energies, double sigma, double* dos);
+
 /* Bisection on [Emin, Emax] for mu with g Tr[P_N(mu) S] = n_e from the
  * accumulated moments (the paper adjusts mu to reproduce N_e through eq. Ne;
  * the method is not stated).  Stops when |g Tr - n_e| <= tol or the bracket

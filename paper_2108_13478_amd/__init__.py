@@ -21,6 +21,8 @@ DM_OK, DM_E_ARG, DM_E_STATE, DM_E_HIP, DM_E_OOM, DM_E_NOTSPD, DM_E_BOUNDS, DM_E_
     0, -1, -2, -3, -4, -5, -6, -7)
 DM_FP64, DM_FP32 = 0, 1
 DM_OP_SINV, DM_OP_H = 0, 1
+DM_DOS_GAUSSIAN, DM_DOS_KPM = 0, 1
+DM_MAX_SETS = 16
 STATUS_NAMES = {0: "DM_OK", -1: "DM_E_ARG", -2: "DM_E_STATE", -3: "DM_E_HIP", -4: "DM_E_OOM",
                 -5: "DM_E_NOTSPD", -6: "DM_E_BOUNDS", -7: "DM_E_NOCONV"}
 
@@ -31,7 +33,8 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_batch_autotune", "dm_batch_stoch_moments", "dm_cheb_order", "dm_mlp_init",
             "dm_mlp_num_params", "dm_mlp_get_params", "dm_mlp_set_params", "dm_mlp_forward",
             "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict",
-            "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape"]
+            "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
+            "dm_dos"]
 
 
 class DMError(RuntimeError):
@@ -102,6 +105,8 @@ def load(path: str = LIB_PATH):
         "dm_set_precision": (_I, [_P, _I]),
         "dm_get_operator": (_I, [_P, _I, _P]),
         "dm_chebyshev_block": (_I, [_P, _P, _LL, _I, _D, _D, _P]),
+        "dm_chebyshev_block_multi": (_I, [_P, _P, _LL, _I, _I, _P, _P, _P]),
+        "dm_dos": (_I, [_P, _I, _I, _P, _D, _P]),
         "dm_trace": (_I, [_P, _D, _D, _P, _P]),
         "dm_solve_mu": (_I, [_P, _D, _D, _D, _P]),
         "dm_moments": (_I, [_P, _P, _I, _P]),
@@ -248,6 +253,40 @@ class Context:
             raise ValueError("P_out too small")
         self._check(self._lib.dm_chebyshev_block(self.h, cp, n, int(order), float(mu), float(beta), pp))
         return P_out
+
+    def dm_chebyshev_block_multi(self, cols, order, mus, betas, P_outs=None):
+        """One pass accumulating len(mus) density-matrix blocks; P_outs: None or
+        a sequence of buffers (or None entries) laid out as for dm_chebyshev_block."""
+        cp, ck = _ptr(cols, np.int64)
+        n = int(len(cols))
+        ns = len(mus)
+        if len(betas) != ns or (P_outs is not None and len(P_outs) != ns):
+            raise ValueError("mus, betas and P_outs must have the same length")
+        mu_a = np.ascontiguousarray(mus, dtype=np.float64)
+        be_a = np.ascontiguousarray(betas, dtype=np.float64)
+        keep = []
+        ptrs = (ctypes.c_void_p * ns)()
+        for q in range(ns):
+            P = None if P_outs is None else P_outs[q]
+            if P is not None:
+                pp, pk = _ptr(P, np.float64)
+                if _numel(pk) < n * self.K:
+                    raise ValueError("P_out too small")
+                keep.append(pk)
+                ptrs[q] = pp.value
+        self._check(self._lib.dm_chebyshev_block_multi(
+            self.h, cp, n, int(order), ns, ctypes.c_void_p(mu_a.ctypes.data), ctypes.c_void_p(be_a.ctypes.data),
+            ptrs if P_outs is not None else None))
+        return P_outs
+
+    def dm_dos(self, kind, energies, sigma=0.0):
+        """Density of states at `energies` from the accumulated moments
+        (DM_DOS_GAUSSIAN with width sigma, or DM_DOS_KPM)."""
+        E = np.ascontiguousarray(energies, dtype=np.float64)
+        out = np.zeros(E.shape[0], dtype=np.float64)
+        self._check(self._lib.dm_dos(self.h, int(kind), int(E.shape[0]), ctypes.c_void_p(E.ctypes.data),
+                                     float(sigma), ctypes.c_void_p(out.ctypes.data)))
+        return out
 
     def dm_trace(self, mu, beta):
         tr, eb = ctypes.c_double(), ctypes.c_double()

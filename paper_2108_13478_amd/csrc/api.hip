@@ -746,15 +746,16 @@ dm_status dm_set_precision(dm_ctx* c, int precision) {
     return normalize(c, c->op);
 }
 
-dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, int order,
-                             double mu, double beta, double* P_out) {
-    if (!c) return DM_E_ARG;
-    dm_status st = enter(c);
-    if (st != DM_OK) return st;
+// One recursion pass over `cols` accumulating nsets density-matrix blocks,
+// set q with the coefficients of (mus[q], betas[q]); the moments are shared.
+static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int order, int nsets,
+                          const double* mus, const double* betas, double* const* P_outs) {
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
     if (order < 2 || order > (1 << 20)) return set_err(c, DM_E_ARG, "order must be >= 2");
-    if (!std::isfinite(mu) || !std::isfinite(beta) || !(beta > 0))
-        return set_err(c, DM_E_ARG, "need finite mu and beta > 0");
+    if (nsets < 1 || nsets > DM_MAX_SETS) return set_err(c, DM_E_ARG, "need 1 <= n_sets <= DM_MAX_SETS");
+    for (int q = 0; q < nsets; ++q)
+        if (!std::isfinite(mus[q]) || !std::isfinite(betas[q]) || !(betas[q] > 0))
+            return set_err(c, DM_E_ARG, "need finite mu and beta > 0");
     if (ncols < 0 || ncols > c->op.K) return set_err(c, DM_E_ARG, "ncols out of range");
     if (ncols > 0 && !cols) return set_err(c, DM_E_ARG, "cols is NULL");
     const long long K = c->op.K;
@@ -779,9 +780,11 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
     if (ncols == 0) return DM_OK;
     const double ebar = 0.5 * (c->op.emax + c->op.emin), de = 0.5 * (c->op.emax - c->op.emin);
     const int M = 4 * order;
-    HIPTRY(c, ensure(c->coef, (size_t)order + 1));
+    const int cstride = order + 1;
+    HIPTRY(c, ensure(c->coef, (size_t)cstride * nsets));
     HIPTRY(c, ensure(c->fk, (size_t)M));
-    HIPTRY(c, cheb_coefficients(order, M, ebar, de, mu, beta, c->fk.p, c->coef.p, s));
+    for (int q = 0; q < nsets; ++q)
+        HIPTRY(c, cheb_coefficients(order, M, ebar, de, mus[q], betas[q], c->fk.p, c->coef.p + (size_t)q * cstride, s));
     HIPTRY(c, fill_i32(c->flag.p, 0, 4, s));
 
     // pass width
@@ -789,7 +792,7 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
     const bool tuned = c->opt.block_width == 0 && c->tuned_width > 0;
     long long bw = c->opt.block_width > 0 ? c->opt.block_width : (tuned ? c->tuned_width : ncols);
     const size_t budget = (size_t)16 << 30;
-    const size_t per_col = (size_t)Kp * (2 * tsz + 16);
+    const size_t per_col = (size_t)Kp * (2 * tsz + 8 + 8 * nsets);
     bw = std::min<long long>(bw, std::max<long long>(128, (long long)(budget / per_col) / 128 * 128));
     bw = std::min(bw, ncols);
     int cfg = pick_cfg(Kp, (int)bw, c->precision);
@@ -802,7 +805,8 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
     HIPTRY(c, ensure(c->Ua, (size_t)Kp * Bp_max * tsz / 8));
     HIPTRY(c, ensure(c->Ub, (size_t)Kp * Bp_max * tsz / 8));
     HIPTRY(c, ensure(c->Z, (size_t)Kp * Bp_max));
-    HIPTRY(c, ensure(c->P, (size_t)Kp * Bp_max));
+    const long long pstride = (long long)Kp * Bp_max;
+    HIPTRY(c, ensure(c->P, (size_t)pstride * nsets));
     HIPTRY(c, ensure(c->cols, (size_t)Bp_max));
     const int nts_step = cheb_num_tiles(Kp, Bp_max, cfg);
     HIPTRY(c, ensure(c->part_steps, (size_t)(order + 1) * nts_step));
@@ -815,8 +819,8 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
         HIPTRY(c, fill_f64(c->Z.p, 0.0, (long long)Kp * Bp, s));
         int nts = 0;
         HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, c->op.Sinv.p, c->op.S_rowptr.p, c->op.S_col.p,
-                             c->op.S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p,
-                             c->part_start.p, &nts, s));
+                             c->op.S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p, nsets,
+                             pstride, cstride, c->part_start.p, &nts, s));
         HIPTRY(c, reduce_moments(0, nts, c->part_start.p, c->mom.p, c->flag.p, s));
         void* ucur = c->Ua.p;
         void* uoth = c->Ub.p;
@@ -829,6 +833,9 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
         a.Z = c->Z.p;
         a.partial = c->part_steps.p;
         a.work = c->work.p;
+        a.nsets = nsets;
+        a.cstride = cstride;
+        a.pstride = pstride;
         const int ntl = cheb_num_tiles(Kp, Bp, cfg);
         for (int l = 1; l <= order; ++l) {
             a.Ucur = ucur;
@@ -842,9 +849,10 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
             std::swap(ucur, uoth);
         }
         HIPTRY(c, reduce_moments(order - 1, ntl, c->part_steps.p + ntl, c->mom.p + 1, c->flag.p, s));
-        if (P_out)
-            HIPTRY(c, hipMemcpy2DAsync(P_out + off * K, (size_t)K * 8, c->P.p, (size_t)Kp * 8,
-                                       (size_t)K * 8, nc, hipMemcpyDefault, s));
+        for (int q = 0; q < nsets; ++q)
+            if (P_outs && P_outs[q])
+                HIPTRY(c, hipMemcpy2DAsync(P_outs[q] + off * K, (size_t)K * 8, c->P.p + (size_t)q * pstride,
+                                           (size_t)Kp * 8, (size_t)K * 8, nc, hipMemcpyDefault, s));
     }
     int flag = 0;
     HIPTRY(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -860,6 +868,27 @@ dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, 
         return set_err(c, DM_E_BOUNDS,
                        "Chebyshev recursion diverged: the spectral interval does not enclose the spectrum");
     return DM_OK;
+}
+
+dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, int order,
+                             double mu, double beta, double* P_out) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    return run_pass(c, cols, ncols, order, 1, &mu, &beta, &P_out);
+}
+
+dm_status dm_chebyshev_block_multi(dm_ctx* c, const long long* cols, long long ncols, int order,
+                                   int n_sets, const double* mu, const double* beta, double* const* P_out) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!mu || !beta) return set_err(c, DM_E_ARG, "mu or beta is NULL");
+    if (n_sets < 1 || n_sets > DM_MAX_SETS) return set_err(c, DM_E_ARG, "need 1 <= n_sets <= DM_MAX_SETS");
+    std::vector<double> hmu(n_sets), hbeta(n_sets);
+    std::copy(mu, mu + n_sets, hmu.begin());
+    std::copy(beta, beta + n_sets, hbeta.begin());
+    return run_pass(c, cols, ncols, order, n_sets, hmu.data(), hbeta.data(), P_out);
 }
 
 static dm_status eval_trace(dm_ctx* c, double beta, double target, double tol, double mu_in,
@@ -904,6 +933,48 @@ dm_status dm_solve_mu(dm_ctx* c, double n_e, double beta, double tol, double* mu
     *mu = out[0];
     if (out[3] == 0.0)
         return set_err(c, DM_E_NOCONV, "bisection bracket collapsed before reaching the tolerance");
+    return DM_OK;
+}
+
+dm_status dm_dos(dm_ctx* c, int kind, int n, const double* energies, double sigma, double* dos) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (n < 0 || (n > 0 && (!energies || !dos))) return set_err(c, DM_E_ARG, "bad energies or output");
+    if (kind != DM_DOS_GAUSSIAN && kind != DM_DOS_KPM) return set_err(c, DM_E_ARG, "unknown DOS kind");
+    if (kind == DM_DOS_GAUSSIAN && !(sigma > 0 && std::isfinite(sigma)))
+        return set_err(c, DM_E_ARG, "need sigma > 0");
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (c->mom_order < 2 || c->ncols_done == 0) return set_err(c, DM_E_STATE, "no accumulated moments");
+    if (n == 0) return DM_OK;
+    hipStream_t s = c->stream;
+    const int N = c->mom_order, M = 4 * N;
+    const double ebar = 0.5 * (c->op.emax + c->op.emin), de = 0.5 * (c->op.emax - c->op.emin);
+    DevBuf<double> Ed, Od;
+    auto rel = [&]() { Ed.release(); Od.release(); };
+    hipError_t e;
+#define DOS(expr)                         \
+    do {                                  \
+        if ((e = (expr)) != hipSuccess) { \
+            rel();                        \
+            return fail_hip(c, e, #expr); \
+        }                                 \
+    } while (0)
+    DOS(ensure(Ed, (size_t)n));
+    DOS(ensure(Od, (size_t)n));
+    DOS(hipMemcpyAsync(Ed.p, energies, (size_t)n * 8, hipMemcpyDefault, s));
+    if (kind == DM_DOS_GAUSSIAN) {
+        DOS(ensure(c->w, (size_t)M));
+        DOS(ensure(c->v, (size_t)M));
+        DOS(trace_weights(N, M, ebar, de, c->mom.p, c->w.p, c->v.p, s));
+        DOS(dos_gauss(n, Ed.p, M, ebar, de, sigma, c->opt.spin, c->w.p, Od.p, s));
+    } else {
+        DOS(dos_kpm(n, Ed.p, N, ebar, de, c->opt.spin, c->mom.p, Od.p, s));
+    }
+    DOS(hipMemcpyAsync(dos, Od.p, (size_t)n * 8, hipMemcpyDefault, s));
+    DOS(hipStreamSynchronize(s));
+#undef DOS
+    rel();
     return DM_OK;
 }
 
@@ -1017,7 +1088,7 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
         AT(fill_f64(Zb.p, 0.0, (long long)Kp * cd.w, s));
         int nts = 0;
         AT(cheb_start(K, Kp, cd.w, nc, colsd.p, c->op.Sinv.p, c->op.S_rowptr.p, c->op.S_col.p, c->op.S_val.p,
-                      c->precision, U0.p, Zb.p, Pb.p, coef.p, pst.p, &nts, s));
+                      c->precision, U0.p, Zb.p, Pb.p, coef.p, 1, 0, 0, pst.p, &nts, s));
         ChebStepArgs a{};
         a.Kp = Kp;
         a.Bp = cd.w;
@@ -1027,6 +1098,7 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
         a.Z = Zb.p;
         a.partial = part.p;
         a.work = work.p;
+        a.nsets = 1;
         void* ucur = U0.p;
         void* uoth = U1.p;
         for (int l = 1; l <= steps + 2; ++l) {
@@ -1153,6 +1225,7 @@ dm_status stoch_moments_op(dm_ctx* c, Op& op, int n_mom, int n_vec, const double
     a.Z = Zs.p;
     a.partial = pss.p;
     a.work = W.p;
+    a.nsets = 1;
     for (int l = 1; l < n_mom; ++l) {
         a.Ucur = ucur;
         a.Uprev = (l == 1) ? nullptr : uoth;
@@ -1262,8 +1335,8 @@ hipError_t batch_start(dm_ctx* c, bool zero_moments) {
         if ((e = fill_f64(b.Z.p, 0.0, (long long)op.Kp * b.Bp, s)) != hipSuccess) return e;
         int nts = 0;
         if ((e = cheb_start((int)op.K, op.Kp, b.Bp, (int)op.K, b.cols.p, op.Sinv.p, op.S_rowptr.p,
-                            op.S_col.p, op.S_val.p, c->precision, b.Ua.p, b.Z.p, b.P.p, b.coef.p,
-                            b.pstart.p, &nts, s)) != hipSuccess)
+                            op.S_col.p, op.S_val.p, c->precision, b.Ua.p, b.Z.p, b.P.p, b.coef.p, 1, 0,
+                            0, b.pstart.p, &nts, s)) != hipSuccess)
             return e;
         if (zero_moments) {
             if ((e = fill_f64(b.mom.p, 0.0, bs.table_order + 1, s)) != hipSuccess) return e;

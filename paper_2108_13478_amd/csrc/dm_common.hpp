@@ -31,7 +31,7 @@ hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, lo
 
 // One step of the Chebyshev column recursion with the fused epilogue:
 //   Unext = alpha * (HN * Ucur) - (has_prev ? Uprev : 0)      (storage T)
-//   P    += coef[l] * Unext                                    (FP64)
+//   P_j  += coef[j * cstride + l] * Unext, j < nsets          (FP64, P_j = P + j * pstride)
 //   partial[l * ntiles + tile] = sum over the tile of Z .* Unext (FP64)
 // HN: Kp x Kp, row-major (row m contiguous); U*, P, Z: Kp x Bp column-major
 // (ld = Kp).  Unext may alias Uprev.  `cfg` selects the tile shape
@@ -54,6 +54,9 @@ struct ChebStepArgs {
     const double* Z;
     double* partial;
     void* work;
+    int nsets;          // coefficient sets / P blocks accumulated in one pass (>= 1)
+    int cstride;        // distance between coefficient sets
+    long long pstride;  // distance between P blocks
 };
 int cheb_num_tile_configs();
 bool cheb_cfg_supports(int cfg, int precision);
@@ -105,13 +108,15 @@ hipError_t cheb_coefficients_devmu(int N, int M, double ebar, double de, const d
                                    double beta, double* fk_scratch, double* a, hipStream_t s);
 
 // U0[:, j] = Sinv[:, cols[j]] (rounded to T), Z[:, j] = column cols[j] of S
-// (from its CSR rows; S is symmetric), P[:, j] = coef[0] * Sinv[:, cols[j]],
-// partial[t] = per-tile sums of Z .* U0 for t < ntiles(start).  Columns
-// j >= ncols are zero.  Z must be zero on entry.
+// (from its CSR rows; S is symmetric), P_s[:, j] = coef[s * cstride] *
+// Sinv[:, cols[j]] for s < nsets (P_s = P + s * pstride), partial[t] =
+// per-tile sums of Z .* U0 for t < ntiles(start).  Columns j >= ncols are
+// zero.  Z must be zero on entry.
 hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, const double* Sinv,
                       const long long* S_rowptr, const int* S_col, const double* S_val,
                       int precision, void* U0, double* Z, double* P, const double* coef,
-                      double* partial, int* ntiles_out, hipStream_t s);
+                      int nsets, long long pstride, int cstride, double* partial, int* ntiles_out,
+                      hipStream_t s);
 
 // Start block from caller vectors: U0 = X (rounded to T), Z = X * zscale.
 hipError_t cheb_start_vectors(int K, int Kp, int Bp, int nvec, const double* X, double zscale,
@@ -137,6 +142,15 @@ hipError_t coef_tail_order(int n, int max_order, const double* a, double tol, in
 // band energy): w_k, v_k for k < M.
 hipError_t trace_weights(int N, int M, double ebar, double de, const double* m, double* w,
                          double* v, hipStream_t s);
+
+// Density of states at n energies E (device): broadened,
+// out_i = scale sum_k w_k G_sigma(E_i - ebar - de cos theta_k) over the M
+// trace weights w; kernel-polynomial (Jackson kernel) from the moments
+// m[0..N), out_i = scale [g_0 m_0 + 2 sum g_l m_l T_l(x_i)] / (pi de sqrt(1-x_i^2)).
+hipError_t dos_gauss(int n, const double* E, int M, double ebar, double de, double sigma, double scale,
+                     const double* w, double* out, hipStream_t s);
+hipError_t dos_kpm(int n, const double* E, int N, double ebar, double de, double scale, const double* m,
+                   double* out, hipStream_t s);
 
 // Single-workgroup bisection/evaluation over the weights.  With max_iter = 0
 // evaluates at mu_in.  out[0] = mu, out[1] = Tr[PS], out[2] = Tr[PF] (no spin),

@@ -317,7 +317,7 @@ cheb_step_kernel(ChebStepArgs a) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
     const T alpha = static_cast<T>(a.alpha);
-    const double c = a.coef[a.l];
+    const double c0 = a.coef[a.l];
     const T* Uprev = static_cast<const T*>(a.Uprev);
     T* Unext = static_cast<T*>(a.Unext);
     double msum = 0.0;
@@ -332,9 +332,16 @@ cheb_step_kernel(ChebStepArgs a) {
             const double4_t z = *reinterpret_cast<const double4_t*>(a.Z + idx);
             double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
             msum += z[0] * od[0] + z[1] * od[1] + z[2] * od[2] + z[3] * od[3];
-            if (c != 0.0) {
+            if (c0 != 0.0) {
                 double4_t* p = reinterpret_cast<double4_t*>(a.P + idx);
-                *p = *p + c * od;
+                *p = *p + c0 * od;
+            }
+            for (int q = 1; q < a.nsets; ++q) {
+                const double c = a.coef[q * a.cstride + a.l];
+                if (c != 0.0) {
+                    double4_t* p = reinterpret_cast<double4_t*>(a.P + q * a.pstride + idx);
+                    *p = *p + c * od;
+                }
             }
         }
 #pragma unroll
@@ -403,10 +410,12 @@ __global__ void __launch_bounds__(256) cheb_combine_kernel(ChebStepArgs a) {
     const double4_t z = *reinterpret_cast<const double4_t*>(a.Z + idx);
     double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
     double msum = z[0] * od[0] + z[1] * od[1] + z[2] * od[2] + z[3] * od[3];
-    const double c = a.coef[a.l];
-    if (c != 0.0) {
-        double4_t* p = reinterpret_cast<double4_t*>(a.P + idx);
-        *p = *p + c * od;
+    for (int q = 0; q < a.nsets; ++q) {
+        const double c = a.coef[q * a.cstride + a.l];
+        if (c != 0.0) {
+            double4_t* p = reinterpret_cast<double4_t*>(a.P + q * a.pstride + idx);
+            *p = *p + c * od;
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) msum += __shfl_xor(msum, off, 64);

@@ -152,13 +152,12 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 cheb_start_kernel(int K, int Kp, int Bp, int ncols, const long long* __restrict__ cols,
                   const double* __restrict__ Sinv, T* __restrict__ U0, double* __restrict__ P,
-                  const double* __restrict__ Z, const double* __restrict__ coef,
-                  double* __restrict__ partial) {
+                  const double* __restrict__ Z, const double* __restrict__ coef, int nsets,
+                  long long pstride, int cstride, double* __restrict__ partial) {
     const int ntr = Kp / kStartRows;
     const int tr = blockIdx.x % ntr, tc = blockIdx.x / ntr;
     const int r0 = tr * kStartRows + 4 * (threadIdx.x & 15);
     const int j = tc * kStartCols + (threadIdx.x >> 4);
-    const double a0 = coef[0];
     double msum = 0.0;
     const long idx = (long)r0 + (long)j * Kp;
     if (j < ncols) {
@@ -166,13 +165,13 @@ cheb_start_kernel(int K, int Kp, int Bp, int ncols, const long long* __restrict_
         for (int i = 0; i < 4; ++i) {
             const double u = src[i];
             U0[idx + i] = static_cast<T>(u);
-            P[idx + i] = a0 * u;
+            for (int q = 0; q < nsets; ++q) P[q * pstride + idx + i] = coef[q * cstride] * u;
             msum += Z[idx + i] * static_cast<double>(static_cast<T>(u));
         }
     } else {
         for (int i = 0; i < 4; ++i) {
             U0[idx + i] = static_cast<T>(0);
-            P[idx + i] = 0.0;
+            for (int q = 0; q < nsets; ++q) P[q * pstride + idx + i] = 0.0;
         }
     }
     __shared__ double red[4];
@@ -285,6 +284,55 @@ __global__ void __launch_bounds__(256) trace_weights_kernel(int N, int M, double
         w[k] = sw / M;
         v[k] = sv / M;
     }
+}
+
+
+// Broadened density of states from the trace quadrature weights:
+// out_i = scale sum_k w_k G_sigma(E_i - ebar - de cos theta_k), G_sigma the
+// normalised Gaussian.  One workgroup per energy, fixed summation order.
+__global__ void __launch_bounds__(256) dos_gauss_kernel(int n, const double* __restrict__ E, int M,
+                                                        double ebar, double de, double sigma,
+                                                        double scale, const double* __restrict__ w,
+                                                        double* __restrict__ out) {
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const double e = E[i];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < M; k += 256) {
+        const double d = (e - ebar - de * cos(kPi * (k + 0.5) / M)) / sigma;
+        s += w[k] * exp(-0.5 * d * d);
+    }
+    __shared__ double red[4];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) out[i] = scale * s / (sqrt(2.0 * kPi) * sigma);
+}
+
+// Kernel-polynomial density of states with the Jackson kernel
+// g_l = [(N - l + 1) cos(q l) + sin(q l) cot q] / (N + 1), q = pi / (N + 1):
+// out_i = scale [g_0 m_0 + 2 sum_{0<l<N} g_l m_l cos(l acos x)] / (pi de sqrt(1 - x^2)),
+// x = (E_i - ebar) / de, zero for |x| >= 1.  One workgroup per energy.
+__global__ void __launch_bounds__(256) dos_kpm_kernel(int n, const double* __restrict__ E, int N,
+                                                      double ebar, double de, double scale,
+                                                      const double* __restrict__ m,
+                                                      double* __restrict__ out) {
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const double x = (E[i] - ebar) / de;
+    if (!(fabs(x) < 1.0)) {
+        if (threadIdx.x == 0) out[i] = 0.0;
+        return;
+    }
+    const double th = acos(x);
+    const double q = kPi / (N + 1);
+    const double cotq = cos(q) / sin(q);
+    double s = 0.0;
+    for (int l = threadIdx.x; l < N; l += 256) {
+        const double g = ((N - l + 1) * cos(q * l) + sin(q * l) * cotq) / (N + 1);
+        s += (l == 0 ? 1.0 : 2.0) * g * m[l] * cos(l * th);
+    }
+    __shared__ double red[4];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) out[i] = scale * s / (kPi * de * sqrt(1.0 - x * x));
 }
 
 __global__ void __launch_bounds__(1024)
@@ -485,7 +533,9 @@ hipError_t normalize_operator(int K, int Kp, const double* HT, double ebar, doub
 hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, const double* Sinv,
                       const long long* S_rowptr, const int* S_col, const double* S_val,
                       int precision, void* U0, double* Z, double* P, const double* coef,
-                      double* partial, int* ntiles_out, hipStream_t s) {
+                      int nsets, long long pstride, int cstride, double* partial, int* ntiles_out,
+                      hipStream_t s) {
+    if (nsets < 1) return hipErrorInvalidValue;
     if (Kp % kStartRows || Bp % kStartCols) return hipErrorInvalidValue;
     if (ncols > 0)
         hipLaunchKernelGGL(scatter_s_columns_kernel, dim3((ncols + 3) / 4), dim3(256), 0, s, Kp,
@@ -493,10 +543,12 @@ hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, c
     const int ntiles = (Kp / kStartRows) * (Bp / kStartCols);
     if (precision == 0)
         hipLaunchKernelGGL(cheb_start_kernel<double>, dim3(ntiles), dim3(256), 0, s, K, Kp, Bp,
-                           ncols, cols, Sinv, static_cast<double*>(U0), P, Z, coef, partial);
+                           ncols, cols, Sinv, static_cast<double*>(U0), P, Z, coef, nsets, pstride, cstride,
+                           partial);
     else
         hipLaunchKernelGGL(cheb_start_kernel<float>, dim3(ntiles), dim3(256), 0, s, K, Kp, Bp,
-                           ncols, cols, Sinv, static_cast<float*>(U0), P, Z, coef, partial);
+                           ncols, cols, Sinv, static_cast<float*>(U0), P, Z, coef, nsets, pstride, cstride,
+                           partial);
     *ntiles_out = ntiles;
     return hipGetLastError();
 }
@@ -536,6 +588,20 @@ hipError_t cheb_coefficients_devmu(int N, int M, double ebar, double de, const d
     hipLaunchKernelGGL(fermi_at_nodes_kernel, dim3((M + 255) / 256), dim3(256), 0, s, M, ebar, de,
                        0.0, mu_dev, beta, fk_scratch);
     hipLaunchKernelGGL(dct_coefficients_kernel, dim3(N + 1), dim3(256), 0, s, N, M, fk_scratch, a);
+    return hipGetLastError();
+}
+
+hipError_t dos_gauss(int n, const double* E, int M, double ebar, double de, double sigma, double scale,
+                     const double* w, double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dos_gauss_kernel, dim3(n), dim3(256), 0, s, n, E, M, ebar, de, sigma, scale, w, out);
+    return hipGetLastError();
+}
+
+hipError_t dos_kpm(int n, const double* E, int N, double ebar, double de, double scale, const double* m,
+                   double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dos_kpm_kernel, dim3(n), dim3(256), 0, s, n, E, N, ebar, de, scale, m, out);
     return hipGetLastError();
 }
 

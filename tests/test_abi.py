@@ -73,3 +73,8 @@ def test_tile_shape_table_without_hip(lib):
     assert lib.dm_tile_shape(len(shapes), None, None, None) == dmlib.DM_E_ARG
     assert lib.dm_tile_shape(-1, None, None, None) == dmlib.DM_E_ARG
     assert lib.dm_set_pass_shape(None, 32, 0) == dmlib.DM_E_ARG
+
+
+def test_multi_and_dos_reject_null_context(lib):
+    assert lib.dm_chebyshev_block_multi(None, None, 0, 10, 1, None, None, None) == dmlib.DM_E_ARG
+    assert lib.dm_dos(None, 0, 0, None, 1.0, None) == dmlib.DM_E_ARG
