@@ -41,6 +41,7 @@ import scipy.fft
 import scipy.linalg
 
 __all__ = [
+    "stochastic_moments_symmetric",
     "gaussian",
     "dos_exact",
     "gaussian_coefficients",
@@ -303,3 +304,21 @@ def kpm_dos(sp, energies, N, emin, emax, spin=2.0):
     series = np.tensordot(w, T, axes=(0, 0))
     rho = spin * series / (np.pi * de * np.sqrt(1.0 - xi ** 2))
     return np.where(inside, rho, 0.0)
+
+
+def stochastic_moments_symmetric(sp, xi, n, emin, emax):
+    """(1/Ns) sum_s xi_s^T T_l(H~_N) xi_s for the symmetric operator
+    H~ = L F L^T, L = U^-T, S = U^T U (U upper Cholesky factor).
+
+    With F C = S C diag(e), C^T S C = I, the columns of W = U C are
+    orthonormal eigenvectors of H~ (H~ W = L F C = L S C diag(e) = W diag(e)),
+    so xi^T T_l(H~_N) xi = sum_i (W^T xi)_i^2 T_l(x_i).
+    """
+    import scipy.linalg
+
+    ebar, de = spectral_scale(emin, emax)
+    U = scipy.linalg.cholesky(sp.S, lower=False)
+    y = (U @ sp.C).T @ xi
+    w = (y * y).sum(axis=1) / xi.shape[1]
+    T = chebyshev_T(n, (sp.e - ebar) / de)
+    return T @ w

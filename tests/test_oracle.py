@@ -347,3 +347,37 @@ def test_jackson_kernel_and_kpm_dos_properties(small):
         sel = (E >= a) & (E < b)
         count = 2.0 * np.sum((sp.e >= a) & (sp.e < b))
         assert abs(np.trapezoid(r[sel], E[sel]) - count) < 0.05 * c.K + 2.0
+
+
+def test_symmetric_form_eigenvalues_and_stochastic_moments(small):
+    """H~ = L F L^T (L = U^-T, S = U^T U) has the generalized eigenvalues of
+    (F, S); xi^T T_l(H~_N) xi by the matrix recursion on the explicitly formed
+    H~ matches the oracle, and all K unit vectors give the exact moments."""
+    import scipy.linalg
+
+    c, sp = small
+    F, S = c.F_dense(), c.S_dense()
+    K = c.K
+    U = scipy.linalg.cholesky(S, lower=False)
+    L = np.linalg.inv(U).T
+    Hs = L @ F @ L.T
+    assert np.allclose(np.linalg.eigvalsh(0.5 * (Hs + Hs.T)), sp.e, atol=1e-9 * np.abs(sp.e).max())
+    emin, emax = sp.e[0] - 0.5, sp.e[-1] + 0.5
+    ebar, de = 0.5 * (emax + emin), 0.5 * (emax - emin)
+    HN = (Hs - ebar * np.eye(K)) / de
+    xi = rademacher(K, 5, 3)
+    n = 16
+    ms = O.stochastic_moments_symmetric(sp, xi, n, emin, emax)
+    T0, T1 = np.eye(K), HN.copy()
+    ref = [np.einsum("is,ij,js->", xi, T0, xi) / 5, np.einsum("is,ij,js->", xi, T1, xi) / 5]
+    for _ in range(2, n):
+        T0, T1 = T1, 2.0 * HN @ T1 - T0
+        ref.append(np.einsum("is,ij,js->", xi, T1, xi) / 5)
+    assert np.allclose(ms, ref, atol=1e-8)
+    m = O.moments_from_eigs(sp.e, n, emin, emax)
+    assert np.allclose(K * O.stochastic_moments_symmetric(sp, np.eye(K), n, emin, emax), m, atol=1e-9)
+    # P = L^T f(H~) L is the same density matrix as C f(e) C^T
+    w, V = np.linalg.eigh(0.5 * (Hs + Hs.T))
+    fw = O.fermi(w, 0.3, 5.0)
+    P_sym = L.T @ (V * fw) @ V.T @ L
+    assert np.allclose(P_sym, O.density_matrix_exact(sp, np.arange(K), 0.3, 5.0), atol=1e-9)
