@@ -104,10 +104,30 @@ dm_status dm_set_bounds(dm_ctx* ctx, double emin, double emax);
 
 /* Copy a setup product to out (host or device, K x K FP64 column-major):
  * which = DM_OP_SINV: S^-1 (the start vectors U_0 = S^-1 u_a are its columns);
- * which = DM_OP_H: H = S^-1 F (supplement "Chebyshev expansion").
- * Errors: DM_E_STATE (no Fock matrix), DM_E_ARG. */
-enum { DM_OP_SINV = 0, DM_OP_H = 1 };
+ * which = DM_OP_H: H = S^-1 F (supplement "Chebyshev expansion");
+ * which = DM_OP_HSYM: H~ = L F L^T, L = U^-T, S = U^T U (symmetric form only).
+ * Errors: DM_E_STATE (no Fock matrix; DM_OP_HSYM of a general-form operator),
+ * DM_E_ARG. */
+enum { DM_OP_SINV = 0, DM_OP_H = 1, DM_OP_HSYM = 2 };
 dm_status dm_get_operator(dm_ctx* ctx, int which, double* out);
+
+/* Operator form of the recursion for the Fock matrices loaded afterwards by
+ * dm_set_fock (an operator already loaded keeps its form):
+ * DM_FORM_GENERAL (default): the recursion runs on H = S^-1 F as in the
+ *   supplement's eq. ChebychevExpansion, from U_0 = S^-1 u_a;
+ * DM_FORM_SYMMETRIC: with the Cholesky factor S = U^T U and L = U^-T it runs
+ *   on the symmetric H~ = L F L^T (same spectrum: H = U^-1 H~ U), from
+ *   V_0 = L u_a, and each pass ends with one FP64 product P u_a =
+ *   L^T sum_l a_l V_l, which is the same P = f(S^-1 F) S^-1 (eq. RDM) since
+ *   f(H) S^-1 = L^T f(H~) L.  T_l(H~_N) has norm <= 1, so FP32 rounding in
+ *   the recursion is not amplified as with the non-normal S^-1 F.  The
+ *   moments use z_a = U u_a (u_a^T S T_l(H) S^-1 u_a = (U u_a)^T T_l(H~) L u_a),
+ *   so traces, mu and the DOS are unchanged; dm_stoch_moments probes H~.
+ *   Costs two K x K FP64 arrays (L, U) and H~ (FP64) more, and K^3 more
+ *   setup flops.  The batch entry points always use the general form.
+ * Errors: DM_E_ARG (unknown form). */
+enum { DM_FORM_GENERAL = 0, DM_FORM_SYMMETRIC = 1 };
+dm_status dm_set_operator_form(dm_ctx* ctx, int form);
 
 /* Switch the recursion precision (DM_FP64 / DM_FP32) of a loaded operator;
  * resets the accumulated moments. */

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libdm.so")
 DM_OK, DM_E_ARG, DM_E_STATE, DM_E_HIP, DM_E_OOM, DM_E_NOTSPD, DM_E_BOUNDS, DM_E_NOCONV = (
     0, -1, -2, -3, -4, -5, -6, -7)
 DM_FP64, DM_FP32 = 0, 1
-DM_OP_SINV, DM_OP_H = 0, 1
+DM_OP_SINV, DM_OP_H, DM_OP_HSYM = 0, 1, 2
+DM_FORM_GENERAL, DM_FORM_SYMMETRIC = 0, 1
 DM_DOS_GAUSSIAN, DM_DOS_KPM = 0, 1
 DM_MAX_SETS = 16
 STATUS_NAMES = {0: "DM_OK", -1: "DM_E_ARG", -2: "DM_E_STATE", -3: "DM_E_HIP", -4: "DM_E_OOM",
@@ -34,7 +35,7 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_mlp_num_params", "dm_mlp_get_params", "dm_mlp_set_params", "dm_mlp_forward",
             "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict",
             "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
-            "dm_dos"]
+            "dm_dos", "dm_set_operator_form"]
 
 
 class DMError(RuntimeError):
@@ -107,6 +108,7 @@ def load(path: str = LIB_PATH):
         "dm_chebyshev_block": (_I, [_P, _P, _LL, _I, _D, _D, _P]),
         "dm_chebyshev_block_multi": (_I, [_P, _P, _LL, _I, _I, _P, _P, _P]),
         "dm_dos": (_I, [_P, _I, _I, _P, _D, _P]),
+        "dm_set_operator_form": (_I, [_P, _I]),
         "dm_trace": (_I, [_P, _D, _D, _P, _P]),
         "dm_solve_mu": (_I, [_P, _D, _D, _D, _P]),
         "dm_moments": (_I, [_P, _P, _I, _P]),
@@ -326,6 +328,10 @@ class Context:
         self._check(self._lib.dm_autotune(self.h, int(ncols), int(steps), ctypes.c_void_p(table.ctypes.data),
                                           ctypes.byref(n), ctypes.byref(bw), ctypes.byref(bc)))
         return bw.value, bc.value, table[:min(n.value, cap)].copy()
+
+    def dm_set_operator_form(self, form):
+        """DM_FORM_GENERAL or DM_FORM_SYMMETRIC, for Fock matrices loaded afterwards."""
+        self._check(self._lib.dm_set_operator_form(self.h, int(form)))
 
     def dm_set_pass_shape(self, width, cfg):
         self._check(self._lib.dm_set_pass_shape(self.h, int(width), int(cfg)))

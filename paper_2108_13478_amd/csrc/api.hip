@@ -48,10 +48,14 @@ struct Op {
     DevBuf<double> Sinv;   // Kp x Kp, S^-1
     DevBuf<double> HT;     // Kp x Kp, (S^-1 F)^T column-major = H row-major
     DevBuf<double> HNbuf;  // Kp x Kp of the recursion precision (FP64 slots reused for FP32)
+    // symmetric form (DM_FORM_SYMMETRIC): S = U^T U, L = U^-T, Hsym = L F L^T
+    int form = DM_FORM_GENERAL;
+    DevBuf<double> Lsym, Usym, Hsym;
     void release() {
         S_rowptr.release(); S_col.release(); S_val.release();
         Sinv.release(); HT.release(); HNbuf.release();
-        K = 0; Kp = 0;
+        Lsym.release(); Usym.release(); Hsym.release();
+        K = 0; Kp = 0; form = DM_FORM_GENERAL;
     }
 };
 
@@ -82,11 +86,14 @@ struct dm_ctx {
     // pass width and tile shape chosen by dm_autotune (0 / -1: none)
     int tuned_width = 0;
     int tuned_cfg = -1;
+    // operator form used by the next dm_set_fock
+    int form = DM_FORM_GENERAL;
 
     // workspace
     DevBuf<double> Ua, Ub, Z, P;  // sized in bytes via double slots
     DevBuf<double> part_start, part_steps;
     DevBuf<double> work;  // partial products of the split-reduction shapes (byte size via double slots)
+    DevBuf<double> Pfin;  // symmetric form: P = L^T Q of one pass
     DevBuf<double> coef, coef_zero, fk, w, v, out;
     DevBuf<int> flag;
     DevBuf<long long> cols;
@@ -390,7 +397,8 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
 
 dm_status normalize(dm_ctx* c, Op& op) {
     const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
-    HIPTRY(c, normalize_operator((int)op.K, op.Kp, op.HT.p, ebar, de, c->precision, op.HNbuf.p, c->stream));
+    const double* H = op.form == DM_FORM_SYMMETRIC ? op.Hsym.p : op.HT.p;  // both row-major
+    HIPTRY(c, normalize_operator((int)op.K, op.Kp, H, ebar, de, c->precision, op.HNbuf.p, c->stream));
     return DM_OK;
 }
 
@@ -468,7 +476,7 @@ dm_status load_csr_pair(dm_ctx* c, long long K, const long long* F_rowptr, const
 }
 
 // Operator setup for one (F, S): S = U^T U, S^-1, H^T, Lanczos interval, H_N.
-dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const HostCsr& Sh) {
+dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const HostCsr& Sh, int form) {
     const std::vector<long long>& frp = Fh.rp;
     const std::vector<int>& fcol = Fh.col;
     const std::vector<double>& fval = Fh.val;
@@ -489,8 +497,15 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
     HIPTRY(c, hipMemcpyAsync(op.S_val.p, sval.data(), sval.size() * 8, hipMemcpyHostToDevice, s));
     DevBuf<long long> Frp;
     DevBuf<int> Fci;
-    DevBuf<double> Fv, Vblk, tmp;
-    auto release_tmp = [&]() { Frp.release(); Fci.release(); Fv.release(); Vblk.release(); tmp.release(); };
+    DevBuf<double> Fv, Vblk, tmp, G;
+    auto release_tmp = [&]() { Frp.release(); Fci.release(); Fv.release(); Vblk.release(); tmp.release(); G.release(); };
+    const bool sym = form == DM_FORM_SYMMETRIC;
+    op.form = DM_FORM_GENERAL;
+    if (!sym) {
+        op.Lsym.release();
+        op.Usym.release();
+        op.Hsym.release();
+    }
     hipError_t e;
 #define ST(expr)                          \
     do {                                  \
@@ -540,6 +555,10 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
         return set_err(c, DM_E_NOTSPD, "overlap matrix is not positive definite (pivot " +
                                            std::to_string(info[0] - 1) + ")");
     }
+    if (sym) {
+        ST(ensure(op.Usym, KK));
+        ST(copy_upper(Kp, A, op.Usym.p, s));
+    }
     // ---- X = U^-T (lower) by block forward substitution
     ST(fill_f64(X, 0.0, (long long)KK, s));
     for (int k = 0; k < Kp; k += kNb) {
@@ -550,16 +569,31 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
         }
         ST(copy_transpose_block(Vk, kNb, X + k + (long)k * ld, ld, s));
     }
+    if (sym) {
+        ST(ensure(op.Lsym, KK));
+        ST(hipMemcpyAsync(op.Lsym.p, X, KK * 8, hipMemcpyDeviceToDevice, s));
+    }
     // ---- S^-1 = X^T X, then A := F and H^T = F S^-1
     ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, X, ld, X, ld, 0.0, op.Sinv.p, ld, false, s));
     ST(fill_f64(A, 0.0, (long long)KK, s));
     ST(csr_to_dense((int)K, Kp, Frp.p, Fci.p, Fv.p, 0.0, A, s));
     ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, A, ld, op.Sinv.p, ld, 0.0, X, ld, false, s));
+    if (sym) {
+        // W = L^T (column-major) in Hsym, G = F L^T, Hsym := W^T G = L F L^T
+        // (symmetric, so its column-major and row-major layouts coincide)
+        ST(ensure(op.Hsym, KK));
+        ST(ensure(G, KK));
+        ST(transpose_square(Kp, op.Lsym.p, op.Hsym.p, s));
+        ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, A, ld, op.Hsym.p, ld, 0.0, G.p, ld, false, s));
+        ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, op.Hsym.p, ld, G.p, ld, 0.0, A, ld, false, s));
+        ST(hipMemcpyAsync(op.Hsym.p, A, KK * 8, hipMemcpyDeviceToDevice, s));
+    }
     ST(hipStreamSynchronize(s));
     release_tmp();
 #undef ST
     dm_status st = lanczos_bounds(c, op);
     if (st != DM_OK) return st;
+    op.form = sym ? DM_FORM_SYMMETRIC : DM_FORM_GENERAL;
     return normalize(c, op);
 }
 
@@ -641,8 +675,8 @@ void dm_destroy(dm_ctx* c) {
     (void)hipSetDevice(c->opt.device);
     if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
     for (auto* b : {&c->op.Sinv, &c->op.HT, &c->op.HNbuf, &c->op.S_val, &c->mom, &c->Ua, &c->Ub, &c->Z, &c->P,
-                    &c->part_start, &c->part_steps, &c->work, &c->coef, &c->coef_zero, &c->fk, &c->w,
-                    &c->v, &c->out})
+                    &c->part_start, &c->part_steps, &c->work, &c->Pfin, &c->coef, &c->coef_zero, &c->fk,
+                    &c->w, &c->v, &c->out})
         b->release();
     c->op.release();
     for (auto& o : c->batch) o.release();
@@ -676,7 +710,7 @@ dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const i
     HostCsr Fh, Sh;
     st = load_csr_pair(c, K, F_rowptr, F_col, F_val, S_rowptr, S_col, S_val, Fh, Sh);
     if (st != DM_OK) return st;
-    st = build_op(c, c->op, K, Fh, Sh);
+    st = build_op(c, c->op, K, Fh, Sh, c->form);
     if (st != DM_OK) return st;
     c->have_fock = true;
     return DM_OK;
@@ -705,16 +739,29 @@ dm_status dm_set_bounds(dm_ctx* c, double emin, double emax) {
     return normalize(c, c->op);
 }
 
+dm_status dm_set_operator_form(dm_ctx* c, int form) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (form != DM_FORM_GENERAL && form != DM_FORM_SYMMETRIC) return set_err(c, DM_E_ARG, "unknown operator form");
+    c->form = form;
+    return DM_OK;
+}
+
 dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
-    if (!out || (which != DM_OP_SINV && which != DM_OP_H)) return set_err(c, DM_E_ARG, "bad operator request");
+    if (!out || (which != DM_OP_SINV && which != DM_OP_H && which != DM_OP_HSYM))
+        return set_err(c, DM_E_ARG, "bad operator request");
+    if (which == DM_OP_HSYM && c->op.form != DM_FORM_SYMMETRIC)
+        return set_err(c, DM_E_STATE, "the loaded operator was not built in the symmetric form");
     const size_t K = (size_t)c->op.K, Kp = (size_t)c->op.Kp;
     hipStream_t s = c->stream;
-    if (which == DM_OP_SINV) {
-        HIPTRY(c, hipMemcpy2DAsync(out, K * 8, c->op.Sinv.p, Kp * 8, K * 8, K, hipMemcpyDefault, s));
+    if (which == DM_OP_SINV || which == DM_OP_HSYM) {
+        const double* src = which == DM_OP_SINV ? c->op.Sinv.p : c->op.Hsym.p;
+        HIPTRY(c, hipMemcpy2DAsync(out, K * 8, src, Kp * 8, K * 8, K, hipMemcpyDefault, s));
     } else {
         // HT holds H^T column-major; transpose through a device scratch buffer
         DevBuf<double> t;
@@ -805,8 +852,13 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
     HIPTRY(c, ensure(c->Ua, (size_t)Kp * Bp_max * tsz / 8));
     HIPTRY(c, ensure(c->Ub, (size_t)Kp * Bp_max * tsz / 8));
     HIPTRY(c, ensure(c->Z, (size_t)Kp * Bp_max));
-    const long long pstride = (long long)Kp * Bp_max;
+    // symmetric form: the accumulated blocks are Q = p_N(H~) L u_a, and P = L^T Q
+    // is one FP64 product per pass, over columns padded to 64
+    const bool sym = c->op.form == DM_FORM_SYMMETRIC;
+    const int Bpad = sym ? (int)round_up(Bp_max, 64) : Bp_max;
+    const long long pstride = (long long)Kp * Bpad;
     HIPTRY(c, ensure(c->P, (size_t)pstride * nsets));
+    if (sym) HIPTRY(c, ensure(c->Pfin, (size_t)pstride));
     HIPTRY(c, ensure(c->cols, (size_t)Bp_max));
     const int nts_step = cheb_num_tiles(Kp, Bp_max, cfg);
     HIPTRY(c, ensure(c->part_steps, (size_t)(order + 1) * nts_step));
@@ -818,9 +870,9 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
         HIPTRY(c, hipMemcpyAsync(c->cols.p, hc.data() + off, (size_t)nc * 8, hipMemcpyHostToDevice, s));
         HIPTRY(c, fill_f64(c->Z.p, 0.0, (long long)Kp * Bp, s));
         int nts = 0;
-        HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, c->op.Sinv.p, c->op.S_rowptr.p, c->op.S_col.p,
-                             c->op.S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p, nsets,
-                             pstride, cstride, c->part_start.p, &nts, s));
+        HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, sym ? c->op.Lsym.p : c->op.Sinv.p, c->op.S_rowptr.p,
+                             c->op.S_col.p, c->op.S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p,
+                             nsets, pstride, cstride, c->part_start.p, &nts, s, sym ? c->op.Usym.p : nullptr));
         HIPTRY(c, reduce_moments(0, nts, c->part_start.p, c->mom.p, c->flag.p, s));
         void* ucur = c->Ua.p;
         void* uoth = c->Ub.p;
@@ -849,10 +901,19 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
             std::swap(ucur, uoth);
         }
         HIPTRY(c, reduce_moments(order - 1, ntl, c->part_steps.p + ntl, c->mom.p + 1, c->flag.p, s));
-        for (int q = 0; q < nsets; ++q)
-            if (P_outs && P_outs[q])
-                HIPTRY(c, hipMemcpy2DAsync(P_outs[q] + off * K, (size_t)K * 8, c->P.p + (size_t)q * pstride,
-                                           (size_t)Kp * 8, (size_t)K * 8, nc, hipMemcpyDefault, s));
+        for (int q = 0; q < nsets; ++q) {
+            if (!P_outs || !P_outs[q]) continue;
+            const double* src = c->P.p + (size_t)q * pstride;
+            if (sym) {
+                const int B64 = (int)round_up(Bp, 64);
+                double* Q = c->P.p + (size_t)q * pstride;
+                if (B64 > Bp) HIPTRY(c, fill_f64(Q + (size_t)Kp * Bp, 0.0, (long long)Kp * (B64 - Bp), s));
+                HIPTRY(c, gemm_tn_f64(Kp, B64, Kp, 1.0, c->op.Lsym.p, Kp, Q, Kp, 0.0, c->Pfin.p, Kp, false, s));
+                src = c->Pfin.p;
+            }
+            HIPTRY(c, hipMemcpy2DAsync(P_outs[q] + off * K, (size_t)K * 8, src, (size_t)Kp * 8, (size_t)K * 8, nc,
+                                       hipMemcpyDefault, s));
+        }
     }
     int flag = 0;
     HIPTRY(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1406,7 +1467,7 @@ dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) {
         HostCsr Fh, Sh;
         st = load_csr_pair(c, cl[i].K, cl[i].F_rowptr, cl[i].F_col, cl[i].F_val, cl[i].S_rowptr,
                            cl[i].S_col, cl[i].S_val, Fh, Sh);
-        if (st == DM_OK) st = build_op(c, c->batch[i], cl[i].K, Fh, Sh);
+        if (st == DM_OK) st = build_op(c, c->batch[i], cl[i].K, Fh, Sh, DM_FORM_GENERAL);
         if (st != DM_OK) {
             const std::string m = "cluster " + std::to_string(i) + ": " + c->err;
             for (auto& o : c->batch) o.release();

@@ -108,15 +108,19 @@ hipError_t cheb_coefficients_devmu(int N, int M, double ebar, double de, const d
                                    double beta, double* fk_scratch, double* a, hipStream_t s);
 
 // U0[:, j] = Sinv[:, cols[j]] (rounded to T), Z[:, j] = column cols[j] of S
-// (from its CSR rows; S is symmetric), P_s[:, j] = coef[s * cstride] *
-// Sinv[:, cols[j]] for s < nsets (P_s = P + s * pstride), partial[t] =
-// per-tile sums of Z .* U0 for t < ntiles(start).  Columns j >= ncols are
-// zero.  Z must be zero on entry.
+// (from its CSR rows; S is symmetric) or, with Zdense, Zdense[:, cols[j]],
+// P_s[:, j] = coef[s * cstride] * Sinv[:, cols[j]] for s < nsets (P_s = P +
+// s * pstride), partial[t] = per-tile sums of Z .* U0 for t < ntiles(start).
+// Columns j >= ncols are zero.  Z must be zero on entry.  (The symmetric form
+// passes L for Sinv and U for Zdense.)
 hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, const double* Sinv,
                       const long long* S_rowptr, const int* S_col, const double* S_val,
                       int precision, void* U0, double* Z, double* P, const double* coef,
                       int nsets, long long pstride, int cstride, double* partial, int* ntiles_out,
-                      hipStream_t s);
+                      hipStream_t s, const double* Zdense = nullptr);
+// dst = src^T (Kp x Kp, Kp % 32 == 0); dst = upper triangle of src.
+hipError_t transpose_square(int Kp, const double* src, double* dst, hipStream_t s);
+hipError_t copy_upper(int Kp, const double* src, double* dst, hipStream_t s);
 
 // Start block from caller vectors: U0 = X (rounded to T), Z = X * zscale.
 hipError_t cheb_start_vectors(int K, int Kp, int Bp, int nvec, const double* X, double zscale,

@@ -130,6 +130,41 @@ __global__ void copy_transpose_block_kernel(const double* src, long lds, double*
     }
 }
 
+
+// dst = src^T for Kp x Kp column-major matrices, 32 x 32 tiles through LDS
+// (row padding avoids bank conflicts); block (bx, by) moves tile (bx, by).
+__global__ void __launch_bounds__(256) transpose_kernel(int Kp, const double* __restrict__ src,
+                                                        double* __restrict__ dst) {
+    __shared__ double tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const long r0 = (long)blockIdx.x * 32, c0 = (long)blockIdx.y * 32;
+    for (int j = ty; j < 32; j += 8) tile[j][tx] = src[(r0 + tx) + (c0 + j) * Kp];
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) dst[(c0 + tx) + (r0 + j) * Kp] = tile[tx][j];
+}
+
+// dst = upper triangle of src (column-major), zero below the diagonal.
+__global__ void copy_upper_kernel(int Kp, const double* __restrict__ src, double* __restrict__ dst) {
+    const long long n = (long long)Kp * Kp;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(i % Kp), c = (int)(i / Kp);
+        dst[i] = r <= c ? src[i] : 0.0;
+    }
+}
+
+// Z[:, j] = D[:, cols[j]] for j < ncols (column-major, ld = Kp).
+__global__ void gather_columns_kernel(int Kp, int ncols, const long long* __restrict__ cols,
+                                      const double* __restrict__ D, double* __restrict__ Z) {
+    const long long n = (long long)Kp * ncols;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(i % Kp);
+        const long long j = i / Kp;
+        Z[i] = D[r + cols[j] * (long long)Kp];
+    }
+}
+
 template <typename T>
 __global__ void normalize_operator_kernel(int K, int Kp, const double* __restrict__ HT, double ebar,
                                           double inv_de, T* __restrict__ HN) {
@@ -518,6 +553,17 @@ hipError_t copy_transpose_block(const double* src, long lds, double* dst, long l
     return hipGetLastError();
 }
 
+hipError_t transpose_square(int Kp, const double* src, double* dst, hipStream_t s) {
+    if (Kp % 32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(transpose_kernel, dim3(Kp / 32, Kp / 32), dim3(256), 0, s, Kp, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t copy_upper(int Kp, const double* src, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(copy_upper_kernel, grid_for((long long)Kp * Kp, 256), dim3(256), 0, s, Kp, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t normalize_operator(int K, int Kp, const double* HT, double ebar, double de,
                               int precision, void* HN, hipStream_t s) {
     const long long n = (long long)Kp * Kp;
@@ -534,10 +580,13 @@ hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, c
                       const long long* S_rowptr, const int* S_col, const double* S_val,
                       int precision, void* U0, double* Z, double* P, const double* coef,
                       int nsets, long long pstride, int cstride, double* partial, int* ntiles_out,
-                      hipStream_t s) {
+                      hipStream_t s, const double* Zdense) {
     if (nsets < 1) return hipErrorInvalidValue;
     if (Kp % kStartRows || Bp % kStartCols) return hipErrorInvalidValue;
-    if (ncols > 0)
+    if (ncols > 0 && Zdense)
+        hipLaunchKernelGGL(gather_columns_kernel, grid_for((long long)Kp * ncols, 256), dim3(256), 0, s, Kp,
+                           ncols, cols, Zdense, Z);
+    else if (ncols > 0)
         hipLaunchKernelGGL(scatter_s_columns_kernel, dim3((ncols + 3) / 4), dim3(256), 0, s, Kp,
                            ncols, cols, S_rowptr, S_col, S_val, Z);
     const int ntiles = (Kp / kStartRows) * (Bp / kStartCols);

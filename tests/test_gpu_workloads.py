@@ -82,6 +82,16 @@ def test_k4096_fp32_recursion_error(k4096):
     # FP32 rounding of H_N and U_l, amplified by cond(S) and beta: a relative
     # floor near 1e-5 of max|P| (reported, not a parity claim)
     assert err < 1e-4 * np.abs(ref).max() and abs(tr - tr_ref) < 1e-3 * abs(tr_ref)
+    # the symmetric form L F L^T with the same FP32 recursion
+    sym = dmlib.Context(precision=dmlib.DM_FP32)
+    sym.dm_set_operator_form(dmlib.DM_FORM_SYMMETRIC)
+    sym.set_cluster(c)
+    sym.dm_set_bounds(emin, emax)
+    sym.dm_chebyshev_block(np.arange(c.K, dtype=np.int64), N, mu, beta, P)
+    err_s = np.abs(P.T - ref).max()
+    tr_s, _ = sym.dm_trace(mu, beta)
+    say(f"  FP32 symmetric form: max|dP| = {err_s:.3e}; |dTr[PS]| = {abs(tr_s - tr_ref):.3e}")
+    assert err_s < 0.5 * err
 
 
 def test_k32768_fp32_full_size_sampled_columns():
