@@ -286,7 +286,10 @@ dm_status dm_batch_run(dm_ctx* ctx, int order, double beta, const double* n_e, d
 
 /* Tile shape of the batch kernel: time `steps` recursion steps of the
  * moments pass for each candidate shape on the loaded batch and keep the
- * fastest.  table rows: (cfg, tile rows, tile cols, ms). */
+ * fastest (shapes with two register buffers or three k-slabs in flight,
+ * 128 x 32 .. 128 x 128; cfg is the shape's index as for dm_tile_shape).
+ * table (host, may be NULL) receives up to *ntable rows of (cfg, tile rows,
+ * tile cols, ms); *ntable returns the number of candidates. */
 dm_status dm_batch_autotune(dm_ctx* ctx, int steps, double* table, int* ntable, int* best_cfg);
 
 /* Smallest expansion order N <= max_order whose coefficient tail

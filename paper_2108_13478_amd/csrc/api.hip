@@ -1581,7 +1581,9 @@ dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, in
     HIPTRY(c, hipEventCreate(&e0));
     HIPTRY(c, hipEventCreate(&e1));
     std::vector<std::pair<int, double>> res;
-    for (int cfg = 0; cfg < 4; ++cfg) {
+    for (int ci = 0; ci < cheb_batch_num_cfgs(); ++ci) {
+        const int cfg = cheb_batch_cfg(ci, c->precision);
+        if (cfg < 0) continue;
         st = batch_tables(c, cfg, steps);
         if (st != DM_OK) break;
         for (size_t i = 0; i < c->batch.size(); ++i) HIPTRY(c, fill_f64(bs.cl[i].coef.p, 0.0, steps + 1, s));

@@ -102,6 +102,11 @@ struct BatchArgs {
 hipError_t cheb_batch(const BatchArgs& a, int cfg, int precision, int grid, hipStream_t s);
 // Workgroups of tile shape cfg that fit on one CU at once.
 int cheb_batch_occupancy(int cfg, int precision);
+// The i-th tile shape the batch kernel is built for (an index into the
+// recursion shapes), or -1 when i is out of range or the shape is not built
+// for this precision; i < cheb_batch_num_cfgs().
+int cheb_batch_num_cfgs();
+int cheb_batch_cfg(int i, int precision);
 
 // Chebyshev coefficients with mu read from device memory (mu_dev[0]).
 hipError_t cheb_coefficients_devmu(int N, int M, double ebar, double de, const double* mu_dev,

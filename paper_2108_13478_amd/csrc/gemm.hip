@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(256) cheb_combine_kernel(ChebStepArgs a) {
 }
 
 // ------------------------------------------------------------ persistent batch
-template <typename T, int TM, int TN, int WM, int WN, int KV>
+template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH>
 __global__ void __launch_bounds__(64 * WM * WN)
 cheb_batch_kernel(BatchArgs a) {
     typedef typename Mfma<T>::vec_t vec_t;
@@ -460,7 +460,7 @@ cheb_batch_kernel(BatchArgs a) {
             for (int r0 = 0; r0 < Kp; r0 += BM) {
                 const int row0 = r0 + (wave % WM) * TM * 16;
                 typename Mfma<T>::acc_t acc[TM][TN];
-                gemm_mainloop<T, TM, TN, KV>(Kp, HN, Kp, ucur, Kp, row0, col0, acc);
+                gemm_mainloop<T, TM, TN, KV, DEPTH>(Kp, HN, Kp, ucur, Kp, row0, col0, acc);
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -645,18 +645,21 @@ hipError_t launch_cheb(const ChebStepArgs& a, int cfg, hipStream_t s) {
     }
 }
 
-template <typename T, int TM, int TN, int WM, int WN, int KV>
+template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH = 2>
 hipError_t launch_batch_one(const BatchArgs& a, int grid, hipStream_t s, int* occ) {
     if (occ) {
         *occ = 0;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            occ, reinterpret_cast<const void*>(&cheb_batch_kernel<T, TM, TN, WM, WN, KV>), 64 * WM * WN, 0);
+            occ, reinterpret_cast<const void*>(&cheb_batch_kernel<T, TM, TN, WM, WN, KV, DEPTH>), 64 * WM * WN, 0);
     }
-    hipLaunchKernelGGL((cheb_batch_kernel<T, TM, TN, WM, WN, KV>), dim3(grid), dim3(64 * WM * WN), 0, s, a);
+    hipLaunchKernelGGL((cheb_batch_kernel<T, TM, TN, WM, WN, KV, DEPTH>), dim3(grid), dim3(64 * WM * WN), 0, s, a);
     return hipGetLastError();
 }
 
-// occ != nullptr: report the occupancy instead of launching
+// Tile shapes of the batch kernel, named by their index in kChebCfgs (the
+// main loop and epilogue are the same code, so a batch run and a pinned
+// single-operator run of the same shape agree bit for bit).
+// occ != nullptr: report the occupancy instead of launching.
 template <typename T>
 hipError_t launch_batch(const BatchArgs& a, int cfg, int grid, hipStream_t s, int* occ) {
     switch (cfg) {
@@ -664,6 +667,14 @@ hipError_t launch_batch(const BatchArgs& a, int cfg, int grid, hipStream_t s, in
         case 1: return launch_batch_one<T, 4, 2, 2, 2, 4>(a, grid, s, occ);
         case 2: return launch_batch_one<T, 2, 2, 4, 1, 4>(a, grid, s, occ);
         case 3: return launch_batch_one<T, 2, 2, 2, 2, 4>(a, grid, s, occ);
+        case 7: return launch_batch_one<T, 2, 2, 4, 1, 4, 4>(a, grid, s, occ);
+        case 8: return launch_batch_one<T, 4, 2, 2, 2, 4, 4>(a, grid, s, occ);
+        case 12:  // the FP64 build of this ring spills in the persistent loop
+            if constexpr (sizeof(T) == 4) return launch_batch_one<float, 4, 4, 2, 2, 4, 4>(a, grid, s, occ);
+            return hipErrorInvalidValue;
+        case 27:
+            if constexpr (sizeof(T) == 4) return launch_batch_one<float, 4, 4, 2, 2, 8, 4>(a, grid, s, occ);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -674,6 +685,15 @@ hipError_t cheb_batch(const BatchArgs& a, int cfg, int precision, int grid, hipS
     if (grid < 1) return hipErrorInvalidValue;
     return precision == 0 ? launch_batch<double>(a, cfg, grid, s, nullptr)
                           : launch_batch<float>(a, cfg, grid, s, nullptr);
+}
+
+int cheb_batch_num_cfgs() { return 8; }
+int cheb_batch_cfg(int i, int precision) {
+    static const int kBatch[] = {0, 1, 2, 3, 7, 8, 12, 27};
+    if (i < 0 || i >= 8) return -1;
+    const int cfg = kBatch[i];
+    if (precision == 0 && cfg == 12) return -1;
+    return cheb_cfg_supports(cfg, precision) ? cfg : -1;
 }
 
 int cheb_batch_occupancy(int cfg, int precision) {
