@@ -112,7 +112,7 @@ enum { DM_OP_SINV = 0, DM_OP_H = 1, DM_OP_HSYM = 2 };
 dm_status dm_get_operator(dm_ctx* ctx, int which, double* out);
 
 /* Operator form of the recursion for the Fock matrices loaded afterwards by
- * dm_set_fock (an operator already loaded keeps its form):
+ * dm_set_fock or dm_batch_set_focks (operators already loaded keep theirs):
  * DM_FORM_GENERAL (default): the recursion runs on H = S^-1 F as in the
  *   supplement's eq. ChebychevExpansion, from U_0 = S^-1 u_a;
  * DM_FORM_SYMMETRIC: with the Cholesky factor S = U^T U and L = U^-T it runs
@@ -124,7 +124,8 @@ dm_status dm_get_operator(dm_ctx* ctx, int which, double* out);
  *   moments use z_a = U u_a (u_a^T S T_l(H) S^-1 u_a = (U u_a)^T T_l(H~) L u_a),
  *   so traces, mu and the DOS are unchanged; dm_stoch_moments probes H~.
  *   Costs two K x K FP64 arrays (L, U) and H~ (FP64) more, and K^3 more
- *   setup flops.  The batch entry points always use the general form.
+ *   setup flops.  dm_batch_set_focks builds every cluster in the form set
+ *   here too (dm_batch_run then ends its P pass with the L^T Q products).
  * Errors: DM_E_ARG (unknown form). */
 enum { DM_FORM_GENERAL = 0, DM_FORM_SYMMETRIC = 1 };
 dm_status dm_set_operator_form(dm_ctx* ctx, int form);

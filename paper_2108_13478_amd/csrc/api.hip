@@ -1395,9 +1395,10 @@ hipError_t batch_start(dm_ctx* c, bool zero_moments) {
         BatchClusterBufs& b = bs.cl[i];
         if ((e = fill_f64(b.Z.p, 0.0, (long long)op.Kp * b.Bp, s)) != hipSuccess) return e;
         int nts = 0;
-        if ((e = cheb_start((int)op.K, op.Kp, b.Bp, (int)op.K, b.cols.p, op.Sinv.p, op.S_rowptr.p,
-                            op.S_col.p, op.S_val.p, c->precision, b.Ua.p, b.Z.p, b.P.p, b.coef.p, 1, 0,
-                            0, b.pstart.p, &nts, s)) != hipSuccess)
+        const bool sym = op.form == DM_FORM_SYMMETRIC;
+        if ((e = cheb_start((int)op.K, op.Kp, b.Bp, (int)op.K, b.cols.p, sym ? op.Lsym.p : op.Sinv.p,
+                            op.S_rowptr.p, op.S_col.p, op.S_val.p, c->precision, b.Ua.p, b.Z.p, b.P.p,
+                            b.coef.p, 1, 0, 0, b.pstart.p, &nts, s, sym ? op.Usym.p : nullptr)) != hipSuccess)
             return e;
         if (zero_moments) {
             if ((e = fill_f64(b.mom.p, 0.0, bs.table_order + 1, s)) != hipSuccess) return e;
@@ -1445,6 +1446,13 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
     BQ(batch_start(c, false));
     BatchArgs a2{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p + 1, order, 1};
     BQ(cheb_batch(a2, bs.cfg, c->precision, grid, s));
+    // symmetric form: P = L^T Q into the Z buffer (Z is not read after the pass)
+    for (int i = 0; i < n; ++i) {
+        const Op& op = c->batch[i];
+        if (op.form != DM_FORM_SYMMETRIC) continue;
+        BatchClusterBufs& b = bs.cl[i];
+        BQ(gemm_tn_f64(op.Kp, b.Bp, op.Kp, 1.0, op.Lsym.p, op.Kp, b.P.p, op.Kp, 0.0, b.Z.p, op.Kp, false, s));
+    }
 #undef BQ
     return hipSuccess;
 }
@@ -1467,14 +1475,18 @@ dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) {
         HostCsr Fh, Sh;
         st = load_csr_pair(c, cl[i].K, cl[i].F_rowptr, cl[i].F_col, cl[i].F_val, cl[i].S_rowptr,
                            cl[i].S_col, cl[i].S_val, Fh, Sh);
-        if (st == DM_OK) st = build_op(c, c->batch[i], cl[i].K, Fh, Sh, DM_FORM_GENERAL);
+        if (st == DM_OK) st = build_op(c, c->batch[i], cl[i].K, Fh, Sh, c->form);
         if (st != DM_OK) {
             const std::string m = "cluster " + std::to_string(i) + ": " + c->err;
             for (auto& o : c->batch) o.release();
             c->batch.clear();
             return set_err(c, st, m);
         }
-        c->batch[i].HT.release();  // H^T is only needed to renormalise; the batch keeps H_N
+        // H^T / H~ are only needed to renormalise, S^-1 only by the general
+        // form's start block; the batch keeps H_N
+        c->batch[i].HT.release();
+        c->batch[i].Hsym.release();
+        if (c->batch[i].form == DM_FORM_SYMMETRIC) c->batch[i].Sinv.release();
     }
     c->bstate = new BatchState();
     c->bstate->cl.resize(n);
@@ -1544,7 +1556,8 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
         for (int i = 0; i < n; ++i)
             if (P_out[i]) {
                 const size_t K = (size_t)c->batch[i].K, Kp = (size_t)c->batch[i].Kp;
-                HIPTRY(c, hipMemcpy2DAsync(P_out[i], K * 8, bs.cl[i].P.p, Kp * 8, K * 8, K, hipMemcpyDefault, s));
+                const double* src = c->batch[i].form == DM_FORM_SYMMETRIC ? bs.cl[i].Z.p : bs.cl[i].P.p;
+                HIPTRY(c, hipMemcpy2DAsync(P_out[i], K * 8, src, Kp * 8, K * 8, K, hipMemcpyDefault, s));
             }
     int flag = 0;
     HIPTRY(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -27,11 +27,13 @@ def run_batch(ctx, clusters, N, beta, tol, flags=0):
     return mu, [p.reshape(c.K, c.K).T for p, c in zip(P, clusters)]
 
 
-def test_fp64_batch_matches_oracle():
+@pytest.mark.parametrize("form", [dmlib.DM_FORM_GENERAL, dmlib.DM_FORM_SYMMETRIC])
+def test_fp64_batch_matches_oracle(form):
     sizes = batch_cluster_sizes(6, lo=25, hi=150, seed=3)  # K = 100 .. 600
     clusters = make_batch(sizes, range(100, 106), processes=1)
-    say(f"case: FP64 batch K = {[c.K for c in clusters]}")
+    say(f"case: FP64 batch K = {[c.K for c in clusters]}, operator form {form}")
     ctx = dmlib.Context(precision=dmlib.DM_FP64)
+    ctx.dm_set_operator_form(form)
     ctx.dm_batch_set_focks(clusters)
     N, beta = 200, 20.0
     mu, P = run_batch(ctx, clusters, N, beta, tol=1e-9)

@@ -122,6 +122,10 @@ def test_trained_network_gain():
         c.n_electrons = float(2 * int(round(a * rng.uniform(0.8, 1.2))))
     probes = [rademacher(c.K, learn.N_VEC, seed=5000 + i) for i, c in enumerate(clusters)]
     tctx = dmlib.Context(precision=dmlib.DM_FP32)
+    # features and the network path use the symmetric form: its stochastic
+    # moments probe T_l(H~_N), whose Frobenius norm is at most sqrt(K), so the
+    # +-1 estimates are far less noisy than with the non-normal S^-1 F
+    tctx.dm_set_operator_form(dmlib.DM_FORM_SYMMETRIC)
     t0 = time.perf_counter()
     X, T, rec = learn.make_dataset(tctx, clusters, betas, probes, label_order=4096, tol_order=1e-3,
                                    max_order=8192)
@@ -158,6 +162,7 @@ def test_trained_network_gain():
         err_plain = np.abs(P.cpu().numpy().T - P_x).max()
         # ---- network + FP32 path
         n32 = dmlib.Context(precision=dmlib.DM_FP32)
+        n32.dm_set_operator_form(dmlib.DM_FORM_SYMMETRIC)
         n32.dm_mlp_init(learn.SIZES)
         n32.dm_mlp_set_params(params)
         xi = torch.from_numpy(rademacher(c.K, learn.N_VEC, seed=9000 + seed)).cuda()
