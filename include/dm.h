@@ -94,6 +94,19 @@ dm_status dm_set_fock(dm_ctx* ctx, long long K,
                       const long long* S_rowptr, const int* S_col, const double* S_val,
                       int atom_block);
 
+/* An orthonormal basis (S = I, e.g. an orthogonal tight-binding model or a
+ * basis the caller has already orthogonalised): P = f_FD(F) (eq. RDM with
+ * S = I).  Only F is given (CSR as for dm_set_fock); the library keeps F in
+ * CSR (Lanczos products, re-normalisation) and builds the dense H_N directly
+ * from it, with no K x K FP64 temporaries, so the operator needs K^2 x 4
+ * bytes in FP32 (69 GB at K = 131072) and K^2 x 8 in FP64.  The start
+ * vectors are the unit vectors u_a, the moment vectors too.  Every entry
+ * point that works on a dm_set_fock operator works on this one, except
+ * dm_get_operator (DM_E_STATE) and the operator form (S = I makes both forms
+ * the same).  Errors: as dm_set_fock. */
+dm_status dm_set_fock_orthonormal(dm_ctx* ctx, long long K, const long long* F_rowptr, const int* F_col,
+                                  const double* F_val);
+
 /* Spectral interval [Emin, Emax] used to normalise H (supplement: Emax and
  * Emin are the extreme eigenvalues of H = S^-1 F).  dm_set_bounds replaces
  * the Lanczos interval (e.g. to pin the interval in a comparison) and resets

@@ -35,7 +35,7 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_mlp_num_params", "dm_mlp_get_params", "dm_mlp_set_params", "dm_mlp_forward",
             "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict",
             "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
-            "dm_dos", "dm_set_operator_form"]
+            "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal"]
 
 
 class DMError(RuntimeError):
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
         "dm_chebyshev_block_multi": (_I, [_P, _P, _LL, _I, _I, _P, _P, _P]),
         "dm_dos": (_I, [_P, _I, _I, _P, _D, _P]),
         "dm_set_operator_form": (_I, [_P, _I]),
+        "dm_set_fock_orthonormal": (_I, [_P, _LL, _P, _P, _P]),
         "dm_trace": (_I, [_P, _D, _D, _P, _P]),
         "dm_solve_mu": (_I, [_P, _D, _D, _D, _P]),
         "dm_moments": (_I, [_P, _P, _I, _P]),
@@ -328,6 +329,12 @@ class Context:
         self._check(self._lib.dm_autotune(self.h, int(ncols), int(steps), ctypes.c_void_p(table.ctypes.data),
                                           ctypes.byref(n), ctypes.byref(bw), ctypes.byref(bc)))
         return bw.value, bc.value, table[:min(n.value, cap)].copy()
+
+    def set_orthonormal(self, K, rowptr, col, val):
+        """Load F of an orthonormal basis (S = I) from CSR arrays (numpy or torch)."""
+        ptrs = [_ptr(rowptr, np.int64), _ptr(col, np.int32), _ptr(val, np.float64)]
+        self._check(self._lib.dm_set_fock_orthonormal(self.h, int(K), *[p[0] for p in ptrs]))
+        self.K = int(K)
 
     def dm_set_operator_form(self, form):
         """DM_FORM_GENERAL or DM_FORM_SYMMETRIC, for Fock matrices loaded afterwards."""

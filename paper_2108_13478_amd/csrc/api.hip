@@ -51,11 +51,18 @@ struct Op {
     // symmetric form (DM_FORM_SYMMETRIC): S = U^T U, L = U^-T, Hsym = L F L^T
     int form = DM_FORM_GENERAL;
     DevBuf<double> Lsym, Usym, Hsym;
+    // orthonormal basis (dm_set_fock_orthonormal): S = I, H = F kept in CSR
+    // (S_* then hold the identity), no dense S^-1 / H^T
+    bool orth = false;
+    DevBuf<long long> F_rowptr;
+    DevBuf<int> F_col;
+    DevBuf<double> F_val;
     void release() {
         S_rowptr.release(); S_col.release(); S_val.release();
         Sinv.release(); HT.release(); HNbuf.release();
         Lsym.release(); Usym.release(); Hsym.release();
-        K = 0; Kp = 0; form = DM_FORM_GENERAL;
+        F_rowptr.release(); F_col.release(); F_val.release();
+        K = 0; Kp = 0; form = DM_FORM_GENERAL; orth = false;
     }
 };
 
@@ -347,7 +354,10 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
     for (int j = 0; j < ksteps; ++j) {
         double* vj = V.p + (size_t)j * ld;
         double* qj = Q.p + (size_t)j * ld;
-        LZ(gemv_rows(K, op.HT.p, ld, vj, wv.p, s));
+        if (op.orth)
+            LZ(csr_spmv(K, op.F_rowptr.p, op.F_col.p, op.F_val.p, vj, wv.p, s));
+        else
+            LZ(gemv_rows(K, op.HT.p, ld, vj, wv.p, s));
         LZ(dots_cols(K, 1, qj, ld, wv.p, alpha + j, s));
         LZ(lanczos_three_term(K, wv.p, vj, j ? vj - ld : nullptr, alpha + j, j ? beta + j - 1 : beta, s));
         for (int rep = 0; rep < 2; ++rep) {
@@ -397,6 +407,13 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
 
 dm_status normalize(dm_ctx* c, Op& op) {
     const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
+    if (op.orth) {
+        const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
+        HIPTRY(c, ensure(op.HNbuf, (size_t)op.Kp * op.Kp * tsz / 8));
+        HIPTRY(c, csr_normalize((int)op.K, op.Kp, op.F_rowptr.p, op.F_col.p, op.F_val.p, ebar, de, c->precision,
+                                op.HNbuf.p, c->stream));
+        return DM_OK;
+    }
     const double* H = op.form == DM_FORM_SYMMETRIC ? op.Hsym.p : op.HT.p;  // both row-major
     HIPTRY(c, normalize_operator((int)op.K, op.Kp, H, ebar, de, c->precision, op.HNbuf.p, c->stream));
     return DM_OK;
@@ -501,6 +518,10 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
     auto release_tmp = [&]() { Frp.release(); Fci.release(); Fv.release(); Vblk.release(); tmp.release(); G.release(); };
     const bool sym = form == DM_FORM_SYMMETRIC;
     op.form = DM_FORM_GENERAL;
+    op.orth = false;
+    op.F_rowptr.release();
+    op.F_col.release();
+    op.F_val.release();
     if (!sym) {
         op.Lsym.release();
         op.Usym.release();
@@ -594,6 +615,37 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
     dm_status st = lanczos_bounds(c, op);
     if (st != DM_OK) return st;
     op.form = sym ? DM_FORM_SYMMETRIC : DM_FORM_GENERAL;
+    return normalize(c, op);
+}
+
+// Operator setup in an orthonormal basis (S = I): F in CSR on the device,
+// the identity as S, the Lanczos interval of F, and H_N built from the CSR.
+dm_status build_orth(dm_ctx* c, Op& op, long long K, const HostCsr& Fh) {
+    hipStream_t s = c->stream;
+    op.release();
+    op.K = K;
+    op.Kp = (int)round_up(K, kRowPad);
+    std::vector<long long> irp((size_t)K + 1);
+    std::vector<int> icol((size_t)K);
+    std::vector<double> ival((size_t)K, 1.0);
+    for (long long i = 0; i <= K; ++i) irp[i] = i;
+    for (long long i = 0; i < K; ++i) icol[i] = (int)i;
+    HIPTRY(c, ensure(op.S_rowptr, (size_t)K + 1));
+    HIPTRY(c, ensure(op.S_col, (size_t)K));
+    HIPTRY(c, ensure(op.S_val, (size_t)K));
+    HIPTRY(c, ensure(op.F_rowptr, (size_t)K + 1));
+    HIPTRY(c, ensure(op.F_col, Fh.col.size()));
+    HIPTRY(c, ensure(op.F_val, Fh.val.size()));
+    HIPTRY(c, hipMemcpyAsync(op.S_rowptr.p, irp.data(), irp.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.S_col.p, icol.data(), icol.size() * 4, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.S_val.p, ival.data(), ival.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.F_rowptr.p, Fh.rp.data(), Fh.rp.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.F_col.p, Fh.col.data(), Fh.col.size() * 4, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.F_val.p, Fh.val.data(), Fh.val.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    op.orth = true;
+    dm_status st = lanczos_bounds(c, op);
+    if (st != DM_OK) return st;
     return normalize(c, op);
 }
 
@@ -716,6 +768,30 @@ dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const i
     return DM_OK;
 }
 
+dm_status dm_set_fock_orthonormal(dm_ctx* c, long long K, const long long* F_rowptr, const int* F_col,
+                                  const double* F_val) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (K <= 0 || K > (1LL << 30)) return set_err(c, DM_E_ARG, "K out of range");
+    if (!F_rowptr || !F_col || !F_val) return set_err(c, DM_E_ARG, "null CSR array");
+    c->have_fock = false;
+    c->tuned_width = 0;
+    c->tuned_cfg = -1;
+    reset_moments(c);
+    HostCsr Fh;
+    HIPTRY(c, to_host(Fh.rp, F_rowptr, (size_t)K + 1));
+    if (Fh.rp[0] != 0 || Fh.rp[K] < 0) return set_err(c, DM_E_ARG, "malformed rowptr");
+    HIPTRY(c, to_host(Fh.col, F_col, (size_t)Fh.rp[K]));
+    HIPTRY(c, to_host(Fh.val, F_val, (size_t)Fh.rp[K]));
+    const std::string msg = check_csr("F", K, Fh.rp, Fh.col, Fh.val, false);
+    if (!msg.empty()) return set_err(c, DM_E_ARG, msg);
+    st = build_orth(c, c->op, K, Fh);
+    if (st != DM_OK) return st;
+    c->have_fock = true;
+    return DM_OK;
+}
+
 dm_status dm_get_bounds(dm_ctx* c, double* emin, double* emax) {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
@@ -757,6 +833,7 @@ dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
         return set_err(c, DM_E_ARG, "bad operator request");
     if (which == DM_OP_HSYM && c->op.form != DM_FORM_SYMMETRIC)
         return set_err(c, DM_E_STATE, "the loaded operator was not built in the symmetric form");
+    if (c->op.orth) return set_err(c, DM_E_STATE, "an orthonormal-basis operator keeps no dense setup products");
     const size_t K = (size_t)c->op.K, Kp = (size_t)c->op.Kp;
     hipStream_t s = c->stream;
     if (which == DM_OP_SINV || which == DM_OP_HSYM) {
@@ -838,7 +915,10 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
     const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
     const bool tuned = c->opt.block_width == 0 && c->tuned_width > 0;
     long long bw = c->opt.block_width > 0 ? c->opt.block_width : (tuned ? c->tuned_width : ncols);
-    const size_t budget = (size_t)16 << 30;
+    // pass buffers may take half of the free HBM (at least 16 GiB)
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    const size_t budget = std::max<size_t>((size_t)16 << 30, free_b / 2);
     const size_t per_col = (size_t)Kp * (2 * tsz + 8 + 8 * nsets);
     bw = std::min<long long>(bw, std::max<long long>(128, (long long)(budget / per_col) / 128 * 128));
     bw = std::min(bw, ncols);
@@ -870,7 +950,8 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
         HIPTRY(c, hipMemcpyAsync(c->cols.p, hc.data() + off, (size_t)nc * 8, hipMemcpyHostToDevice, s));
         HIPTRY(c, fill_f64(c->Z.p, 0.0, (long long)Kp * Bp, s));
         int nts = 0;
-        HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, sym ? c->op.Lsym.p : c->op.Sinv.p, c->op.S_rowptr.p,
+        const double* v0src = c->op.orth ? nullptr : (sym ? c->op.Lsym.p : c->op.Sinv.p);
+        HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, v0src, c->op.S_rowptr.p,
                              c->op.S_col.p, c->op.S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p,
                              nsets, pstride, cstride, c->part_start.p, &nts, s, sym ? c->op.Usym.p : nullptr));
         HIPTRY(c, reduce_moments(0, nts, c->part_start.p, c->mom.p, c->flag.p, s));
@@ -1148,7 +1229,7 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
         const int nc = std::min(cd.w, K);
         AT(fill_f64(Zb.p, 0.0, (long long)Kp * cd.w, s));
         int nts = 0;
-        AT(cheb_start(K, Kp, cd.w, nc, colsd.p, c->op.Sinv.p, c->op.S_rowptr.p, c->op.S_col.p, c->op.S_val.p,
+        AT(cheb_start(K, Kp, cd.w, nc, colsd.p, c->op.orth ? nullptr : c->op.Sinv.p, c->op.S_rowptr.p, c->op.S_col.p, c->op.S_val.p,
                       c->precision, U0.p, Zb.p, Pb.p, coef.p, 1, 0, 0, pst.p, &nts, s));
         ChebStepArgs a{};
         a.Kp = Kp;

@@ -117,12 +117,17 @@ hipError_t cheb_coefficients_devmu(int N, int M, double ebar, double de, const d
 // P_s[:, j] = coef[s * cstride] * Sinv[:, cols[j]] for s < nsets (P_s = P +
 // s * pstride), partial[t] = per-tile sums of Z .* U0 for t < ntiles(start).
 // Columns j >= ncols are zero.  Z must be zero on entry.  (The symmetric form
-// passes L for Sinv and U for Zdense.)
+// passes L for Sinv and U for Zdense; an orthonormal basis passes no Sinv:
+// U0 and P start from the unit vectors.)
 hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, const double* Sinv,
                       const long long* S_rowptr, const int* S_col, const double* S_val,
                       int precision, void* U0, double* Z, double* P, const double* coef,
                       int nsets, long long pstride, int cstride, double* partial, int* ntiles_out,
                       hipStream_t s, const double* Zdense = nullptr);
+// Orthonormal basis (S = I): HN = (F - ebar I) / de from F's CSR rows,
+// padding zero, in FP64 (precision 0) or FP32; Kp * Kp even.
+hipError_t csr_normalize(int K, int Kp, const long long* rp, const int* col, const double* val, double ebar,
+                         double de, int precision, void* HN, hipStream_t s);
 // dst = src^T (Kp x Kp, Kp % 32 == 0); dst = upper triangle of src.
 hipError_t transpose_square(int Kp, const double* src, double* dst, hipStream_t s);
 hipError_t copy_upper(int Kp, const double* src, double* dst, hipStream_t s);

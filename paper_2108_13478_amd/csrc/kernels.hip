@@ -165,6 +165,30 @@ __global__ void gather_columns_kernel(int Kp, int ncols, const long long* __rest
     }
 }
 
+
+// HN = (F - ebar I) * inv_de straight from the CSR rows of a symmetric F
+// (orthonormal basis, S = I); HN zero on entry, row r at HN + r * Kp.  One
+// thread per row; a row without a stored diagonal gets -ebar * inv_de.
+template <typename T>
+__global__ void csr_normalize_kernel(int K, int Kp, const long long* __restrict__ rp,
+                                     const int* __restrict__ col, const double* __restrict__ val,
+                                     double ebar, double inv_de, T* __restrict__ HN) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= K) return;
+    bool diag = false;
+    T* row = HN + (long)r * Kp;
+    for (long long p = rp[r]; p < rp[r + 1]; ++p) {
+        const int cc = col[p];
+        double v = val[p];
+        if (cc == r) {
+            v -= ebar;
+            diag = true;
+        }
+        row[cc] = static_cast<T>(v * inv_de);
+    }
+    if (!diag) row[r] = static_cast<T>(-ebar * inv_de);
+}
+
 template <typename T>
 __global__ void normalize_operator_kernel(int K, int Kp, const double* __restrict__ HT, double ebar,
                                           double inv_de, T* __restrict__ HN) {
@@ -196,9 +220,9 @@ cheb_start_kernel(int K, int Kp, int Bp, int ncols, const long long* __restrict_
     double msum = 0.0;
     const long idx = (long)r0 + (long)j * Kp;
     if (j < ncols) {
-        const double* src = Sinv + (long)cols[j] * Kp + r0;
+        const double* src = Sinv ? Sinv + (long)cols[j] * Kp + r0 : nullptr;
         for (int i = 0; i < 4; ++i) {
-            const double u = src[i];
+            const double u = src ? src[i] : (r0 + i == cols[j] ? 1.0 : 0.0);  // no Sinv: S = I
             U0[idx + i] = static_cast<T>(u);
             for (int q = 0; q < nsets; ++q) P[q * pstride + idx + i] = coef[q * cstride] * u;
             msum += Z[idx + i] * static_cast<double>(static_cast<T>(u));
@@ -561,6 +585,20 @@ hipError_t transpose_square(int Kp, const double* src, double* dst, hipStream_t 
 
 hipError_t copy_upper(int Kp, const double* src, double* dst, hipStream_t s) {
     hipLaunchKernelGGL(copy_upper_kernel, grid_for((long long)Kp * Kp, 256), dim3(256), 0, s, Kp, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t csr_normalize(int K, int Kp, const long long* rp, const int* col, const double* val, double ebar,
+                         double de, int precision, void* HN, hipStream_t s) {
+    const long long n = (long long)Kp * Kp;
+    hipError_t e = fill_f64(static_cast<double*>(HN), 0.0, precision == 0 ? n : n / 2, s);
+    if (e != hipSuccess) return e;
+    if (precision == 0)
+        hipLaunchKernelGGL(csr_normalize_kernel<double>, dim3((K + 255) / 256), dim3(256), 0, s, K, Kp, rp, col,
+                           val, ebar, 1.0 / de, static_cast<double*>(HN));
+    else
+        hipLaunchKernelGGL(csr_normalize_kernel<float>, dim3((K + 255) / 256), dim3(256), 0, s, K, Kp, rp, col,
+                           val, ebar, 1.0 / de, static_cast<float*>(HN));
     return hipGetLastError();
 }
 
