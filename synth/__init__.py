@@ -11,8 +11,10 @@ from .clusters import (  # noqa: F401
     SPACING,
     Cluster,
     WORKLOADS,
+    basis_functions,
     batch_cluster_sizes,
     cube_sites,
+    grid_around,
     make_batch,
     make_cluster,
     rademacher,

@@ -254,6 +254,25 @@ WORKLOADS = {
 }
 
 
+def basis_functions(cluster: Cluster):
+    """(centres K x 3, exponents K) of the basis: EXPONENTS on every atom,
+    atom-major, the order of F and S."""
+    nb = len(EXPONENTS)
+    centres = np.repeat(np.asarray(cluster.positions, dtype=np.float64), nb, axis=0)
+    exps = np.tile(np.asarray(EXPONENTS, dtype=np.float64), cluster.n_atoms)
+    return centres, exps
+
+
+def grid_around(cluster: Cluster, h: float, margin: float):
+    """A uniform grid of spacing h covering the atoms plus `margin` on every
+    side: (origin (3,), h, (nx, ny, nz))."""
+    pos = np.asarray(cluster.positions, dtype=np.float64)
+    lo = pos.min(axis=0) - margin
+    hi = pos.max(axis=0) + margin
+    n = np.ceil((hi - lo) / h).astype(int) + 1
+    return lo, float(h), tuple(int(x) for x in n)
+
+
 def workload(name: str) -> Cluster:
     w = WORKLOADS[name]
     return make_cluster(w["n_atoms"], seed=w.get("seed", 0), geometry=w["geometry"],
