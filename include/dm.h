@@ -205,6 +205,25 @@ dm_status dm_chebyshev_block_multi(dm_ctx* ctx, const long long* cols, long long
 enum { DM_DOS_GAUSSIAN = 0, DM_DOS_KPM = 1 };
 dm_status dm_dos(dm_ctx* ctx, int kind, int n, const double* energies, double sigma, double* dos);
 
+/* Electron density on a uniform grid from columns of P (Method, eq.
+ * ElectronDensity): n(r_g) += sum_j 2 phi_a(r_g) sum_b phi_b(r_g) P_cols[b, j],
+ * a = cols[j], so calls over disjoint column shares add up to the density of
+ * eq. density (the paper's reduce over processors).  The basis is K
+ * normalised s-type Gaussians (2a/pi)^{3/4} exp(-a |r - R|^2): centres (host,
+ * K x 3 row-major) and exponents (host, K), in the order of F and S; each is
+ * zero outside the cube of half-width sqrt(ln(1/eta)/a) around its centre
+ * (the grid windows of the paper, 0 < eta < 1).  Grid: r_g = origin (host,
+ * 3) + h (i, j, k), dims (host, 3) = (nx, ny, nz), flattened index
+ * g = i + nx (j + ny k).  cols (int64, host or device, ncols distinct
+ * indices); P_cols (host or device, K x ncols column-major FP64, as written
+ * by dm_chebyshev_block); n_out (host or device, nx ny nz FP64) is
+ * accumulated.  Independent of any loaded Fock matrix.
+ * Errors: DM_E_ARG (bad sizes, exponents <= 0, h <= 0, eta outside (0, 1),
+ * bad or repeated columns), DM_E_OOM, DM_E_HIP. */
+dm_status dm_density_on_grid(dm_ctx* ctx, long long K, const double* centres, const double* exponents,
+                             const double* origin, double h, const int* dims, double eta,
+                             const long long* cols, long long ncols, const double* P_cols, double* n_out);
+
 /* Bisection on [Emin, Emax] for mu with g Tr[P_N(mu) S] = n_e from the
  * accumulated moments (the paper adjusts mu to reproduce N_e through eq. Ne;
  * the method is not stated).  Stops when |g Tr - n_e| <= tol or the bracket

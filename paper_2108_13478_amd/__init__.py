@@ -35,7 +35,7 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_mlp_num_params", "dm_mlp_get_params", "dm_mlp_set_params", "dm_mlp_forward",
             "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict",
             "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
-            "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal"]
+            "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal", "dm_density_on_grid"]
 
 
 class DMError(RuntimeError):
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         "dm_dos": (_I, [_P, _I, _I, _P, _D, _P]),
         "dm_set_operator_form": (_I, [_P, _I]),
         "dm_set_fock_orthonormal": (_I, [_P, _LL, _P, _P, _P]),
+        "dm_density_on_grid": (_I, [_P, _LL, _P, _P, _P, _D, _P, _D, _P, _LL, _P, _P]),
         "dm_trace": (_I, [_P, _D, _D, _P, _P]),
         "dm_solve_mu": (_I, [_P, _D, _D, _D, _P]),
         "dm_moments": (_I, [_P, _P, _I, _P]),
@@ -335,6 +336,28 @@ class Context:
         ptrs = [_ptr(rowptr, np.int64), _ptr(col, np.int32), _ptr(val, np.float64)]
         self._check(self._lib.dm_set_fock_orthonormal(self.h, int(K), *[p[0] for p in ptrs]))
         self.K = int(K)
+
+    def dm_density_on_grid(self, centres, exponents, origin, h, dims, eta, cols, P_cols, n_out=None):
+        """Accumulate the grid density of columns `cols` of P into n_out (a
+        float64 array of nx*ny*nz, i fastest; created zero if None).  P_cols:
+        K x ncols column-major, i.e. a (ncols, K) C-order array or tensor."""
+        cen = np.ascontiguousarray(centres, dtype=np.float64)
+        ex = np.ascontiguousarray(exponents, dtype=np.float64)
+        org = np.ascontiguousarray(origin, dtype=np.float64)
+        dm_ = np.ascontiguousarray(dims, dtype=np.int32)
+        K = ex.shape[0]
+        if n_out is None:
+            n_out = np.zeros(int(np.prod(dm_)), dtype=np.float64)
+        elif isinstance(n_out, np.ndarray) and (n_out.dtype != np.float64 or not n_out.flags.c_contiguous):
+            raise TypeError("n_out must be a contiguous float64 array (it is accumulated in place)")
+        cp, ck = _ptr(cols, np.int64)
+        pp, pk = _ptr(P_cols, np.float64)
+        npt, nk = _ptr(n_out, np.float64)
+        self._check(self._lib.dm_density_on_grid(
+            self.h, K, ctypes.c_void_p(cen.ctypes.data), ctypes.c_void_p(ex.ctypes.data),
+            ctypes.c_void_p(org.ctypes.data), float(h), ctypes.c_void_p(dm_.ctypes.data), float(eta),
+            cp, _numel(ck), pp, npt))
+        return n_out
 
     def dm_set_operator_form(self, form):
         """DM_FORM_GENERAL or DM_FORM_SYMMETRIC, for Fock matrices loaded afterwards."""

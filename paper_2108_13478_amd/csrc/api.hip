@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "../../include/dm.h"
@@ -1116,6 +1117,151 @@ dm_status dm_dos(dm_ctx* c, int kind, int n, const double* energies, double sigm
     DOS(hipMemcpyAsync(dos, Od.p, (size_t)n * 8, hipMemcpyDefault, s));
     DOS(hipStreamSynchronize(s));
 #undef DOS
+    rel();
+    return DM_OK;
+}
+
+dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, const double* exponents,
+                             const double* origin, double h, const int* dims, double eta, const long long* cols,
+                             long long ncols, const double* P_cols, double* n_out) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (K <= 0 || K > (1LL << 30) || !centres || !exponents || !origin || !dims || !n_out)
+        return set_err(c, DM_E_ARG, "bad basis or grid arguments");
+    if (!(h > 0) || !std::isfinite(h) || !(eta > 0 && eta < 1)) return set_err(c, DM_E_ARG, "need h > 0 and 0 < eta < 1");
+    if (ncols < 0 || ncols > K || (ncols > 0 && (!cols || !P_cols))) return set_err(c, DM_E_ARG, "bad columns");
+    const int nx = dims[0], ny = dims[1], nz = dims[2];
+    if (nx < 1 || ny < 1 || nz < 1) return set_err(c, DM_E_ARG, "grid dimensions must be >= 1");
+    const long long G = (long long)nx * ny * nz;
+    if (ncols == 0) return DM_OK;
+    std::vector<long long> hc;
+    HIPTRY(c, to_host(hc, cols, (size_t)ncols));
+    std::vector<int> colpos((size_t)K, -1);
+    for (long long j = 0; j < ncols; ++j) {
+        if (hc[j] < 0 || hc[j] >= K) return set_err(c, DM_E_ARG, "column index out of range");
+        if (colpos[hc[j]] >= 0) return set_err(c, DM_E_ARG, "repeated column index");
+        colpos[hc[j]] = (int)j;
+    }
+    // per-function data and window half-widths (host arrays, K entries)
+    std::vector<double> fx(K), fy(K), fz(K), fe(K), fn(K), fr(K);
+    const double lninv = std::log(1.0 / eta);
+    for (long long b = 0; b < K; ++b) {
+        const double a = exponents[b];
+        if (!(a > 0) || !std::isfinite(a)) return set_err(c, DM_E_ARG, "exponents must be > 0");
+        fx[b] = centres[3 * b];
+        fy[b] = centres[3 * b + 1];
+        fz[b] = centres[3 * b + 2];
+        fe[b] = a;
+        fn[b] = std::pow(2.0 * a / 3.14159265358979323846, 0.75);
+        fr[b] = std::sqrt(lninv / a);
+    }
+    // cell lists: function b reaches the grid indices [lo, hi] along each axis
+    const int ncx = (nx + 3) / 4, ncy = (ny + 3) / 4, ncz = (nz + 3) / 4;
+    const long long ncell = (long long)ncx * ncy * ncz;
+    if (ncell > (1LL << 31) - 1) return set_err(c, DM_E_ARG, "grid too large");
+    std::vector<int> bcount((size_t)ncell + 1, 0), acount((size_t)ncell + 1, 0);
+    // grid indices a window reaches, with one point of slack on each side (the
+    // kernel tests every point exactly), clamped before the integer conversion
+    auto range = [&](double ctr, double R, double o, int n, int& lo, int& hi) {
+        const double l = std::ceil((ctr - R - o) / h) - 1, u = std::floor((ctr + R - o) / h) + 1;
+        if (!(u >= 0) || !(l <= n - 1)) return false;
+        lo = (int)std::max(0.0, l);
+        hi = (int)std::min((double)n - 1, u);
+        return lo <= hi;
+    };
+    std::vector<std::array<int, 6>> box((size_t)K);
+    std::vector<char> reach((size_t)K, 0);
+    for (long long b = 0; b < K; ++b) {
+        int xl, xh, yl, yh, zl, zh;
+        if (!range(fx[b], fr[b], origin[0], nx, xl, xh) || !range(fy[b], fr[b], origin[1], ny, yl, yh) ||
+            !range(fz[b], fr[b], origin[2], nz, zl, zh))
+            continue;
+        box[b] = {xl / 4, xh / 4, yl / 4, yh / 4, zl / 4, zh / 4};
+        reach[b] = 1;
+        for (int cz = zl / 4; cz <= zh / 4; ++cz)
+            for (int cy = yl / 4; cy <= yh / 4; ++cy)
+                for (int cx = xl / 4; cx <= xh / 4; ++cx) {
+                    const long long cell = cx + (long long)ncx * (cy + (long long)ncy * cz);
+                    ++bcount[cell + 1];
+                    if (colpos[b] >= 0) ++acount[cell + 1];
+                }
+    }
+    for (long long i = 0; i < ncell; ++i) {
+        bcount[i + 1] += bcount[i];
+        acount[i + 1] += acount[i];
+    }
+    std::vector<int> bidx((size_t)bcount[ncell]), aidx((size_t)acount[ncell]), acol((size_t)acount[ncell]);
+    {
+        std::vector<int> bfill(bcount.begin(), bcount.end() - 1), afill(acount.begin(), acount.end() - 1);
+        for (long long b = 0; b < K; ++b) {
+            if (!reach[b]) continue;
+            const auto& bx = box[b];
+            for (int cz = bx[4]; cz <= bx[5]; ++cz)
+                for (int cy = bx[2]; cy <= bx[3]; ++cy)
+                    for (int cx = bx[0]; cx <= bx[1]; ++cx) {
+                        const long long cell = cx + (long long)ncx * (cy + (long long)ncy * cz);
+                        bidx[bfill[cell]++] = (int)b;
+                        if (colpos[b] >= 0) {
+                            aidx[afill[cell]] = (int)b;
+                            acol[afill[cell]++] = colpos[b];
+                        }
+                    }
+        }
+    }
+    hipStream_t s = c->stream;
+    DevBuf<double> dfx, dfy, dfz, dfe, dfn, dfr, dP, dn;
+    DevBuf<int> dbp, dbi, dap, dai, dac;
+    auto rel = [&]() {
+        for (auto* x : {&dfx, &dfy, &dfz, &dfe, &dfn, &dfr, &dP, &dn}) x->release();
+        for (auto* x : {&dbp, &dbi, &dap, &dai, &dac}) x->release();
+    };
+    hipError_t e;
+#define GR(expr)                          \
+    do {                                  \
+        if ((e = (expr)) != hipSuccess) { \
+            rel();                        \
+            return fail_hip(c, e, #expr); \
+        }                                 \
+    } while (0)
+    auto up_d = [&](DevBuf<double>& d, const std::vector<double>& v) -> hipError_t {
+        hipError_t r = ensure(d, v.size());
+        if (r == hipSuccess) r = hipMemcpyAsync(d.p, v.data(), v.size() * 8, hipMemcpyHostToDevice, s);
+        return r;
+    };
+    auto up_i = [&](DevBuf<int>& d, const std::vector<int>& v) -> hipError_t {
+        hipError_t r = ensure(d, std::max<size_t>(v.size(), 1));
+        if (r == hipSuccess && !v.empty()) r = hipMemcpyAsync(d.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s);
+        return r;
+    };
+    GR(up_d(dfx, fx));
+    GR(up_d(dfy, fy));
+    GR(up_d(dfz, fz));
+    GR(up_d(dfe, fe));
+    GR(up_d(dfn, fn));
+    GR(up_d(dfr, fr));
+    GR(up_i(dbp, bcount));
+    GR(up_i(dbi, bidx));
+    GR(up_i(dap, acount));
+    GR(up_i(dai, aidx));
+    GR(up_i(dac, acol));
+    // P and n through device buffers (either may be host memory)
+    GR(ensure(dP, (size_t)K * ncols));
+    GR(hipMemcpyAsync(dP.p, P_cols, (size_t)K * ncols * 8, hipMemcpyDefault, s));
+    GR(ensure(dn, (size_t)G));
+    GR(hipMemcpyAsync(dn.p, n_out, (size_t)G * 8, hipMemcpyDefault, s));
+    GridArgs ga{};
+    ga.nx = nx; ga.ny = ny; ga.nz = nz; ga.ncx = ncx; ga.ncy = ncy; ga.ncz = ncz;
+    ga.ox = origin[0]; ga.oy = origin[1]; ga.oz = origin[2]; ga.h = h;
+    ga.cx = dfx.p; ga.cy = dfy.p; ga.cz = dfz.p; ga.ex = dfe.p; ga.norm = dfn.p; ga.R = dfr.p;
+    ga.beta_ptr = dbp.p; ga.beta_idx = dbi.p; ga.alpha_ptr = dap.p; ga.alpha_idx = dai.p; ga.alpha_col = dac.p;
+    ga.P = dP.p;
+    ga.ldp = K;
+    ga.n = dn.p;
+    GR(density_on_grid(ga, s));
+    GR(hipMemcpyAsync(n_out, dn.p, (size_t)G * 8, hipMemcpyDefault, s));
+    GR(hipStreamSynchronize(s));
+#undef GR
     rel();
     return DM_OK;
 }

@@ -190,6 +190,25 @@ hipError_t mlp_init_layer(int nin, int nout, unsigned long long seed, float* W, 
 hipError_t mlp_features(int n_mom, const double* m, double emin, double emax, double beta,
                         double n_e, double spin, double K, float* x, hipStream_t s);
 
+// ----------------------------------------------------------------- grid density
+// Uniform grid r = (ox, oy, oz) + h (i, j, k), i < nx ..., cells of 4^3 points
+// (ncx = ceil(nx / 4) ...), cell c = cx + ncx (cy + ncy cz).  Per basis
+// function (K): centre, exponent, normalisation (2a/pi)^{3/4} and cube
+// window half-width R.  Per cell (CSR over cells): beta_idx = functions whose
+// window reaches the cell (ascending), alpha_idx / alpha_col = those whose
+// column is in P (column position alpha_col).  P: K x ncols column-major with
+// leading dimension ldp.  n (nx ny nz, i fastest) is accumulated.
+struct GridArgs {
+    int nx, ny, nz, ncx, ncy, ncz;
+    double ox, oy, oz, h;
+    const double *cx, *cy, *cz, *ex, *norm, *R;
+    const int *beta_ptr, *beta_idx, *alpha_ptr, *alpha_idx, *alpha_col;
+    const double* P;
+    long long ldp;
+    double* n;
+};
+hipError_t density_on_grid(const GridArgs& a, hipStream_t s);
+
 // ----------------------------------------------------------------- setup
 hipError_t fill_f64(double* x, double v, long long n, hipStream_t s);
 hipError_t fill_i32(int* x, int v, long long n, hipStream_t s);
