@@ -144,7 +144,10 @@ enum { DM_FORM_GENERAL = 0, DM_FORM_SYMMETRIC = 1 };
 dm_status dm_set_operator_form(dm_ctx* ctx, int form);
 
 /* Switch the recursion precision (DM_FP64 / DM_FP32) of a loaded operator;
- * resets the accumulated moments. */
+ * resets the accumulated moments and forgets a tuned or pinned pass shape.
+ * A loaded batch keeps only its H_N and so the precision it was loaded in:
+ * the batch calls return DM_E_STATE until dm_batch_set_focks is called
+ * again (or the precision is switched back). */
 dm_status dm_set_precision(dm_ctx* ctx, int precision);
 
 /* Columns `cols` of P_N = sum_{l<order} a_l T_l(H_N) S^-1 (eq. RDM with the

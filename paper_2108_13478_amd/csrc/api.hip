@@ -55,6 +55,7 @@ struct Op {
     // orthonormal basis (dm_set_fock_orthonormal): S = I, H = F kept in CSR
     // (S_* then hold the identity), no dense S^-1 / H^T
     bool orth = false;
+    int hn_precision = -1;  // precision H_N was last built in
     DevBuf<long long> F_rowptr;
     DevBuf<int> F_col;
     DevBuf<double> F_val;
@@ -413,10 +414,22 @@ dm_status normalize(dm_ctx* c, Op& op) {
         HIPTRY(c, ensure(op.HNbuf, (size_t)op.Kp * op.Kp * tsz / 8));
         HIPTRY(c, csr_normalize((int)op.K, op.Kp, op.F_rowptr.p, op.F_col.p, op.F_val.p, ebar, de, c->precision,
                                 op.HNbuf.p, c->stream));
+        op.hn_precision = c->precision;
         return DM_OK;
     }
     const double* H = op.form == DM_FORM_SYMMETRIC ? op.Hsym.p : op.HT.p;  // both row-major
     HIPTRY(c, normalize_operator((int)op.K, op.Kp, H, ebar, de, c->precision, op.HNbuf.p, c->stream));
+    op.hn_precision = c->precision;
+    return DM_OK;
+}
+
+// The batch keeps only H_N (its FP64 sources are released to save memory),
+// so it can only run in the precision it was loaded with.
+dm_status batch_precision_ok(dm_ctx* c) {
+    for (const Op& o : c->batch)
+        if (o.hn_precision != c->precision)
+            return set_err(c, DM_E_STATE,
+                           "the batch was loaded in the other precision; call dm_batch_set_focks again");
     return DM_OK;
 }
 
@@ -1454,6 +1467,7 @@ dm_status dm_batch_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* 
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (c->batch.empty()) return set_err(c, DM_E_STATE, "no batch loaded");
+    if ((st = batch_precision_ok(c)) != DM_OK) return st;
     if (n_mom < 1 || n_vec < 1 || !xi || !m_out) return set_err(c, DM_E_ARG, "bad stochastic-moment arguments");
     for (size_t i = 0; i < c->batch.size(); ++i) {
         if (!xi[i]) return set_err(c, DM_E_ARG, "null probe block");
@@ -1735,6 +1749,7 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!c->bstate || c->batch.empty()) return set_err(c, DM_E_STATE, "no batch loaded");
+    if ((st = batch_precision_ok(c)) != DM_OK) return st;
     if (order < 2 || !(beta > 0) || !std::isfinite(beta) || !(tol > 0) || !n_e)
         return set_err(c, DM_E_ARG, "need order >= 2, beta > 0, tol > 0 and n_e");
     BatchState& bs = *c->bstate;
@@ -1814,6 +1829,7 @@ dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, in
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!c->bstate || c->batch.empty()) return set_err(c, DM_E_STATE, "no batch loaded");
+    if ((st = batch_precision_ok(c)) != DM_OK) return st;
     if (steps < 2) return set_err(c, DM_E_ARG, "steps must be >= 2");
     BatchState& bs = *c->bstate;
     hipStream_t s = c->stream;

@@ -127,3 +127,20 @@ def test_batch64_fp32_full_configuration():
             f"oracle 2Tr - N_e at mu = {ne_err:.2e}")
         assert err < 1e-4 * np.abs(ref).max()
         assert abs(ne_err) < 1e-3 * c.n_electrons
+
+
+def test_batch_refuses_other_precision():
+    """The batch keeps only H_N, so after a precision switch its calls refuse
+    to run (instead of reading H_N in the wrong format) until switched back."""
+    clusters = make_batch(batch_cluster_sizes(2, lo=30, hi=60, seed=6), [300, 301], processes=1)
+    ctx = dmlib.Context(precision=dmlib.DM_FP32)
+    ctx.dm_batch_set_focks(clusters)
+    ne = [c.n_electrons for c in clusters]
+    ctx.dm_batch_run(50, 10.0, ne, tol=1e-4, flags=dmlib.DM_BATCH_MOMENTS_ONLY)
+    ctx.dm_set_precision(dmlib.DM_FP64)
+    with pytest.raises(dmlib.DMError):
+        ctx.dm_batch_run(50, 10.0, ne, tol=1e-4, flags=dmlib.DM_BATCH_MOMENTS_ONLY)
+    with pytest.raises(dmlib.DMError):
+        ctx.dm_batch_autotune(steps=4)
+    ctx.dm_set_precision(dmlib.DM_FP32)
+    ctx.dm_batch_run(50, 10.0, ne, tol=1e-4, flags=dmlib.DM_BATCH_MOMENTS_ONLY)
