@@ -139,9 +139,58 @@ dm_status dm_get_operator(dm_ctx* ctx, int which, double* out);
  *   Costs two K x K FP64 arrays (L, U) and H~ (FP64) more, and K^3 more
  *   setup flops.  dm_batch_set_focks builds every cluster in the form set
  *   here too (dm_batch_run then ends its P pass with the L^T Q products).
+ * DM_FORM_FACTORED: H = S^-1 F is never formed.  Every application
+ *   H_N U = (S^-1 (F U) - Ebar U) / dE is one sparse product with F and a
+ *   solve S X = F U by preconditioned conjugate gradients, the paper's own
+ *   route (Methods, column-by-column evaluation; the footnote on the overlap
+ *   solve), with a factorised sparse approximate inverse G (S^-1 ~ G^T G, G
+ *   lower triangular on a pattern taken from S, see
+ *   dm_set_factored_options) in place of the paper's incomplete Cholesky
+ *   preconditioner.  F, S and G stay sparse: memory is O(nnz + K x block
+ *   width) instead of O(K^2).  Runs in FP64 only (dm_chebyshev_block returns
+ *   DM_E_STATE under DM_FP32).  P matches the other forms to within the
+ *   solve tolerance amplified by the recursion (about 10 x cg_tol x the
+ *   largest |P| entry).  The Lanczos interval is computed through the same
+ *   solves.  Not for dm_batch_set_focks, dm_stoch_moments, dm_autotune,
+ *   dm_set_pass_shape or dm_get_operator (DM_E_STATE).
  * Errors: DM_E_ARG (unknown form). */
-enum { DM_FORM_GENERAL = 0, DM_FORM_SYMMETRIC = 1 };
+enum { DM_FORM_GENERAL = 0, DM_FORM_SYMMETRIC = 1, DM_FORM_FACTORED = 2 };
 dm_status dm_set_operator_form(dm_ctx* ctx, int form);
+
+/* Factored form settings.  cg_tol: a column's solve stops when its
+ * residual satisfies ||S x - b|| <= cg_tol ||b|| (default 1e-11);
+ * cg_max_iter: iteration limit per solve (default 2000; reaching it fails
+ * the call with DM_E_NOCONV).  fsai_drop, fsai_max_per_row: pattern of row
+ * i of G, the lower entries j < i of S with |S_ij| >= fsai_drop
+ * sqrt(S_ii S_jj), at most fsai_max_per_row - 1 of them (the largest), and
+ * the diagonal (defaults 1e-3 and 128); row i of G is then the solution of
+ * S[J, J] g = e_i scaled so that (G S G^T)_ii = 1 (Kolotilina-Yeremin
+ * factorised sparse approximate inverse).  The tolerance and limit apply
+ * from the next call; the pattern from the next dm_set_fock.
+ * Errors: DM_E_ARG (cg_tol not in (0, 1), cg_max_iter < 1, fsai_drop < 0,
+ * fsai_max_per_row not in [1, 128]). */
+dm_status dm_set_factored_options(dm_ctx* ctx, double cg_tol, int cg_max_iter, double fsai_drop,
+                                  int fsai_max_per_row);
+
+/* X = S^-1 B by the factored form's preconditioned conjugate gradients,
+ * B and X K x nrhs column-major FP64 (host or device); each column to the
+ * tolerance of dm_set_factored_options.  Errors: DM_E_STATE (no factored
+ * operator loaded), DM_E_ARG, DM_E_NOCONV (iteration limit reached). */
+dm_status dm_solve_overlap(dm_ctx* ctx, const double* B, long long nrhs, double* X);
+
+/* The FSAI factor G of the loaded factored operator in CSR: *nnz (host,
+ * may be NULL) receives its number of entries; rowptr (K + 1 int64),
+ * col (nnz int32, ascending per row, the diagonal last) and val (nnz FP64)
+ * are filled when not NULL (host or device).
+ * Errors: DM_E_STATE (no factored operator loaded). */
+dm_status dm_get_preconditioner(dm_ctx* ctx, long long* nnz, long long* rowptr, int* col, double* val);
+
+/* Conjugate-gradient counters of the factored form since the last call (or
+ * the last dm_set_fock): solves run, iterations summed over the solves (for
+ * the 64-column group that needed most) and the largest iteration count of
+ * one solve.  Any output pointer (host) may be NULL.
+ * Errors: DM_E_STATE (no factored operator loaded). */
+dm_status dm_cg_stats(dm_ctx* ctx, long long* solves, long long* iterations, int* max_iterations);
 
 /* Switch the recursion precision (DM_FP64 / DM_FP32) of a loaded operator;
  * resets the accumulated moments and forgets a tuned or pinned pass shape.

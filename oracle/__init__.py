@@ -7,3 +7,4 @@ It shares no code with the HIP path.
 from .dm_oracle import *  # noqa: F401,F403
 from . import mlp_oracle  # noqa: F401
 from . import grid_oracle  # noqa: F401
+from . import factored_oracle  # noqa: F401

@@ -21,7 +21,7 @@ DM_OK, DM_E_ARG, DM_E_STATE, DM_E_HIP, DM_E_OOM, DM_E_NOTSPD, DM_E_BOUNDS, DM_E_
     0, -1, -2, -3, -4, -5, -6, -7)
 DM_FP64, DM_FP32 = 0, 1
 DM_OP_SINV, DM_OP_H, DM_OP_HSYM = 0, 1, 2
-DM_FORM_GENERAL, DM_FORM_SYMMETRIC = 0, 1
+DM_FORM_GENERAL, DM_FORM_SYMMETRIC, DM_FORM_FACTORED = 0, 1, 2
 DM_DOS_GAUSSIAN, DM_DOS_KPM = 0, 1
 DM_MAX_SETS = 16
 STATUS_NAMES = {0: "DM_OK", -1: "DM_E_ARG", -2: "DM_E_STATE", -3: "DM_E_HIP", -4: "DM_E_OOM",
@@ -35,7 +35,8 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_mlp_num_params", "dm_mlp_get_params", "dm_mlp_set_params", "dm_mlp_forward",
             "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict",
             "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
-            "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal", "dm_density_on_grid"]
+            "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal", "dm_density_on_grid",
+            "dm_set_factored_options", "dm_solve_overlap", "dm_get_preconditioner", "dm_cg_stats"]
 
 
 class DMError(RuntimeError):
@@ -109,6 +110,10 @@ def load(path: str = LIB_PATH):
         "dm_chebyshev_block_multi": (_I, [_P, _P, _LL, _I, _I, _P, _P, _P]),
         "dm_dos": (_I, [_P, _I, _I, _P, _D, _P]),
         "dm_set_operator_form": (_I, [_P, _I]),
+        "dm_set_factored_options": (_I, [_P, _D, _I, _D, _I]),
+        "dm_solve_overlap": (_I, [_P, _P, _LL, _P]),
+        "dm_get_preconditioner": (_I, [_P, _P, _P, _P, _P]),
+        "dm_cg_stats": (_I, [_P, _P, _P, _P]),
         "dm_set_fock_orthonormal": (_I, [_P, _LL, _P, _P, _P]),
         "dm_density_on_grid": (_I, [_P, _LL, _P, _P, _P, _D, _P, _D, _P, _LL, _P, _P]),
         "dm_trace": (_I, [_P, _D, _D, _P, _P]),
@@ -282,6 +287,37 @@ class Context:
             self.h, cp, n, int(order), ns, ctypes.c_void_p(mu_a.ctypes.data), ctypes.c_void_p(be_a.ctypes.data),
             ptrs if P_outs is not None else None))
         return P_outs
+
+    def dm_set_factored_options(self, cg_tol=1e-11, cg_max_iter=2000, fsai_drop=1e-3, fsai_max_per_row=128):
+        self._check(self._lib.dm_set_factored_options(self.h, float(cg_tol), int(cg_max_iter), float(fsai_drop),
+                                                      int(fsai_max_per_row)))
+
+    def dm_solve_overlap(self, B):
+        """X = S^-1 B for B of shape (K, n) (numpy); returns X (K, n)."""
+        Bc = np.asfortranarray(np.asarray(B, dtype=np.float64).reshape(self.K, -1))
+        X = np.zeros_like(Bc, order="F")
+        n = Bc.shape[1]
+        self._check(self._lib.dm_solve_overlap(self.h, ctypes.c_void_p(Bc.ctypes.data), n,
+                                               ctypes.c_void_p(X.ctypes.data)))
+        return X
+
+    def dm_get_preconditioner(self):
+        """(rowptr, col, val) of the FSAI factor G in CSR (numpy)."""
+        nnz = ctypes.c_longlong()
+        self._check(self._lib.dm_get_preconditioner(self.h, ctypes.byref(nnz), None, None, None))
+        rp = np.zeros(self.K + 1, dtype=np.int64)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value, dtype=np.float64)
+        self._check(self._lib.dm_get_preconditioner(self.h, None, ctypes.c_void_p(rp.ctypes.data),
+                                                    ctypes.c_void_p(col.ctypes.data),
+                                                    ctypes.c_void_p(val.ctypes.data)))
+        return rp, col, val
+
+    def dm_cg_stats(self):
+        """(solves, iterations, max_iterations) since the last call."""
+        ns, it, mx = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+        self._check(self._lib.dm_cg_stats(self.h, ctypes.byref(ns), ctypes.byref(it), ctypes.byref(mx)))
+        return ns.value, it.value, mx.value
 
     def dm_dos(self, kind, energies, sigma=0.0):
         """Density of states at `energies` from the accumulated moments

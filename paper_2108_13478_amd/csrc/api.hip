@@ -59,7 +59,12 @@ struct Op {
     DevBuf<long long> F_rowptr;
     DevBuf<int> F_col;
     DevBuf<double> F_val;
+    // factored form (DM_FORM_FACTORED): sparse F, S and the FSAI factor G;
+    // no dense arrays
+    FactOp* fact = nullptr;
     void release() {
+        if (fact) fact_destroy(fact);
+        fact = nullptr;
         S_rowptr.release(); S_col.release(); S_val.release();
         Sinv.release(); HT.release(); HNbuf.release();
         Lsym.release(); Usym.release(); Hsym.release();
@@ -97,6 +102,11 @@ struct dm_ctx {
     int tuned_cfg = -1;
     // operator form used by the next dm_set_fock
     int form = DM_FORM_GENERAL;
+    // factored form: solve tolerance and iteration limit, FSAI pattern
+    double cg_tol = 1e-11;
+    int cg_max_iter = 2000;
+    double fsai_drop = 1e-3;
+    int fsai_cap = 128;
 
     // workspace
     DevBuf<double> Ua, Ub, Z, P;  // sized in bytes via double slots
@@ -356,10 +366,18 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
     for (int j = 0; j < ksteps; ++j) {
         double* vj = V.p + (size_t)j * ld;
         double* qj = Q.p + (size_t)j * ld;
-        if (op.orth)
+        if (op.orth) {
             LZ(csr_spmv(K, op.F_rowptr.p, op.F_col.p, op.F_val.p, vj, wv.p, s));
-        else
+        } else if (op.fact) {
+            int conv = 1;
+            LZ(fact_apply(op.fact, vj, wv.p, c->cg_tol, c->cg_max_iter, &conv, s));
+            if (!conv) {
+                cleanup();
+                return set_err(c, DM_E_NOCONV, "Lanczos: the solve with S did not converge within the iteration limit");
+            }
+        } else {
             LZ(gemv_rows(K, op.HT.p, ld, vj, wv.p, s));
+        }
         LZ(dots_cols(K, 1, qj, ld, wv.p, alpha + j, s));
         LZ(lanczos_three_term(K, wv.p, vj, j ? vj - ld : nullptr, alpha + j, j ? beta + j - 1 : beta, s));
         for (int rep = 0; rep < 2; ++rep) {
@@ -409,6 +427,10 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
 
 dm_status normalize(dm_ctx* c, Op& op) {
     const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
+    if (op.form == DM_FORM_FACTORED) {  // H_N is applied, never formed
+        op.hn_precision = c->precision;
+        return DM_OK;
+    }
     if (op.orth) {
         const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
         HIPTRY(c, ensure(op.HNbuf, (size_t)op.Kp * op.Kp * tsz / 8));
@@ -515,6 +537,8 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
     const std::vector<int>& scol = Sh.col;
     const std::vector<double>& sval = Sh.val;
     hipStream_t s = c->stream;
+    if (op.fact) fact_destroy(op.fact);
+    op.fact = nullptr;
     op.K = K;
     op.Kp = (int)round_up(K, kRowPad);
     const int Kp = op.Kp;
@@ -663,6 +687,38 @@ dm_status build_orth(dm_ctx* c, Op& op, long long K, const HostCsr& Fh) {
     return normalize(c, op);
 }
 
+// Operator setup in the factored form: S in CSR on the device (Lanczos
+// products, start vectors), F, S and the FSAI factor G in row groups, the
+// Lanczos interval of S^-1 F through solves with S.
+dm_status build_fact(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const HostCsr& Sh) {
+    hipStream_t s = c->stream;
+    op.release();
+    op.K = K;
+    op.Kp = (int)round_up(K, kRowPad);
+    HIPTRY(c, ensure(op.S_rowptr, (size_t)K + 1));
+    HIPTRY(c, ensure(op.S_col, Sh.col.size()));
+    HIPTRY(c, ensure(op.S_val, Sh.val.size()));
+    HIPTRY(c, hipMemcpyAsync(op.S_rowptr.p, Sh.rp.data(), Sh.rp.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.S_col.p, Sh.col.data(), Sh.col.size() * 4, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.S_val.p, Sh.val.data(), Sh.val.size() * 8, hipMemcpyHostToDevice, s));
+    op.fact = fact_create();
+    if (!op.fact) return set_err(c, DM_E_OOM, "factored form: host allocation failed");
+    int bad = 0;
+    const hipError_t e = fact_setup(op.fact, (int)K, Fh.rp.data(), Fh.col.data(), Fh.val.data(), Sh.rp.data(),
+                                    Sh.col.data(), Sh.val.data(), c->fsai_drop, c->fsai_cap, &bad, s);
+    if (e == hipErrorInvalidValue)
+        return set_err(c, DM_E_ARG, "factored form: more than 2^31 - 1 stored entries");
+    if (e != hipSuccess) return fail_hip(c, e, "factored setup");
+    if (bad)
+        return set_err(c, DM_E_NOTSPD, "overlap matrix is not positive definite (FSAI block of row " +
+                                           std::to_string(bad - 1) + ")");
+    op.form = DM_FORM_FACTORED;
+    dm_status st = lanczos_bounds(c, op);
+    if (st != DM_OK) return st;
+    HIPTRY(c, fact_reset_stats(op.fact, s));  // count the solves of the passes only
+    return normalize(c, op);
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -776,7 +832,7 @@ dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const i
     HostCsr Fh, Sh;
     st = load_csr_pair(c, K, F_rowptr, F_col, F_val, S_rowptr, S_col, S_val, Fh, Sh);
     if (st != DM_OK) return st;
-    st = build_op(c, c->op, K, Fh, Sh, c->form);
+    st = c->form == DM_FORM_FACTORED ? build_fact(c, c->op, K, Fh, Sh) : build_op(c, c->op, K, Fh, Sh, c->form);
     if (st != DM_OK) return st;
     c->have_fock = true;
     return DM_OK;
@@ -833,8 +889,65 @@ dm_status dm_set_operator_form(dm_ctx* c, int form) {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
-    if (form != DM_FORM_GENERAL && form != DM_FORM_SYMMETRIC) return set_err(c, DM_E_ARG, "unknown operator form");
+    if (form != DM_FORM_GENERAL && form != DM_FORM_SYMMETRIC && form != DM_FORM_FACTORED)
+        return set_err(c, DM_E_ARG, "unknown operator form");
     c->form = form;
+    return DM_OK;
+}
+
+dm_status dm_set_factored_options(dm_ctx* c, double cg_tol, int cg_max_iter, double fsai_drop,
+                                  int fsai_max_per_row) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!(cg_tol > 0.0 && cg_tol < 1.0) || cg_max_iter < 1 || !(fsai_drop >= 0.0) || !std::isfinite(fsai_drop) ||
+        fsai_max_per_row < 1 || fsai_max_per_row > 128)
+        return set_err(c, DM_E_ARG, "need 0 < cg_tol < 1, cg_max_iter >= 1, fsai_drop >= 0, 1 <= max_per_row <= 128");
+    c->cg_tol = cg_tol;
+    c->cg_max_iter = cg_max_iter;
+    c->fsai_drop = fsai_drop;
+    c->fsai_cap = fsai_max_per_row;
+    return DM_OK;
+}
+
+dm_status dm_solve_overlap(dm_ctx* c, const double* B, long long nrhs, double* X) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock || !c->op.fact) return set_err(c, DM_E_STATE, "no factored operator loaded");
+    if (nrhs < 0 || nrhs > c->op.K * 64 || (nrhs > 0 && (!B || !X))) return set_err(c, DM_E_ARG, "bad right-hand sides");
+    if (nrhs == 0) return DM_OK;
+    int conv = 1;
+    const hipError_t e = fact_solve(c->op.fact, (int)nrhs, B, c->op.K, X, c->op.K, c->cg_tol, c->cg_max_iter,
+                                    1024, &conv, c->stream);
+    if (e == hipErrorOutOfMemory) return set_err(c, DM_E_OOM, "solve: device allocation failed");
+    if (e != hipSuccess) return fail_hip(c, e, "solve with S");
+    if (!conv) return set_err(c, DM_E_NOCONV, "the conjugate-gradient solve with S did not converge within the iteration limit");
+    return DM_OK;
+}
+
+dm_status dm_get_preconditioner(dm_ctx* c, long long* nnz, long long* rowptr, int* col, double* val) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock || !c->op.fact) return set_err(c, DM_E_STATE, "no factored operator loaded");
+    if (nnz) *nnz = fact_precond_nnz(c->op.fact);
+    HIPTRY(c, fact_precond_copy(c->op.fact, rowptr, col, val, c->stream));
+    return DM_OK;
+}
+
+dm_status dm_cg_stats(dm_ctx* c, long long* solves, long long* iterations, int* max_iterations) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock || !c->op.fact) return set_err(c, DM_E_STATE, "no factored operator loaded");
+    long long ns = 0, it = 0;
+    int mx = 0;
+    HIPTRY(c, fact_stats(c->op.fact, &ns, &it, &mx, c->stream));
+    HIPTRY(c, fact_reset_stats(c->op.fact, c->stream));
+    if (solves) *solves = ns;
+    if (iterations) *iterations = it;
+    if (max_iterations) *max_iterations = mx;
     return DM_OK;
 }
 
@@ -848,6 +961,7 @@ dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
     if (which == DM_OP_HSYM && c->op.form != DM_FORM_SYMMETRIC)
         return set_err(c, DM_E_STATE, "the loaded operator was not built in the symmetric form");
     if (c->op.orth) return set_err(c, DM_E_STATE, "an orthonormal-basis operator keeps no dense setup products");
+    if (c->op.fact) return set_err(c, DM_E_STATE, "a factored operator keeps no dense setup products");
     const size_t K = (size_t)c->op.K, Kp = (size_t)c->op.Kp;
     hipStream_t s = c->stream;
     if (which == DM_OP_SINV || which == DM_OP_HSYM) {
@@ -884,11 +998,77 @@ dm_status dm_set_precision(dm_ctx* c, int precision) {
     return normalize(c, c->op);
 }
 
+// End of a pass: the moments accumulated so far must be finite and bounded.
+static dm_status finish_pass(dm_ctx* c, int order, long long ncols) {
+    hipStream_t s = c->stream;
+    int flag = 0;
+    HIPTRY(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<double> hm((size_t)order + 1);
+    HIPTRY(c, hipMemcpyAsync(hm.data(), c->mom.p, hm.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    c->ncols_done += ncols;
+    const double lim = 1e8 * (double)(c->ncols_done + 1);
+    bool bad = flag != 0;
+    for (double x : hm)
+        if (!std::isfinite(x) || std::fabs(x) > lim) bad = true;
+    if (bad)
+        return set_err(c, DM_E_BOUNDS,
+                       "Chebyshev recursion diverged: the spectral interval does not enclose the spectrum");
+    return DM_OK;
+}
+
+// Factored form: blocks of up to `bw` columns, each a full recursion with one
+// solve with S per step (FP64).
+static dm_status run_fact_blocks(dm_ctx* c, const std::vector<long long>& hc, long long ncols, int order,
+                                 int nsets, int cstride, double ebar, double de, double* const* P_outs) {
+    hipStream_t s = c->stream;
+    const long long K = c->op.K;
+    const long long Kr = round_up(K, 64);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    const size_t budget = std::max<size_t>((size_t)16 << 30, free_b / 2);
+    const size_t per_col = (size_t)Kr * 8 * (13 + nsets);
+    long long bw = c->opt.block_width > 0 ? c->opt.block_width : ncols;
+    bw = std::min<long long>(bw, std::max<long long>(64, (long long)(budget / per_col) / 64 * 64));
+    bw = std::min(bw, ncols);
+    HIPTRY(c, ensure(c->cols, (size_t)bw));
+    std::vector<double*> dst((size_t)nsets);
+    for (long long off = 0; off < ncols; off += bw) {
+        const int nc = (int)std::min<long long>(bw, ncols - off);
+        HIPTRY(c, hipMemcpyAsync(c->cols.p, hc.data() + off, (size_t)nc * 8, hipMemcpyHostToDevice, s));
+        for (int q = 0; q < nsets; ++q) dst[q] = (P_outs && P_outs[q]) ? P_outs[q] + off * K : nullptr;
+        FactBlockArgs fa{};
+        fa.nc = nc;
+        fa.cols = c->cols.p;
+        fa.order = order;
+        fa.coef = c->coef.p;
+        fa.cstride = cstride;
+        fa.nsets = nsets;
+        fa.ebar = ebar;
+        fa.de = de;
+        fa.tol = c->cg_tol;
+        fa.max_iter = c->cg_max_iter;
+        fa.mom = c->mom.p;
+        fa.flag = c->flag.p;
+        fa.P_out = dst.data();
+        int conv = 1;
+        const hipError_t e = fact_block(c->op.fact, fa, &conv, s);
+        if (e == hipErrorOutOfMemory) return set_err(c, DM_E_OOM, "factored pass: device allocation failed");
+        if (e != hipSuccess) return fail_hip(c, e, "factored pass");
+        if (!conv)
+            return set_err(c, DM_E_NOCONV,
+                           "the conjugate-gradient solve with S did not converge within the iteration limit");
+    }
+    return DM_OK;
+}
+
 // One recursion pass over `cols` accumulating nsets density-matrix blocks,
 // set q with the coefficients of (mus[q], betas[q]); the moments are shared.
 static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int order, int nsets,
                           const double* mus, const double* betas, double* const* P_outs) {
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (c->op.fact && c->precision != DM_FP64)
+        return set_err(c, DM_E_STATE, "the factored form runs in FP64 only");
     if (order < 2 || order > (1 << 20)) return set_err(c, DM_E_ARG, "order must be >= 2");
     if (nsets < 1 || nsets > DM_MAX_SETS) return set_err(c, DM_E_ARG, "need 1 <= n_sets <= DM_MAX_SETS");
     for (int q = 0; q < nsets; ++q)
@@ -924,6 +1104,14 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
     for (int q = 0; q < nsets; ++q)
         HIPTRY(c, cheb_coefficients(order, M, ebar, de, mus[q], betas[q], c->fk.p, c->coef.p + (size_t)q * cstride, s));
     HIPTRY(c, fill_i32(c->flag.p, 0, 4, s));
+    if (c->op.fact) {
+        const dm_status fs = run_fact_blocks(c, hc, ncols, order, nsets, cstride, ebar, de, P_outs);
+        if (fs != DM_OK) {
+            c->mom_order = -1;  // partial moments of a failed pass
+            return fs;
+        }
+        return finish_pass(c, order, ncols);
+    }
 
     // pass width
     const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
@@ -1010,20 +1198,7 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
                                        hipMemcpyDefault, s));
         }
     }
-    int flag = 0;
-    HIPTRY(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    std::vector<double> hm((size_t)order + 1);
-    HIPTRY(c, hipMemcpyAsync(hm.data(), c->mom.p, hm.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPTRY(c, hipStreamSynchronize(s));
-    c->ncols_done += ncols;
-    const double lim = 1e8 * (double)(c->ncols_done + 1);
-    bool bad = flag != 0;
-    for (double x : hm)
-        if (!std::isfinite(x) || std::fabs(x) > lim) bad = true;
-    if (bad)
-        return set_err(c, DM_E_BOUNDS,
-                       "Chebyshev recursion diverged: the spectral interval does not enclose the spectrum");
-    return DM_OK;
+    return finish_pass(c, order, ncols);
 }
 
 dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, int order,
@@ -1308,6 +1483,7 @@ dm_status dm_set_pass_shape(dm_ctx* c, int width, int cfg) {
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (c->op.fact) return set_err(c, DM_E_STATE, "tile shapes do not apply to the factored form");
     if (width < 1 || cfg < 0 || cfg >= cheb_num_tile_configs() ||
         !cheb_cfg_fits(cfg, c->precision, c->op.Kp, (int)round_up(width, cheb_tile_cols(cfg))))
         return set_err(c, DM_E_ARG, "pass width must be >= 1 and the tile shape one that fits this operator and precision");
@@ -1332,6 +1508,7 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (c->op.fact) return set_err(c, DM_E_STATE, "tile shapes do not apply to the factored form");
     if (ncols < 1 || steps < 1) return set_err(c, DM_E_ARG, "need ncols >= 1 and steps >= 1");
     hipStream_t s = c->stream;
     const int K = (int)c->op.K, Kp = c->op.Kp;
@@ -1458,6 +1635,7 @@ dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, do
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    if (c->op.fact) return set_err(c, DM_E_STATE, "stochastic moments need a general or symmetric operator");
     if (n_mom < 1 || n_vec < 1 || !xi || !m_out) return set_err(c, DM_E_ARG, "bad stochastic-moment arguments");
     return stoch_moments_op(c, c->op, n_mom, n_vec, xi, m_out);
 }
@@ -1707,6 +1885,8 @@ dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) {
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (n < 1 || !cl) return set_err(c, DM_E_ARG, "need n >= 1 clusters");
+    if (c->form == DM_FORM_FACTORED)
+        return set_err(c, DM_E_STATE, "the batch runs in the general or symmetric form");
     delete c->bstate;
     c->bstate = nullptr;
     for (auto& o : c->batch) o.release();

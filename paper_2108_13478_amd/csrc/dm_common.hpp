@@ -243,4 +243,49 @@ hipError_t lanczos_reorth(int K, int n, double* w, const double* V, long ldv, co
 hipError_t lanczos_next(int K, const double* w, const double* sw, const double* wSw,
                         double* beta_out, double* vnext, double* qnext, hipStream_t s);
 
+// ----------------------------------------------------------------- factored form
+// H = S^-1 F applied as a sparse product with F and a conjugate-gradient
+// solve with S, preconditioned by an FSAI factor G (S^-1 ~ G^T G), all FP64.
+struct FactOp;
+FactOp* fact_create();
+void fact_destroy(FactOp* f);
+// Host CSR F and S (K x K, sorted columns).  The FSAI pattern of row i keeps
+// the lower entries with |S_ij| >= drop sqrt(S_ii S_jj), at most cap - 1 of
+// them (the largest), plus the diagonal; cap <= 128.  *bad_row = row + 1 of
+// a row whose S[J, J] is not positive definite (0 = none).
+hipError_t fact_setup(FactOp* f, int K, const long long* Frp, const int* Fcol, const double* Fval,
+                      const long long* Srp, const int* Scol, const double* Sval, double drop, int cap,
+                      int* bad_row, hipStream_t s);
+long long fact_precond_nnz(const FactOp* f);
+// G in CSR (K + 1 row pointers, columns, values); host or device pointers, any may be null.
+hipError_t fact_precond_copy(const FactOp* f, long long* rp, int* col, double* val, hipStream_t s);
+// X = S^-1 B for n columns (K x n column-major, host or device), at most
+// wmax columns per solve; *converged = 0 if a solve hit max_iter.
+hipError_t fact_solve(FactOp* f, int n, const double* B, long long ldb, double* X, long long ldx, double tol,
+                      int max_iter, int wmax, int* converged, hipStream_t s);
+// y = S^-1 (F x) for one device K-vector.
+hipError_t fact_apply(FactOp* f, const double* x, double* y, double tol, int max_iter, int* converged,
+                      hipStream_t s);
+// One block of the recursion: U_0 = S^-1 e_cols, U_1 = H_N U_0,
+// U_{l+1} = 2 H_N U_l - U_{l-1} up to U_order; P_q = sum_l coef[q cstride + l] U_l;
+// mom[l] += sum over the block of S[:, col] . U_l.
+struct FactBlockArgs {
+    int nc;                 // columns of the block
+    const long long* cols;  // device, nc column indices
+    int order;
+    const double* coef;     // device
+    int cstride, nsets;
+    double ebar, de;
+    double tol;
+    int max_iter;
+    double* mom;            // device, order + 1 entries, accumulated
+    int* flag;              // device, flag[0] |= 1 on a non-finite moment
+    double* const* P_out;   // nsets destinations (K x nc column-major, host or device) or null
+};
+hipError_t fact_block(FactOp* f, const FactBlockArgs& a, int* converged, hipStream_t s);
+// Solves since the last reset, the largest per-group sum of iterations and
+// the largest iteration count of one solve.
+hipError_t fact_stats(FactOp* f, long long* solves, long long* iters, int* max_iters, hipStream_t s);
+hipError_t fact_reset_stats(FactOp* f, hipStream_t s);
+
 }  // namespace dm

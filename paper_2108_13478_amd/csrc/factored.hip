@@ -1,0 +1,1006 @@
+// Factored operator form: the recursion applies H = S^-1 F without forming
+// it, as one sparse product with F followed by a solve with S, the way the
+// paper applies the overlap inverse (Methods, column-by-column evaluation of
+// the density matrix, and its footnote on the overlap solve by preconditioned
+// conjugate gradients).  The preconditioner here is a factorised sparse
+// approximate inverse (FSAI: S^-1 ~ G^T G with G sparse and lower
+// triangular) instead of the paper's incomplete Cholesky factor: applying
+// it is two sparse products, with none of the dependency chains of
+// triangular solves.
+//
+// Data layout.  A block of W columns (W a multiple of 64) is stored row-
+// interleaved, v[i * W + c]: a wavefront takes 64 adjacent columns in its
+// lanes, so each gathered matrix row is one 512-byte coalesced load.  Sparse
+// matrices are stored in row groups of kRG = 4 rows (one atom of the
+// four-function basis): the group keeps the sorted union of its rows'
+// columns, and every listed column carries four values, zero where a row has
+// no entry.  One gathered row of the block then feeds four output rows.
+//
+// The conjugate-gradient iteration runs W independent systems in lock step,
+// each with its own step lengths.  Per-column dot products are reduced in
+// two fixed-order stages inside the producing kernel: every workgroup writes
+// its partial sums, and the last workgroup of a 64-column group to finish
+// (atomic ticket) adds them in index order and updates the column scalars.
+// Converged columns keep their solution; a 64-column group whose columns have
+// all converged skips every later kernel of the solve.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "dm_common.hpp"
+
+namespace dm {
+namespace {
+
+constexpr int kRG = 4;              // rows per group
+constexpr int kWv = 16;             // waves per workgroup of the row kernels
+constexpr int kRowsWG = kRG * kWv;  // 64 rows per workgroup
+constexpr int kFsaiMax = 128;       // largest pattern of one FSAI row (LDS)
+constexpr int kChunk = 8;           // iterations between convergence polls
+
+struct RgView {
+    const long long* ptr;  // ngroups + 1
+    const int* col;        // sorted union of the group's columns
+    const double* val;     // kRG values per listed column
+};
+
+__device__ inline void st_agent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_agent(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sums v over the 16 waves of the workgroup for each lane (column); the
+// result is valid in wave 0.  Fixed order.
+__device__ inline double wg_column_sum(double v, double (*red)[64]) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    red[w][lane] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (w == 0)
+        for (int k = 0; k < kWv; ++k) s += red[k][lane];
+    return s;
+}
+
+// Wave 0 has written this workgroup's partials; returns true in the last
+// workgroup of the column group to arrive (uniform over the workgroup).
+__device__ inline bool arrive_last(int* ticket) {
+    __shared__ int last;
+    if (threadIdx.x < 64) __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    const bool is_last = last != 0;
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+// In the last workgroup: column sums of part[x * W + y * 64 + lane] over x <
+// gridDim.x, in fixed order (16 strided slices, then the slices in order).
+// Valid in wave 0.
+__device__ inline double last_column_sum(const double* part, int W, double (*red)[64]) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = blockIdx.y * 64 + lane;
+    double s = 0.0;
+    for (int x = w; x < (int)gridDim.x; x += kWv) s += ld_agent(part + (size_t)x * W + col);
+    __syncthreads();
+    return wg_column_sum(s, red);
+}
+
+struct CgArgs {
+    int W;
+    const double* B;
+    double *X, *R, *Z, *Pd, *Q, *T;
+    double *bb, *rz, *alpha, *beta;
+    int* done;
+    int* active;  // per 64-column group: columns not yet converged
+    int* iters;   // per 64-column group: iterations of the current solve
+    int* ticket;  // per 64-column group
+    double* part; // gridDim.x x W
+    double tol2;
+    int first;
+};
+
+enum { kPlain = 0, kPq = 1, kRz = 2 };
+
+// Y = A X over the block (kPlain); the conjugate-gradient products fuse their
+// vector updates and dot products:
+//   kPq: Pd = Z + beta Pd, Q = A Z + beta Q (= A Pd), pq = Pd . Q,
+//        last workgroup: alpha = rz / pq;
+//   kRz: Z = A T (the preconditioner's second factor), rz_new = R . Z,
+//        last workgroup: beta = rz_new / rz (0 on the first iteration).
+template <int MODE>
+__global__ void __launch_bounds__(1024) rg_spmm_kernel(RgView A, const double* __restrict__ Xin,
+                                                       double* __restrict__ Yout, CgArgs a) {
+    __shared__ double red[kWv][64];
+    const int y = blockIdx.y;
+    if (a.active && a.active[y] == 0) return;
+    const int W = a.W;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int g = blockIdx.x * kWv + wv;
+    const int c = y * 64 + lane;
+    const long long p0 = A.ptr[g], p1 = A.ptr[g + 1];
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    const double* xc = Xin + c;
+    long long p = p0;
+    for (; p + 8 <= p1; p += 8) {
+        int j[8];
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) j[u] = A.col[p + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = xc[(size_t)j[u] * W];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double* v = A.val + (p + u) * kRG;
+            acc0 += v[0] * x[u];
+            acc1 += v[1] * x[u];
+            acc2 += v[2] * x[u];
+            acc3 += v[3] * x[u];
+        }
+    }
+    for (; p < p1; ++p) {
+        const double x = xc[(size_t)A.col[p] * W];
+        const double* v = A.val + p * kRG;
+        acc0 += v[0] * x;
+        acc1 += v[1] * x;
+        acc2 += v[2] * x;
+        acc3 += v[3] * x;
+    }
+    const double acc[4] = {acc0, acc1, acc2, acc3};
+    const size_t base = (size_t)g * kRG * W + c;
+    if (MODE == kPlain) {
+#pragma unroll
+        for (int r = 0; r < kRG; ++r) Yout[base + (size_t)r * W] = acc[r];
+        return;
+    }
+    double d = 0.0;
+    if (MODE == kPq) {
+        const double b = a.beta[c];
+#pragma unroll
+        for (int r = 0; r < kRG; ++r) {
+            const size_t e = base + (size_t)r * W;
+            // beta = 0 (first iteration, converged column): Pd and Q may
+            // hold anything, so they are not read
+            const double pd = b != 0.0 ? Xin[e] + b * a.Pd[e] : Xin[e];
+            const double q = b != 0.0 ? acc[r] + b * a.Q[e] : acc[r];
+            a.Pd[e] = pd;
+            a.Q[e] = q;
+            d += pd * q;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kRG; ++r) {
+            const size_t e = base + (size_t)r * W;
+            a.Z[e] = acc[r];
+            d += a.R[e] * acc[r];
+        }
+    }
+    const double s = wg_column_sum(d, red);
+    if (threadIdx.x < 64) st_agent(a.part + (size_t)blockIdx.x * W + c, s);
+    if (!arrive_last(a.ticket + y)) return;
+    const double tot = last_column_sum(a.part, W, red);
+    if (threadIdx.x < 64) {
+        const bool dn = a.done[c] != 0;
+        if (MODE == kPq) {
+            double al = 0.0;
+            if (!dn) {
+                if (tot > 0.0)
+                    al = a.rz[c] / tot;
+                else
+                    a.done[c] = 1;  // zero search direction: the residual is already zero
+            }
+            a.alpha[c] = al;
+        } else {
+            a.beta[c] = (a.first || dn || !(a.rz[c] > 0.0)) ? 0.0 : tot / a.rz[c];
+            a.rz[c] = tot;
+        }
+        if (threadIdx.x == 0) __hip_atomic_store(a.ticket + y, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// X = 0, R = B, bb = B . B per column; last workgroup: done = (bb == 0),
+// active count, beta = 0.
+__global__ void __launch_bounds__(1024) cg_init_kernel(CgArgs a) {
+    __shared__ double red[kWv][64];
+    const int W = a.W, y = blockIdx.y;
+    const int g = blockIdx.x * kWv + (threadIdx.x >> 6);
+    const int c = y * 64 + (threadIdx.x & 63);
+    double d = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRG; ++r) {
+        const size_t e = ((size_t)g * kRG + r) * W + c;
+        const double b = a.B[e];
+        a.X[e] = 0.0;
+        a.R[e] = b;
+        d += b * b;
+    }
+    const double s = wg_column_sum(d, red);
+    if (threadIdx.x < 64) st_agent(a.part + (size_t)blockIdx.x * W + c, s);
+    if (!arrive_last(a.ticket + y)) return;
+    const double tot = last_column_sum(a.part, W, red);
+    if (threadIdx.x < 64) {
+        const bool dn = !(tot > 0.0);
+        a.bb[c] = tot;
+        a.done[c] = dn ? 1 : 0;
+        a.beta[c] = 0.0;
+        a.alpha[c] = 0.0;
+        const unsigned long long live = __ballot(!dn);
+        if (threadIdx.x == 0) {
+            a.active[y] = __popcll(live);
+            a.iters[y] = 0;
+            __hip_atomic_store(a.ticket + y, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// X += alpha Pd, R -= alpha Q, rr = R . R; last workgroup: columns with
+// rr <= tol^2 bb are done, new active count.
+__global__ void __launch_bounds__(1024) cg_update_kernel(CgArgs a) {
+    __shared__ double red[kWv][64];
+    const int W = a.W, y = blockIdx.y;
+    if (a.active[y] == 0) return;
+    const int g = blockIdx.x * kWv + (threadIdx.x >> 6);
+    const int c = y * 64 + (threadIdx.x & 63);
+    const double al = a.alpha[c];
+    double d = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRG; ++r) {
+        const size_t e = ((size_t)g * kRG + r) * W + c;
+        a.X[e] += al * a.Pd[e];
+        const double rv = a.R[e] - al * a.Q[e];
+        a.R[e] = rv;
+        d += rv * rv;
+    }
+    const double s = wg_column_sum(d, red);
+    if (threadIdx.x < 64) st_agent(a.part + (size_t)blockIdx.x * W + c, s);
+    if (!arrive_last(a.ticket + y)) return;
+    const double tot = last_column_sum(a.part, W, red);
+    if (threadIdx.x < 64) {
+        bool dn = a.done[c] != 0;
+        if (!dn && tot <= a.tol2 * a.bb[c]) {
+            dn = true;
+            a.done[c] = 1;
+        }
+        const unsigned long long live = __ballot(!dn);
+        if (threadIdx.x == 0) {
+            a.active[y] = __popcll(live);
+            a.iters[y] += 1;
+            __hip_atomic_store(a.ticket + y, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Per solve: fold the iteration counts into the totals, flag groups that
+// did not converge.
+__global__ void cg_fold_kernel(int ngroups, const int* active, const int* iters, long long* tot,
+                               int* mx, int* notconv) {
+    const int y = threadIdx.x;
+    if (y >= ngroups) return;
+    tot[y] += iters[y];
+    mx[y] = max(mx[y], iters[y]);
+    if (active[y] != 0) notconv[0] = 1;
+}
+
+// One step of the recursion on the block (eq. ChebychevExpansion):
+//   Unew = sx X + su Ucur - (has_prev ? Uprev : 0)   -> Uout (may alias Uprev)
+//   P_q (+)= coef[q cstride + l] Unew for q < nsets   (assigned when l == 0)
+//   mpart[l * ngroups + y] = sum over the group's columns of Zm . Unew
+struct StepArgs {
+    int W, l, nsets, cstride, has_prev;
+    const double* X;
+    const double* Ucur;
+    const double* Uprev;
+    double* Uout;
+    double sx, su;
+    const double* coef;
+    double* P;
+    long long pstride;
+    const double* Zm;
+    double* wgpart;  // gridDim.y x gridDim.x
+    double* mpart;
+    int* ticket;
+};
+
+__global__ void __launch_bounds__(1024) fact_step_kernel(StepArgs a) {
+    __shared__ double red[kWv][64];
+    const int W = a.W, y = blockIdx.y;
+    const int g = blockIdx.x * kWv + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int c = y * 64 + lane;
+    double d = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRG; ++r) {
+        const size_t e = ((size_t)g * kRG + r) * W + c;
+        double u = a.sx * a.X[e];
+        if (a.su != 0.0) u += a.su * a.Ucur[e];
+        if (a.has_prev) u -= a.Uprev[e];
+        a.Uout[e] = u;
+        for (int q = 0; q < a.nsets; ++q) {
+            double* P = a.P + (size_t)q * a.pstride;
+            const double cq = a.coef[q * a.cstride + a.l];
+            P[e] = a.l == 0 ? cq * u : P[e] + cq * u;
+        }
+        d += a.Zm[e] * u;
+    }
+    double s = wg_column_sum(d, red);
+    if (threadIdx.x < 64) {
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (threadIdx.x == 0) st_agent(a.wgpart + (size_t)y * gridDim.x + blockIdx.x, s);
+    }
+    if (!arrive_last(a.ticket + y)) return;
+    if (threadIdx.x < 64) {
+        double t = 0.0;
+        for (int x = lane; x < (int)gridDim.x; x += 64) t += ld_agent(a.wgpart + (size_t)y * gridDim.x + x);
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (threadIdx.x == 0) {
+            a.mpart[(size_t)a.l * gridDim.y + y] = t;
+            __hip_atomic_store(a.ticket + y, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Y = unit vectors e_{cols[c]} (c < nc), zero elsewhere.
+__global__ void fact_unit_kernel(int Kr, int W, int nc, const long long* cols, double* Y) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)Kr * W) return;
+    const int c = (int)(e % W);
+    const long long i = (long long)(e / W);
+    Y[e] = (c < nc && cols[c] == i) ? 1.0 : 0.0;
+}
+
+// Zm[:, c] = column cols[c] of S (= its row: S is symmetric); Zm zero on entry.
+__global__ void fact_zm_kernel(int W, int nc, const long long* cols, const long long* Srp,
+                               const int* Scol, const double* Sval, double* Zm) {
+    const int c = blockIdx.x;
+    if (c >= nc) return;
+    const long long row = cols[c];
+    for (long long p = Srp[row] + threadIdx.x; p < Srp[row + 1]; p += blockDim.x)
+        Zm[(size_t)Scol[p] * W + c] = Sval[p];
+}
+
+// Column-major K x n (ld) <-> row-interleaved block (W), 32 x 32 tiles.
+__global__ void to_block_kernel(int K, int n, const double* src, long long ld, int W, double* dst) {
+    __shared__ double t[32][33];
+    const int i0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: ty < 8
+    for (int k = ty; k < 32; k += 8) {
+        const int i = i0 + tx, c = c0 + k;
+        t[k][tx] = (i < K && c < n) ? src[(size_t)c * ld + i] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int i = i0 + k, c = c0 + tx;
+        dst[(size_t)i * W + c] = t[tx][k];
+    }
+}
+
+__global__ void from_block_kernel(int K, int n, const double* src, int W, double* dst, long long ld) {
+    __shared__ double t[32][33];
+    const int i0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int i = i0 + k, c = c0 + tx;
+        t[k][tx] = src[(size_t)i * W + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int i = i0 + tx, c = c0 + k;
+        if (i < K && c < n) dst[(size_t)c * ld + i] = t[tx][k];
+    }
+}
+
+// rg_val[e] = src[idx[e]] (0 where idx[e] < 0)
+__global__ void gather_vals_kernel(long long n, const int* idx, const double* src, double* dst) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int k = idx[e];
+    dst[e] = k >= 0 ? src[k] : 0.0;
+}
+
+// One FSAI row per workgroup: with J the row's pattern (sorted, ending with
+// the row itself), factor S[J, J] = L L^T in LDS and solve L^T g = e_last;
+// g is row i of G on J (G S G^T then has a unit diagonal, and G = L_S^-1
+// when J is the whole lower triangle).  info[0] = some failing row + 1.
+__global__ void __launch_bounds__(256) fsai_kernel(const long long* Srp, const int* Scol,
+                                                   const double* Sval, const long long* Grp,
+                                                   const int* Gcol, double* Gval, int* info) {
+    __shared__ double A[kFsaiMax][kFsaiMax + 1];
+    __shared__ int J[kFsaiMax];
+    __shared__ double acc[kFsaiMax];
+    __shared__ int bad;
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63;
+    const long long q0 = Grp[i];
+    const int n = (int)(Grp[i + 1] - q0);
+    for (int t = tid; t < n; t += 256) J[t] = Gcol[q0 + t];
+    for (int e = tid; e < n * kFsaiMax; e += 256) A[e / kFsaiMax][e % kFsaiMax] = 0.0;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    // lower triangle of S[J, J]: row J[r] of S, columns found in J[0..r]
+    for (int r = w; r < n; r += 4) {
+        const int jr = J[r];
+        for (long long p = Srp[jr] + lane; p < Srp[jr + 1]; p += 64) {
+            const int k = Scol[p];
+            if (k > jr) continue;
+            int lo = 0, hi = r;  // search J[0..r]
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (J[mid] < k) lo = mid + 1; else hi = mid;
+            }
+            if (J[lo] == k) A[r][lo] = Sval[p];
+        }
+    }
+    __syncthreads();
+    // right-looking Cholesky, lower
+    for (int k = 0; k < n; ++k) {
+        if (tid == 0) {
+            const double dkk = A[k][k];
+            if (!(dkk > 0.0)) bad = 1;
+            A[k][k] = dkk > 0.0 ? sqrt(dkk) : 1.0;
+        }
+        __syncthreads();
+        if (bad) break;
+        const double piv = A[k][k];
+        for (int r = k + 1 + tid; r < n; r += 256) A[r][k] /= piv;
+        __syncthreads();
+        for (int r = k + 1 + w; r < n; r += 4)
+            for (int t = k + 1 + lane; t <= r; t += 64) A[r][t] -= A[r][k] * A[t][k];
+        __syncthreads();
+    }
+    if (bad) {
+        for (int t = tid; t < n; t += 256) Gval[q0 + t] = 0.0;
+        if (tid == 0) atomicCAS(info, 0, i + 1);
+        return;
+    }
+    // L^T g = e_{n-1} by columns of L, from the last unknown up
+    for (int t = tid; t < n; t += 256) acc[t] = t == n - 1 ? 1.0 : 0.0;
+    __syncthreads();
+    for (int t = n - 1; t >= 0; --t) {
+        const double gt = acc[t] / A[t][t];
+        __syncthreads();
+        if (tid == 0) acc[t] = gt;
+        for (int r = tid; r < t; r += 256) acc[r] -= A[t][r] * gt;
+        __syncthreads();
+    }
+    for (int t = tid; t < n; t += 256) Gval[q0 + t] = acc[t];
+}
+
+// --------------------------------------------------------------- host side
+template <typename T>
+struct Buf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t m) {
+        if (m <= n && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipMalloc(&p, std::max<size_t>(m, 1) * sizeof(T));
+        if (e == hipSuccess) n = m;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct RgMat {
+    Buf<long long> ptr;
+    Buf<int> col;
+    Buf<double> val;
+    Buf<int> src;  // G and G^T: value source index into the CSR values of G
+    long long nent = 0;
+    RgView view() const { return RgView{ptr.p, col.p, val.p}; }
+    void release() {
+        ptr.release(); col.release(); val.release(); src.release();
+        nent = 0;
+    }
+};
+
+// Row-group layout of a CSR matrix (rows >= K and groups beyond the matrix
+// are empty).  vals may be null; then srcidx[e] receives the CSR position
+// of each slot (-1 for the zero slots).
+void row_groups(int K, int Kr, const std::vector<long long>& rp, const std::vector<int>& ci,
+                const double* vals, std::vector<long long>& gptr, std::vector<int>& gcol,
+                std::vector<double>& gval, std::vector<int>& srcidx) {
+    const int ng = Kr / kRG;
+    gptr.assign((size_t)ng + 1, 0);
+    gcol.clear();
+    gval.clear();
+    srcidx.clear();
+    std::vector<long long> pos(kRG);
+    for (int g = 0; g < ng; ++g) {
+        for (int r = 0; r < kRG; ++r) {
+            const long long row = (long long)g * kRG + r;
+            pos[r] = row < K ? rp[row] : 0;
+        }
+        while (true) {
+            int next = 0x7fffffff;
+            for (int r = 0; r < kRG; ++r) {
+                const long long row = (long long)g * kRG + r;
+                if (row < K && pos[r] < rp[row + 1]) next = std::min(next, ci[pos[r]]);
+            }
+            if (next == 0x7fffffff) break;
+            gcol.push_back(next);
+            for (int r = 0; r < kRG; ++r) {
+                const long long row = (long long)g * kRG + r;
+                long long k = -1;
+                if (row < K && pos[r] < rp[row + 1] && ci[pos[r]] == next) k = pos[r]++;
+                if (vals)
+                    gval.push_back(k >= 0 ? vals[k] : 0.0);
+                else
+                    srcidx.push_back((int)k);
+            }
+        }
+        gptr[g + 1] = (long long)gcol.size();
+    }
+}
+
+}  // namespace
+
+struct FactOp {
+    int K = 0, Kr = 0;
+    RgMat S, F, G, GT;
+    Buf<long long> Srp, Grp;
+    Buf<int> Scol, Gcol;
+    Buf<double> Sval, Gval;
+    long long g_nnz = 0;
+    // workspace of width W
+    int W = 0;
+    Buf<double> B, X, R, Z, Pd, Q, T, U0, U1, Zm, P, Pout;
+    Buf<double> bb, rz, alpha, beta, part, wgpart, mpart;
+    Buf<int> done, active, iters, ticket, mx, notconv;
+    Buf<long long> tot;
+    int* h_active = nullptr;  // pinned, 2 x ngroups
+    int h_cap = 0;
+    int nsets_cap = 0, order_cap = 0;
+    long long solves = 0;
+    ~FactOp() {
+        for (RgMat* m : {&S, &F, &G, &GT}) m->release();
+        Srp.release(); Grp.release(); Scol.release(); Gcol.release(); Sval.release(); Gval.release();
+        for (auto* b : {&B, &X, &R, &Z, &Pd, &Q, &T, &U0, &U1, &Zm, &P, &Pout, &bb, &rz, &alpha, &beta, &part,
+                        &wgpart, &mpart})
+            b->release();
+        for (auto* b : {&done, &active, &iters, &ticket, &mx, &notconv}) b->release();
+        tot.release();
+        if (h_active) (void)hipHostFree(h_active);
+    }
+};
+
+namespace {
+
+#define FTRY(expr)                              \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+hipError_t upload_rg(RgMat& m, const std::vector<long long>& gptr, const std::vector<int>& gcol,
+                     const std::vector<double>& gval, const std::vector<int>& src, hipStream_t s) {
+    m.nent = (long long)gcol.size();
+    FTRY(m.ptr.ensure(gptr.size()));
+    FTRY(m.col.ensure(gcol.size()));
+    FTRY(m.val.ensure(gcol.size() * kRG));
+    FTRY(hipMemcpyAsync(m.ptr.p, gptr.data(), gptr.size() * 8, hipMemcpyHostToDevice, s));
+    if (!gcol.empty()) FTRY(hipMemcpyAsync(m.col.p, gcol.data(), gcol.size() * 4, hipMemcpyHostToDevice, s));
+    if (!gval.empty()) FTRY(hipMemcpyAsync(m.val.p, gval.data(), gval.size() * 8, hipMemcpyHostToDevice, s));
+    if (!src.empty()) {
+        FTRY(m.src.ensure(src.size()));
+        FTRY(hipMemcpyAsync(m.src.p, src.data(), src.size() * 4, hipMemcpyHostToDevice, s));
+    }
+    return hipSuccess;
+}
+
+hipError_t ensure_width(FactOp* f, int W, int nsets, int order, hipStream_t s) {
+    const size_t nb = (size_t)f->Kr * W;
+    const int ng = W / 64, nx = f->Kr / kRowsWG;
+    if (W > f->W) {
+        for (auto* b : {&f->B, &f->X, &f->R, &f->Z, &f->Pd, &f->Q, &f->T, &f->U0, &f->U1, &f->Zm, &f->Pout})
+            FTRY(b->ensure(nb));
+        FTRY(f->bb.ensure(W));
+        FTRY(f->rz.ensure(W));
+        FTRY(f->alpha.ensure(W));
+        FTRY(f->beta.ensure(W));
+        FTRY(f->done.ensure(W));
+        FTRY(f->part.ensure((size_t)nx * W));
+        FTRY(f->wgpart.ensure((size_t)nx * ng));
+        FTRY(f->active.ensure(ng));
+        FTRY(f->iters.ensure(ng));
+        FTRY(f->ticket.ensure(ng));
+        FTRY(f->mx.ensure(ng));
+        FTRY(f->tot.ensure(ng));
+        FTRY(f->notconv.ensure(1));
+        FTRY(hipMemsetAsync(f->ticket.p, 0, (size_t)ng * sizeof(int), s));
+        FTRY(hipMemsetAsync(f->mx.p, 0, (size_t)ng * sizeof(int), s));
+        FTRY(hipMemsetAsync(f->tot.p, 0, (size_t)ng * sizeof(long long), s));
+        FTRY(hipMemsetAsync(f->notconv.p, 0, sizeof(int), s));
+        if (f->h_active) (void)hipHostFree(f->h_active);
+        f->h_active = nullptr;
+        FTRY(hipHostMalloc((void**)&f->h_active, (size_t)2 * ng * sizeof(int), hipHostMallocDefault));
+        f->h_cap = ng;
+        f->W = W;
+        f->nsets_cap = 0;
+        f->order_cap = 0;
+    }
+    if (nsets > f->nsets_cap) {
+        FTRY(f->P.ensure((size_t)f->Kr * f->W * nsets));
+        f->nsets_cap = nsets;
+    }
+    if (order > f->order_cap) {
+        FTRY(f->mpart.ensure((size_t)(order + 1) * (f->W / 64)));
+        f->order_cap = order;
+    }
+    return hipSuccess;
+}
+
+CgArgs cg_args(FactOp* f, int W, double tol) {
+    CgArgs a{};
+    a.W = W;
+    a.B = f->B.p;
+    a.X = f->X.p;
+    a.R = f->R.p;
+    a.Z = f->Z.p;
+    a.Pd = f->Pd.p;
+    a.Q = f->Q.p;
+    a.T = f->T.p;
+    a.bb = f->bb.p;
+    a.rz = f->rz.p;
+    a.alpha = f->alpha.p;
+    a.beta = f->beta.p;
+    a.done = f->done.p;
+    a.active = f->active.p;
+    a.iters = f->iters.p;
+    a.ticket = f->ticket.p;
+    a.part = f->part.p;
+    a.tol2 = tol * tol;
+    a.first = 0;
+    return a;
+}
+
+// X = S^-1 B on the block (width W <= f->W), B and X in the workspace.
+// *converged = 0 when some column needed more than max_iter iterations.
+hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, hipStream_t s) {
+    const int ng = W / 64;
+    max_iter = std::max(max_iter, 1);
+    const dim3 grid(f->Kr / kRowsWG, ng), blk(1024);
+    CgArgs a = cg_args(f, W, tol);
+    hipLaunchKernelGGL(cg_init_kernel, grid, blk, 0, s, a);
+    FTRY(hipGetLastError());
+    // Z = G^T (G R): preconditioned residual, rz = R . Z
+    {
+        CgArgs p = a;
+        p.first = 1;
+        hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, grid, blk, 0, s, f->G.view(), (const double*)a.R, a.T, p);
+        hipLaunchKernelGGL(rg_spmm_kernel<kRz>, grid, blk, 0, s, f->GT.view(), (const double*)a.T, a.Z, p);
+        FTRY(hipGetLastError());
+    }
+    int it = 0, chunk = 0;
+    bool conv = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    FTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    hipError_t err = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+    auto check = [&](int k) -> int {  // active columns seen after chunk k
+        int n = 0;
+        for (int y = 0; y < ng; ++y) n += f->h_active[(k & 1) * f->h_cap + y];
+        return n;
+    };
+    while (err == hipSuccess && it < max_iter) {
+        const int n_it = std::min(kChunk, max_iter - it);
+        for (int k = 0; k < n_it; ++k) {
+            hipLaunchKernelGGL(rg_spmm_kernel<kPq>, grid, blk, 0, s, f->S.view(), (const double*)a.Z, a.Q, a);
+            hipLaunchKernelGGL(cg_update_kernel, grid, blk, 0, s, a);
+            hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, grid, blk, 0, s, f->G.view(), (const double*)a.R, a.T, a);
+            hipLaunchKernelGGL(rg_spmm_kernel<kRz>, grid, blk, 0, s, f->GT.view(), (const double*)a.T, a.Z, a);
+        }
+        it += n_it;
+        if ((err = hipGetLastError()) != hipSuccess) break;
+        const int slot = chunk & 1;
+        if ((err = hipMemcpyAsync(f->h_active + slot * f->h_cap, f->active.p, (size_t)ng * sizeof(int),
+                                  hipMemcpyDeviceToHost, s)) != hipSuccess)
+            break;
+        if ((err = hipEventRecord(ev[slot], s)) != hipSuccess) break;
+        if (chunk > 0) {
+            if ((err = hipEventSynchronize(ev[slot ^ 1])) != hipSuccess) break;
+            if (check(chunk - 1) == 0) {
+                conv = true;
+                break;
+            }
+        }
+        ++chunk;
+    }
+    if (err == hipSuccess && !conv) {
+        // the last chunk decides
+        const int last = (chunk > 0 && it >= max_iter) ? chunk - 1 : chunk;
+        if ((err = hipEventSynchronize(ev[last & 1])) == hipSuccess) conv = check(last) == 0;
+    }
+    (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    FTRY(err);
+    hipLaunchKernelGGL(cg_fold_kernel, dim3(1), dim3(std::max(64, (ng + 63) / 64 * 64)), 0, s, ng, f->active.p,
+                       f->iters.p, f->tot.p, f->mx.p, f->notconv.p);
+    FTRY(hipGetLastError());
+    f->solves += 1;
+    *converged = conv ? 1 : 0;
+    return hipSuccess;
+}
+
+}  // namespace
+
+FactOp* fact_create() { return new FactOp(); }
+void fact_destroy(FactOp* f) { delete f; }
+
+hipError_t fact_setup(FactOp* f, int K, const long long* Frp, const int* Fcol, const double* Fval,
+                      const long long* Srp, const int* Scol, const double* Sval, double drop, int cap,
+                      int* bad_row, hipStream_t s) {
+    *bad_row = 0;
+    if (cap < 1 || cap > kFsaiMax || K <= 0) return hipErrorInvalidValue;
+    f->K = K;
+    f->Kr = (K + kRowsWG - 1) / kRowsWG * kRowsWG;
+    f->W = 0;
+    f->solves = 0;
+    const long long snnz = Srp[K], fnnz = Frp[K];
+    std::vector<long long> srp(Srp, Srp + K + 1), frp(Frp, Frp + K + 1);
+    std::vector<int> scol(Scol, Scol + snnz), fcol(Fcol, Fcol + fnnz);
+    // FSAI pattern: lower entries with |S_ij| >= drop sqrt(S_ii S_jj), the
+    // cap - 1 largest of them, plus the diagonal (last)
+    std::vector<double> diag(K, 0.0);
+    for (int i = 0; i < K; ++i)
+        for (long long p = srp[i]; p < srp[i + 1]; ++p)
+            if (scol[p] == i) diag[i] = Sval[p];
+    std::vector<long long> grp((size_t)K + 1, 0);
+    std::vector<int> gcol;
+    std::vector<std::pair<double, int>> cand;
+    for (int i = 0; i < K; ++i) {
+        cand.clear();
+        for (long long p = srp[i]; p < srp[i + 1]; ++p) {
+            const int j = scol[p];
+            if (j >= i) continue;
+            const double rel = std::fabs(Sval[p]) / std::sqrt(std::fabs(diag[i] * diag[j]) + 1e-300);
+            if (rel >= drop) cand.push_back({rel, j});
+        }
+        if ((int)cand.size() > cap - 1) {
+            std::stable_sort(cand.begin(), cand.end(),
+                             [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+                                 return x.first > y.first;
+                             });
+            cand.resize(cap - 1);
+        }
+        std::vector<int> J;
+        for (auto& pr : cand) J.push_back(pr.second);
+        std::sort(J.begin(), J.end());
+        J.push_back(i);
+        gcol.insert(gcol.end(), J.begin(), J.end());
+        grp[i + 1] = (long long)gcol.size();
+    }
+    f->g_nnz = (long long)gcol.size();
+    if (f->g_nnz >= 0x7fffffffLL || snnz >= 0x7fffffffLL) return hipErrorInvalidValue;
+    // plain CSR copies of S (start vectors, moment columns) and of G's pattern
+    FTRY(f->Srp.ensure(K + 1));
+    FTRY(f->Scol.ensure(std::max<long long>(snnz, 1)));
+    FTRY(f->Sval.ensure(std::max<long long>(snnz, 1)));
+    FTRY(hipMemcpyAsync(f->Srp.p, srp.data(), srp.size() * 8, hipMemcpyHostToDevice, s));
+    FTRY(hipMemcpyAsync(f->Scol.p, scol.data(), (size_t)snnz * 4, hipMemcpyHostToDevice, s));
+    FTRY(hipMemcpyAsync(f->Sval.p, Sval, (size_t)snnz * 8, hipMemcpyHostToDevice, s));
+    FTRY(f->Grp.ensure(K + 1));
+    FTRY(f->Gcol.ensure(gcol.size()));
+    FTRY(f->Gval.ensure(gcol.size()));
+    FTRY(hipMemcpyAsync(f->Grp.p, grp.data(), grp.size() * 8, hipMemcpyHostToDevice, s));
+    FTRY(hipMemcpyAsync(f->Gcol.p, gcol.data(), gcol.size() * 4, hipMemcpyHostToDevice, s));
+    Buf<int> info;
+    FTRY(info.ensure(1));
+    FTRY(hipMemsetAsync(info.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(fsai_kernel, dim3(K), dim3(256), 0, s, f->Srp.p, f->Scol.p, f->Sval.p, f->Grp.p, f->Gcol.p,
+                       f->Gval.p, info.p);
+    FTRY(hipGetLastError());
+    // row groups: S and F from the host values, G and G^T gathered on the device
+    std::vector<long long> gp;
+    std::vector<int> gc, src;
+    std::vector<double> gv;
+    row_groups(K, f->Kr, srp, scol, Sval, gp, gc, gv, src);
+    FTRY(upload_rg(f->S, gp, gc, gv, src, s));
+    row_groups(K, f->Kr, frp, fcol, Fval, gp, gc, gv, src);
+    FTRY(upload_rg(f->F, gp, gc, gv, src, s));
+    row_groups(K, f->Kr, grp, gcol, nullptr, gp, gc, gv, src);
+    FTRY(upload_rg(f->G, gp, gc, gv, src, s));
+    {
+        const long long n = (long long)src.size();
+        if (n > 0)
+            hipLaunchKernelGGL(gather_vals_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, f->G.src.p,
+                               (const double*)f->Gval.p, f->G.val.p);
+        FTRY(hipGetLastError());
+    }
+    // G^T in CSR; tpos[d] = position in G of the d-th entry of G^T
+    std::vector<long long> trp((size_t)K + 1, 0);
+    for (int cidx : gcol) trp[cidx + 1] += 1;
+    for (int i = 0; i < K; ++i) trp[i + 1] += trp[i];
+    std::vector<int> tcol(gcol.size()), tpos(gcol.size());
+    {
+        std::vector<long long> fillp(trp.begin(), trp.end() - 1);
+        for (int i = 0; i < K; ++i)
+            for (long long q = grp[i]; q < grp[i + 1]; ++q) {
+                const long long d = fillp[gcol[q]]++;
+                tcol[d] = i;
+                tpos[d] = (int)q;
+            }
+    }
+    row_groups(K, f->Kr, trp, tcol, nullptr, gp, gc, gv, src);
+    for (int& k : src) k = k >= 0 ? tpos[k] : -1;
+    FTRY(upload_rg(f->GT, gp, gc, gv, src, s));
+    {
+        const long long n = (long long)src.size();
+        if (n > 0)
+            hipLaunchKernelGGL(gather_vals_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                               f->GT.src.p, (const double*)f->Gval.p, f->GT.val.p);
+        FTRY(hipGetLastError());
+    }
+    int hinfo = 0;
+    FTRY(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    FTRY(hipStreamSynchronize(s));
+    info.release();
+    *bad_row = hinfo;
+    return hipSuccess;
+}
+
+long long fact_precond_nnz(const FactOp* f) { return f->g_nnz; }
+
+hipError_t fact_precond_copy(const FactOp* f, long long* rp, int* col, double* val, hipStream_t s) {
+    if (rp) FTRY(hipMemcpyAsync(rp, f->Grp.p, ((size_t)f->K + 1) * 8, hipMemcpyDefault, s));
+    if (col) FTRY(hipMemcpyAsync(col, f->Gcol.p, (size_t)f->g_nnz * 4, hipMemcpyDefault, s));
+    if (val) FTRY(hipMemcpyAsync(val, f->Gval.p, (size_t)f->g_nnz * 8, hipMemcpyDefault, s));
+    return hipStreamSynchronize(s);
+}
+
+
+hipError_t fact_solve(FactOp* f, int n, const double* B, long long ldb, double* X, long long ldx, double tol,
+                      int max_iter, int wmax, int* converged, hipStream_t s) {
+    *converged = 1;
+    const int K = f->K;
+    for (int off = 0; off < n; off += wmax) {
+        const int nc = std::min(wmax, n - off);
+        const int W = (nc + 63) / 64 * 64;
+        FTRY(ensure_width(f, W, 1, 1, s));
+        // stage B through device memory when it lives on the host
+        FTRY(f->Pout.ensure((size_t)f->Kr * f->W));
+        FTRY(hipMemcpy2DAsync(f->Pout.p, (size_t)K * 8, B + (size_t)off * ldb, (size_t)ldb * 8, (size_t)K * 8, nc,
+                              hipMemcpyDefault, s));
+        hipLaunchKernelGGL(to_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, nc, (const double*)f->Pout.p,
+                           (long long)K, W, f->B.p);
+        FTRY(hipGetLastError());
+        int conv = 1;
+        FTRY(cg_solve(f, W, tol, max_iter, &conv, s));
+        if (!conv) *converged = 0;
+        hipLaunchKernelGGL(from_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, nc, (const double*)f->X.p,
+                           W, f->Pout.p, (long long)K);
+        FTRY(hipGetLastError());
+        FTRY(hipMemcpy2DAsync(X + (size_t)off * ldx, (size_t)ldx * 8, f->Pout.p, (size_t)K * 8, (size_t)K * 8, nc,
+                              hipMemcpyDefault, s));
+    }
+    return hipStreamSynchronize(s);
+}
+
+hipError_t fact_apply(FactOp* f, const double* x, double* y, double tol, int max_iter, int* converged,
+                      hipStream_t s) {
+    const int K = f->K, W = 64;
+    FTRY(ensure_width(f, W, 1, 1, s));
+    hipLaunchKernelGGL(to_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, 1, x, (long long)K, W, f->U0.p);
+    CgArgs a = cg_args(f, W, tol);
+    a.active = nullptr;
+    hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, dim3(f->Kr / kRowsWG, 1), dim3(1024), 0, s, f->F.view(),
+                       (const double*)f->U0.p, f->B.p, a);
+    FTRY(hipGetLastError());
+    FTRY(cg_solve(f, W, tol, max_iter, converged, s));
+    hipLaunchKernelGGL(from_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, 1, (const double*)f->X.p, W, y,
+                       (long long)K);
+    return hipGetLastError();
+}
+
+hipError_t fact_block(FactOp* f, const FactBlockArgs& b, int* converged, hipStream_t s) {
+    *converged = 1;
+    const int K = f->K, nc = b.nc;
+    const int W = (nc + 63) / 64 * 64;
+    FTRY(ensure_width(f, W, b.nsets, b.order, s));
+    const int ng = W / 64;
+    const dim3 grid(f->Kr / kRowsWG, ng), blk(1024);
+    const size_t nb = (size_t)f->Kr * W;
+    // start block and moment columns
+    hipLaunchKernelGGL(fact_unit_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, f->Kr, W, nc, b.cols,
+                       f->B.p);
+    FTRY(fill_f64(f->Zm.p, 0.0, (long long)nb, s));
+    hipLaunchKernelGGL(fact_zm_kernel, dim3(nc), dim3(256), 0, s, W, nc, b.cols, (const long long*)f->Srp.p,
+                       (const int*)f->Scol.p, (const double*)f->Sval.p, f->Zm.p);
+    FTRY(hipGetLastError());
+    StepArgs st{};
+    st.W = W;
+    st.nsets = b.nsets;
+    st.cstride = b.cstride;
+    st.coef = b.coef;
+    st.P = f->P.p;
+    st.pstride = (long long)nb;
+    st.Zm = f->Zm.p;
+    st.wgpart = f->wgpart.p;
+    st.mpart = f->mpart.p;
+    st.ticket = f->ticket.p;
+    double* Ucur = f->U0.p;
+    double* Uoth = f->U1.p;
+    CgArgs plain = cg_args(f, W, b.tol);
+    plain.active = nullptr;
+    for (int l = 0; l <= b.order; ++l) {
+        if (l > 0) {
+            hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, grid, blk, 0, s, f->F.view(), (const double*)Ucur, f->B.p,
+                               plain);
+            FTRY(hipGetLastError());
+        }
+        int conv = 1;
+        FTRY(cg_solve(f, W, b.tol, b.max_iter, &conv, s));
+        if (!conv) {
+            *converged = 0;
+            return hipSuccess;
+        }
+        st.l = l;
+        st.X = f->X.p;
+        if (l == 0) {  // U_0 = S^-1 e_cols
+            st.sx = 1.0;
+            st.su = 0.0;
+            st.has_prev = 0;
+            st.Ucur = nullptr;
+            st.Uprev = nullptr;
+            st.Uout = Ucur;
+        } else {  // U_{l+1} = alpha (X - ebar U_l) / de - U_{l-1}
+            const double al = l == 1 ? 1.0 : 2.0;
+            st.sx = al / b.de;
+            st.su = -al * b.ebar / b.de;
+            st.has_prev = l > 1;
+            st.Ucur = Ucur;
+            st.Uprev = Uoth;
+            st.Uout = Uoth;
+        }
+        hipLaunchKernelGGL(fact_step_kernel, grid, blk, 0, s, st);
+        FTRY(hipGetLastError());
+        if (l > 0) std::swap(Ucur, Uoth);
+    }
+    FTRY(reduce_moments(b.order, ng, f->mpart.p, b.mom, b.flag, s));
+    for (int q = 0; q < b.nsets; ++q) {
+        if (!b.P_out || !b.P_out[q]) continue;
+        hipLaunchKernelGGL(from_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, nc,
+                           (const double*)(f->P.p + (size_t)q * nb), W, f->Pout.p, (long long)K);
+        FTRY(hipGetLastError());
+        FTRY(hipMemcpyAsync(b.P_out[q], f->Pout.p, (size_t)K * nc * 8, hipMemcpyDefault, s));
+    }
+    return hipSuccess;
+}
+
+hipError_t fact_stats(FactOp* f, long long* solves, long long* iters, int* max_iters, hipStream_t s) {
+    *solves = f->solves;
+    *iters = 0;
+    *max_iters = 0;
+    const int ng = f->W / 64;
+    if (ng == 0) return hipSuccess;
+    std::vector<long long> t(ng);
+    std::vector<int> m(ng);
+    FTRY(hipMemcpyAsync(t.data(), f->tot.p, (size_t)ng * 8, hipMemcpyDeviceToHost, s));
+    FTRY(hipMemcpyAsync(m.data(), f->mx.p, (size_t)ng * 4, hipMemcpyDeviceToHost, s));
+    FTRY(hipStreamSynchronize(s));
+    for (int y = 0; y < ng; ++y) {
+        *iters = std::max(*iters, t[y]);
+        *max_iters = std::max(*max_iters, m[y]);
+    }
+    return hipSuccess;
+}
+
+hipError_t fact_reset_stats(FactOp* f, hipStream_t s) {
+    f->solves = 0;
+    const int ng = f->W / 64;
+    if (ng == 0) return hipSuccess;
+    FTRY(hipMemsetAsync(f->tot.p, 0, (size_t)ng * 8, s));
+    FTRY(hipMemsetAsync(f->mx.p, 0, (size_t)ng * 4, s));
+    return hipSuccess;
+}
+
+}  // namespace dm

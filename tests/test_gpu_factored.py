@@ -1,0 +1,223 @@
+"""The factored form (H = S^-1 F applied as a sparse product with F and a
+preconditioned conjugate-gradient solve with S at every step, the paper's
+route) against the FP64 oracle.
+
+The FSAI factor is compared entry by entry with the oracle's (same pattern
+rule, same per-row definition), the solve with a direct solve, and the
+density matrix with the eigen-decomposition route.  The solve tolerance
+cg_tol bounds the residual of every solve; over N steps the recursion
+carries these errors to P at about 3-5 cg_tol (measured on the CPU with the
+oracle's own factored recursion at K = 256, N = 400 and K = 1024, N = 1000),
+so with cg_tol = 1e-11 the test bound 1e-8 on max|dP| leaves a wide margin
+and stays two orders below the 1e-6 acceptance bound of the workloads."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+from oracle import factored_oracle as FO
+import paper_2108_13478_amd as dmlib
+from synth import make_cluster, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL_P = 1e-8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    c = make_cluster(64, seed=0, geometry="cube")
+    sp = O.spectrum(c)
+    w = sp.e[-1] - sp.e[0]
+    return c, sp, (sp.e[0] - 0.01 * w, sp.e[-1] + 0.01 * w)
+
+
+def fact_ctx(c, bounds=None, **opts):
+    ctx = dmlib.Context(precision=dmlib.DM_FP64)
+    ctx.dm_set_operator_form(dmlib.DM_FORM_FACTORED)
+    if opts:
+        ctx.dm_set_factored_options(**opts)
+    ctx.set_cluster(c)
+    if bounds is not None:
+        ctx.dm_set_bounds(*bounds)
+    return ctx
+
+
+def check_rows(S, rp, col, val, rows, drop=1e-3, cap=128):
+    pats = FO.fsai_pattern(S, drop, cap, rows=rows)
+    worst = 0.0
+    for i, J in zip(rows, pats):
+        Jg = col[rp[i]:rp[i + 1]]
+        assert np.array_equal(Jg, J), f"pattern of row {i}"
+        g = FO.fsai_row(S, J)
+        worst = max(worst, np.abs(val[rp[i]:rp[i + 1]] - g).max() / np.abs(g).max())
+    return worst
+
+
+def test_preconditioner_matches_oracle(c1):
+    c, _, _ = c1
+    say(f"case: FSAI factor K={c.K}")
+    ctx = fact_ctx(c)
+    rp, col, val = ctx.dm_get_preconditioner()
+    assert rp[0] == 0 and rp[-1] == len(col) == len(val)
+    worst = check_rows(c.S_dense(), rp, col, val, range(c.K))
+    say(f"  nnz/row {len(col) / c.K:.1f}, max rel. row error {worst:.2e}")
+    assert worst < 1e-10
+
+
+def test_solve_overlap_matches_direct_solve(c1):
+    c, _, _ = c1
+    S = c.S_dense()
+    rng = np.random.default_rng(7)
+    B = rng.standard_normal((c.K, 70))
+    B[:, 65] = 0.0
+    say(f"case: solve K={c.K} nrhs=70")
+    ctx = fact_ctx(c, cg_tol=1e-12)
+    X = ctx.dm_solve_overlap(B)
+    ref = scipy.linalg.cho_solve(scipy.linalg.cho_factor(S), B)
+    res = np.linalg.norm(S @ X - B, axis=0) / np.maximum(np.linalg.norm(B, axis=0), 1e-300)
+    fwd = np.linalg.norm(X - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), 1e-300)
+    cond = np.linalg.cond(S)
+    say(f"  max rel residual {res.max():.2e}, max rel error {fwd.max():.2e} (cond {cond:.1e})")
+    assert np.all(X[:, 65] == 0.0)
+    assert res.max() < 1e-11
+    assert fwd.max() < cond * 1e-11
+    ns, it, mx = ctx.dm_cg_stats()
+    assert ns == 1 and 0 < mx <= it  # 70 columns fit one block
+
+
+def test_factored_fp64_matches_oracle(c1):
+    """All 256 columns in one block, N = 400: P, the moments and the traces."""
+    c, sp, (emin, emax) = c1
+    mu = 0.5 * (sp.e[63] + sp.e[64])
+    N, beta = 400, 100.0
+    ctx = fact_ctx(c, (emin, emax))
+    cols = np.arange(c.K, dtype=np.int64)
+    P = np.zeros((c.K, c.K))
+    ctx.dm_chebyshev_block(cols, N, mu, beta, P)
+    ref = O.density_matrix_poly(sp, cols, N, mu, beta, emin, emax)
+    err = np.abs(P.T - ref).max()
+    m, nd = ctx.dm_moments(N + 1)
+    mref = O.moments_from_eigs(sp.e, N + 1, emin, emax)
+    tr, eb = ctx.dm_trace(mu, beta)
+    tr_ref, eb_ref = O.trace_poly(sp, N, mu, beta, emin, emax)
+    ns, it, mx = ctx.dm_cg_stats()
+    say(f"case: factored FP64 K={c.K} N={N}: max|dP| = {err:.3e} (|P|max {np.abs(ref).max():.1f}), "
+        f"max|dm| = {np.abs(m - mref).max():.2e}, dTr {abs(tr - tr_ref):.2e}, dE {abs(eb - eb_ref):.2e}; "
+        f"{ns} solves, {it} iterations, at most {mx}")
+    assert err <= TOL_P and nd == c.K
+    assert np.abs(m - mref).max() < 1e-7
+    assert abs(tr - tr_ref) < 1e-7 and abs(eb - eb_ref) < 1e-6 * max(1.0, abs(eb_ref))
+    assert ns == N + 1 and mx <= 2000
+
+
+def test_factored_bounds_enclose_spectrum(c1):
+    c, sp, _ = c1
+    ctx = fact_ctx(c)
+    lo, hi = ctx.dm_get_bounds()
+    gen = dmlib.Context()
+    gen.set_cluster(c)
+    glo, ghi = gen.dm_get_bounds()
+    say(f"case: factored Lanczos K={c.K}: [{lo:.6f}, {hi:.6f}] vs dense form [{glo:.6f}, {ghi:.6f}], "
+        f"spectrum [{sp.e[0]:.6f}, {sp.e[-1]:.6f}]")
+    assert lo <= sp.e[0] and hi >= sp.e[-1]
+    w = sp.e[-1] - sp.e[0]
+    assert abs(lo - glo) < 1e-6 * w and abs(hi - ghi) < 1e-6 * w
+
+
+def test_factored_sets_bitwise_and_repeatable(c1):
+    """37 ragged columns: two coefficient sets in one pass equal the two
+    single-set passes bit for bit, and a repeated pass is bitwise identical
+    (every reduction runs in a fixed order)."""
+    c, sp, bounds = c1
+    cols = np.array([(7 * j + 3) % c.K for j in range(37)], dtype=np.int64)
+    mus = [0.5 * (sp.e[63] + sp.e[64]), sp.e[100]]
+    betas = [100.0, 40.0]
+    N = 150
+    ctx = fact_ctx(c, bounds)
+    Pm = [np.zeros((37, c.K)), np.zeros((37, c.K))]
+    ctx.dm_chebyshev_block_multi(cols, N, mus, betas, Pm)
+    for q in range(2):
+        P1 = np.zeros((37, c.K))
+        ctx.dm_chebyshev_block(cols, N, mus[q], betas[q], P1)
+        assert np.array_equal(P1, Pm[q]), f"set {q}"
+        P2 = np.zeros((37, c.K))
+        ctx.dm_chebyshev_block(cols, N, mus[q], betas[q], P2)
+        assert np.array_equal(P1, P2)
+        ref = O.density_matrix_poly(sp, cols, N, mus[q], betas[q], *bounds)
+        err = np.abs(P1.T - ref).max()
+        say(f"case: factored ragged 37 cols set {q}: max|dP| = {err:.2e}")
+        assert err <= TOL_P
+
+
+def test_factored_edge_cases(c1):
+    c, sp, bounds = c1
+    ctx = fact_ctx(c, bounds)
+    mu = 0.5 * (sp.e[63] + sp.e[64])
+    ctx.dm_chebyshev_block(np.zeros(0, dtype=np.int64), 50, mu, 100.0, None)  # empty block
+    cols = np.array([0, 255], dtype=np.int64)
+    P = np.zeros((2, c.K))
+    ctx.dm_chebyshev_block(cols, 2, mu, 100.0, P)  # shortest expansion
+    ref = O.density_matrix_poly(sp, cols, 2, mu, 100.0, *bounds)
+    assert np.abs(P.T - ref).max() <= TOL_P
+    with pytest.raises(dmlib.DMError):
+        ctx.dm_get_operator(dmlib.DM_OP_SINV)
+    with pytest.raises(dmlib.DMError):
+        ctx.dm_stoch_moments(8, np.ones((c.K, 2)))
+    with pytest.raises(dmlib.DMError):
+        ctx.dm_autotune(64, 1)
+    with pytest.raises(dmlib.DMError):
+        ctx.dm_set_factored_options(cg_tol=0.0)
+    # an iteration limit below what the solves need fails the call cleanly
+    ctx.dm_set_factored_options(cg_max_iter=1)
+    with pytest.raises(dmlib.DMError) as ei:
+        ctx.dm_chebyshev_block(cols, 10, mu, 100.0, P)
+    assert ei.value.status == dmlib.DM_E_NOCONV
+    ctx.dm_set_factored_options()
+    ctx.dm_chebyshev_block(cols, 2, mu, 100.0, P)
+    assert np.abs(P.T - ref).max() <= TOL_P
+    # FP64 only
+    ctx.dm_set_precision(dmlib.DM_FP32)
+    with pytest.raises(dmlib.DMError):
+        ctx.dm_chebyshev_block(cols, 10, mu, 100.0, P)
+    ctx.dm_set_precision(dmlib.DM_FP64)
+    ctx.dm_chebyshev_block(cols, 2, mu, 100.0, P)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    c = workload("K4096_sphere1024_fp64")
+    return c, O.spectrum(c)
+
+
+def test_factored_K4096_sampled(c2):
+    """The benchmark cluster (K = 4096, N = 1000): the FSAI factor on sampled
+    rows and 61 sampled columns of P against the oracle."""
+    c, sp = c2
+    w = sp.e[-1] - sp.e[0]
+    bounds = (sp.e[0] - 0.01 * w, sp.e[-1] + 0.01 * w)
+    say(f"case: factored K={c.K}")
+    ctx = fact_ctx(c, bounds)
+    rp, col, val = ctx.dm_get_preconditioner()
+    rows = [0, 1, 2, 3, 1000, 2047, 3000, 4093, 4094, 4095]
+    worst = check_rows(c.S_dense(), rp, col, val, rows)
+    say(f"  FSAI nnz/row {len(col) / c.K:.1f}, sampled rows max rel error {worst:.2e}")
+    assert worst < 1e-9
+    mu = 0.5 * (sp.e[2047] + sp.e[2048])
+    N, beta = 1000, 200.0
+    cols = np.array(sorted({(67 * j + 11) % c.K for j in range(61)}), dtype=np.int64)
+    P = np.zeros((len(cols), c.K))
+    ctx.dm_chebyshev_block(cols, N, mu, beta, P)
+    ref = O.density_matrix_poly(sp, cols, N, mu, beta, *bounds)
+    err = np.abs(P.T - ref).max()
+    ns, it, mx = ctx.dm_cg_stats()
+    say(f"  {len(cols)} columns N={N}: max|dP| = {err:.3e} (|P|max {np.abs(ref).max():.1f}); "
+        f"{ns} solves, {it / max(ns, 1):.1f} iterations per solve, at most {mx}")
+    assert err <= TOL_P
