@@ -18,11 +18,13 @@
 //
 // The conjugate-gradient iteration runs W independent systems in lock step,
 // each with its own step lengths.  Per-column dot products are reduced in
-// two fixed-order stages inside the producing kernel: every workgroup writes
-// its partial sums, and the last workgroup of a 64-column group to finish
-// (atomic ticket) adds them in index order and updates the column scalars.
-// Converged columns keep their solution; a 64-column group whose columns have
-// all converged skips every later kernel of the solve.
+// two fixed orders: the producing kernel writes one partial sum per
+// workgroup and column, and a small kernel with one workgroup per 64
+// columns adds them in index order and takes the scalar step (step length,
+// convergence test).  No workgroup waits for another and no fence is
+// needed inside a kernel; results are bitwise reproducible.  Converged
+// columns keep their solution; a 64-column group whose columns have all
+// converged skips every later kernel of the solve.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -46,11 +48,27 @@ struct RgView {
     const double* val;     // kRG values per listed column
 };
 
-__device__ inline void st_agent(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double ld_agent(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Workgroup -> (row block x < nx, column group y < ng).  Workgroups are
+// dealt to the 8 XCDs round robin; with xcd_split each XCD takes the column
+// groups y = xcd (mod 8) one after another, row blocks in order, so the
+// 64-column slice of the block that its row blocks gather from (K x 512
+// bytes) stays in that XCD's L2 while the group is processed.  Without the
+// split (fewer than 8 groups) the order is row blocks fastest.  Returns
+// false for the padding workgroups of the split grid.
+struct Tiles {
+    int nx, ng, xcd_split;
+};
+__device__ inline bool tile_of(const Tiles& t, int& x, int& y) {
+    const int b = blockIdx.x;
+    if (t.xcd_split) {
+        const int s = b >> 3;
+        y = (s / t.nx) * 8 + (b & 7);
+        x = s % t.nx;
+    } else {
+        y = b / t.nx;
+        x = b % t.nx;
+    }
+    return y < t.ng;
 }
 
 // Sums v over the 16 waves of the workgroup for each lane (column); the
@@ -65,41 +83,16 @@ __device__ inline double wg_column_sum(double v, double (*red)[64]) {
     return s;
 }
 
-// Wave 0 has written this workgroup's partials; returns true in the last
-// workgroup of the column group to arrive (uniform over the workgroup).
-__device__ inline bool arrive_last(int* ticket) {
-    __shared__ int last;
-    if (threadIdx.x < 64) __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
-    __syncthreads();
-    const bool is_last = last != 0;
-    if (is_last) __threadfence();
-    return is_last;
-}
-
-// In the last workgroup: column sums of part[x * W + y * 64 + lane] over x <
-// gridDim.x, in fixed order (16 strided slices, then the slices in order).
-// Valid in wave 0.
-__device__ inline double last_column_sum(const double* part, int W, double (*red)[64]) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = blockIdx.y * 64 + lane;
-    double s = 0.0;
-    for (int x = w; x < (int)gridDim.x; x += kWv) s += ld_agent(part + (size_t)x * W + col);
-    __syncthreads();
-    return wg_column_sum(s, red);
-}
-
 struct CgArgs {
     int W;
+    Tiles t;
     const double* B;
     double *X, *R, *Z, *Pd, *Q, *T;
     double *bb, *rz, *alpha, *beta;
     int* done;
     int* active;  // per 64-column group: columns not yet converged
     int* iters;   // per 64-column group: iterations of the current solve
-    int* ticket;  // per 64-column group
-    double* part; // gridDim.x x W
+    double* part; // nx x W: per-workgroup column sums of the last producer
     double tol2;
     int first;
 };
@@ -107,21 +100,20 @@ struct CgArgs {
 enum { kPlain = 0, kPq = 1, kRz = 2 };
 
 // Y = A X over the block (kPlain); the conjugate-gradient products fuse their
-// vector updates and dot products:
-//   kPq: Pd = Z + beta Pd, Q = A Z + beta Q (= A Pd), pq = Pd . Q,
-//        last workgroup: alpha = rz / pq;
-//   kRz: Z = A T (the preconditioner's second factor), rz_new = R . Z,
-//        last workgroup: beta = rz_new / rz (0 on the first iteration).
+// vector updates and the per-workgroup parts of their dot products:
+//   kPq: Pd = Z + beta Pd, Q = A Z + beta Q (= A Pd), part = Pd . Q;
+//   kRz: Z = A T (the preconditioner's second factor), part = R . Z.
 template <int MODE>
 __global__ void __launch_bounds__(1024) rg_spmm_kernel(RgView A, const double* __restrict__ Xin,
                                                        double* __restrict__ Yout, CgArgs a) {
     __shared__ double red[kWv][64];
-    const int y = blockIdx.y;
+    int bx, y;
+    if (!tile_of(a.t, bx, y)) return;
     if (a.active && a.active[y] == 0) return;
     const int W = a.W;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int g = blockIdx.x * kWv + wv;
+    const int g = bx * kWv + wv;
     const int c = y * 64 + lane;
     const long long p0 = A.ptr[g], p1 = A.ptr[g + 1];
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
@@ -181,34 +173,16 @@ __global__ void __launch_bounds__(1024) rg_spmm_kernel(RgView A, const double* _
         }
     }
     const double s = wg_column_sum(d, red);
-    if (threadIdx.x < 64) st_agent(a.part + (size_t)blockIdx.x * W + c, s);
-    if (!arrive_last(a.ticket + y)) return;
-    const double tot = last_column_sum(a.part, W, red);
-    if (threadIdx.x < 64) {
-        const bool dn = a.done[c] != 0;
-        if (MODE == kPq) {
-            double al = 0.0;
-            if (!dn) {
-                if (tot > 0.0)
-                    al = a.rz[c] / tot;
-                else
-                    a.done[c] = 1;  // zero search direction: the residual is already zero
-            }
-            a.alpha[c] = al;
-        } else {
-            a.beta[c] = (a.first || dn || !(a.rz[c] > 0.0)) ? 0.0 : tot / a.rz[c];
-            a.rz[c] = tot;
-        }
-        if (threadIdx.x == 0) __hip_atomic_store(a.ticket + y, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x < 64) a.part[(size_t)bx * W + c] = s;
 }
 
-// X = 0, R = B, bb = B . B per column; last workgroup: done = (bb == 0),
-// active count, beta = 0.
+// X = 0, R = B, part = B . B.
 __global__ void __launch_bounds__(1024) cg_init_kernel(CgArgs a) {
     __shared__ double red[kWv][64];
-    const int W = a.W, y = blockIdx.y;
-    const int g = blockIdx.x * kWv + (threadIdx.x >> 6);
+    int bx, y;
+    if (!tile_of(a.t, bx, y)) return;
+    const int W = a.W;
+    const int g = bx * kWv + (threadIdx.x >> 6);
     const int c = y * 64 + (threadIdx.x & 63);
     double d = 0.0;
 #pragma unroll
@@ -220,31 +194,17 @@ __global__ void __launch_bounds__(1024) cg_init_kernel(CgArgs a) {
         d += b * b;
     }
     const double s = wg_column_sum(d, red);
-    if (threadIdx.x < 64) st_agent(a.part + (size_t)blockIdx.x * W + c, s);
-    if (!arrive_last(a.ticket + y)) return;
-    const double tot = last_column_sum(a.part, W, red);
-    if (threadIdx.x < 64) {
-        const bool dn = !(tot > 0.0);
-        a.bb[c] = tot;
-        a.done[c] = dn ? 1 : 0;
-        a.beta[c] = 0.0;
-        a.alpha[c] = 0.0;
-        const unsigned long long live = __ballot(!dn);
-        if (threadIdx.x == 0) {
-            a.active[y] = __popcll(live);
-            a.iters[y] = 0;
-            __hip_atomic_store(a.ticket + y, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    if (threadIdx.x < 64) a.part[(size_t)bx * W + c] = s;
 }
 
-// X += alpha Pd, R -= alpha Q, rr = R . R; last workgroup: columns with
-// rr <= tol^2 bb are done, new active count.
+// X += alpha Pd, R -= alpha Q, part = R . R.
 __global__ void __launch_bounds__(1024) cg_update_kernel(CgArgs a) {
     __shared__ double red[kWv][64];
-    const int W = a.W, y = blockIdx.y;
+    int bx, y;
+    if (!tile_of(a.t, bx, y)) return;
+    const int W = a.W;
     if (a.active[y] == 0) return;
-    const int g = blockIdx.x * kWv + (threadIdx.x >> 6);
+    const int g = bx * kWv + (threadIdx.x >> 6);
     const int c = y * 64 + (threadIdx.x & 63);
     const double al = a.alpha[c];
     double d = 0.0;
@@ -257,21 +217,64 @@ __global__ void __launch_bounds__(1024) cg_update_kernel(CgArgs a) {
         d += rv * rv;
     }
     const double s = wg_column_sum(d, red);
-    if (threadIdx.x < 64) st_agent(a.part + (size_t)blockIdx.x * W + c, s);
-    if (!arrive_last(a.ticket + y)) return;
-    const double tot = last_column_sum(a.part, W, red);
-    if (threadIdx.x < 64) {
+    if (threadIdx.x < 64) a.part[(size_t)bx * W + c] = s;
+}
+
+enum { kSumBB = 0, kSumPQ = 1, kSumRR = 2, kSumRZ = 3 };
+
+// Column totals of the producer's parts (x < nx, fixed order: 16 strided
+// slices, then the slices in order) and the scalar step of the iteration,
+// one workgroup per 64-column group:
+//   kSumBB: bb = B . B, done = (bb == 0), beta = alpha = 0, active count;
+//   kSumPQ: alpha = rz / (Pd . Q) (0 for converged columns);
+//   kSumRR: done once R . R <= tol^2 bb, active count, iteration count;
+//   kSumRZ: beta = rz_new / rz (0 on the first iteration), rz = rz_new.
+template <int MODE>
+__global__ void __launch_bounds__(1024) cg_colsum_kernel(CgArgs a) {
+    __shared__ double red[kWv][64];
+    const int y = blockIdx.x;
+    if (MODE != kSumBB && a.active[y] == 0) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = y * 64 + lane;
+    double s = 0.0;
+    for (int x = w; x < a.t.nx; x += kWv) s += a.part[(size_t)x * a.W + c];
+    const double tot = wg_column_sum(s, red);
+    if (w != 0) return;
+    if (MODE == kSumBB) {
+        const bool dn = !(tot > 0.0);
+        a.bb[c] = tot;
+        a.done[c] = dn ? 1 : 0;
+        a.beta[c] = 0.0;
+        a.alpha[c] = 0.0;
+        const unsigned long long live = __ballot(!dn);
+        if (lane == 0) {
+            a.active[y] = __popcll(live);
+            a.iters[y] = 0;
+        }
+    } else if (MODE == kSumPQ) {
+        double al = 0.0;
+        if (a.done[c] == 0) {
+            if (tot > 0.0)
+                al = a.rz[c] / tot;
+            else
+                a.done[c] = 1;  // zero search direction: the residual is already zero
+        }
+        a.alpha[c] = al;
+    } else if (MODE == kSumRR) {
         bool dn = a.done[c] != 0;
         if (!dn && tot <= a.tol2 * a.bb[c]) {
             dn = true;
             a.done[c] = 1;
         }
         const unsigned long long live = __ballot(!dn);
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             a.active[y] = __popcll(live);
             a.iters[y] += 1;
-            __hip_atomic_store(a.ticket + y, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+    } else {
+        const bool dn = a.done[c] != 0;
+        a.beta[c] = (a.first || dn || !(a.rz[c] > 0.0)) ? 0.0 : tot / a.rz[c];
+        a.rz[c] = tot;
     }
 }
 
@@ -289,9 +292,10 @@ __global__ void cg_fold_kernel(int ngroups, const int* active, const int* iters,
 // One step of the recursion on the block (eq. ChebychevExpansion):
 //   Unew = sx X + su Ucur - (has_prev ? Uprev : 0)   -> Uout (may alias Uprev)
 //   P_q (+)= coef[q cstride + l] Unew for q < nsets   (assigned when l == 0)
-//   mpart[l * ngroups + y] = sum over the group's columns of Zm . Unew
+//   mpart[l * ng * nx + y * nx + x] = this workgroup's sum of Zm . Unew
 struct StepArgs {
     int W, l, nsets, cstride, has_prev;
+    Tiles t;
     const double* X;
     const double* Ucur;
     const double* Uprev;
@@ -301,15 +305,15 @@ struct StepArgs {
     double* P;
     long long pstride;
     const double* Zm;
-    double* wgpart;  // gridDim.y x gridDim.x
     double* mpart;
-    int* ticket;
 };
 
 __global__ void __launch_bounds__(1024) fact_step_kernel(StepArgs a) {
     __shared__ double red[kWv][64];
-    const int W = a.W, y = blockIdx.y;
-    const int g = blockIdx.x * kWv + (threadIdx.x >> 6);
+    int bx, y;
+    if (!tile_of(a.t, bx, y)) return;
+    const int W = a.W, nx = a.t.nx;
+    const int g = bx * kWv + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int c = y * 64 + lane;
     double d = 0.0;
@@ -330,17 +334,7 @@ __global__ void __launch_bounds__(1024) fact_step_kernel(StepArgs a) {
     double s = wg_column_sum(d, red);
     if (threadIdx.x < 64) {
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (threadIdx.x == 0) st_agent(a.wgpart + (size_t)y * gridDim.x + blockIdx.x, s);
-    }
-    if (!arrive_last(a.ticket + y)) return;
-    if (threadIdx.x < 64) {
-        double t = 0.0;
-        for (int x = lane; x < (int)gridDim.x; x += 64) t += ld_agent(a.wgpart + (size_t)y * gridDim.x + x);
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        if (threadIdx.x == 0) {
-            a.mpart[(size_t)a.l * gridDim.y + y] = t;
-            __hip_atomic_store(a.ticket + y, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (threadIdx.x == 0) a.mpart[((size_t)a.l * a.t.ng + y) * nx + bx] = s;
     }
 }
 
@@ -555,8 +549,8 @@ struct FactOp {
     // workspace of width W
     int W = 0;
     Buf<double> B, X, R, Z, Pd, Q, T, U0, U1, Zm, P, Pout;
-    Buf<double> bb, rz, alpha, beta, part, wgpart, mpart;
-    Buf<int> done, active, iters, ticket, mx, notconv;
+    Buf<double> bb, rz, alpha, beta, part, mpart;
+    Buf<int> done, active, iters, mx, notconv;
     Buf<long long> tot;
     int* h_active = nullptr;  // pinned, 2 x ngroups
     int h_cap = 0;
@@ -566,9 +560,9 @@ struct FactOp {
         for (RgMat* m : {&S, &F, &G, &GT}) m->release();
         Srp.release(); Grp.release(); Scol.release(); Gcol.release(); Sval.release(); Gval.release();
         for (auto* b : {&B, &X, &R, &Z, &Pd, &Q, &T, &U0, &U1, &Zm, &P, &Pout, &bb, &rz, &alpha, &beta, &part,
-                        &wgpart, &mpart})
+                        &mpart})
             b->release();
-        for (auto* b : {&done, &active, &iters, &ticket, &mx, &notconv}) b->release();
+        for (auto* b : {&done, &active, &iters, &mx, &notconv}) b->release();
         tot.release();
         if (h_active) (void)hipHostFree(h_active);
     }
@@ -610,14 +604,11 @@ hipError_t ensure_width(FactOp* f, int W, int nsets, int order, hipStream_t s) {
         FTRY(f->beta.ensure(W));
         FTRY(f->done.ensure(W));
         FTRY(f->part.ensure((size_t)nx * W));
-        FTRY(f->wgpart.ensure((size_t)nx * ng));
         FTRY(f->active.ensure(ng));
         FTRY(f->iters.ensure(ng));
-        FTRY(f->ticket.ensure(ng));
         FTRY(f->mx.ensure(ng));
         FTRY(f->tot.ensure(ng));
         FTRY(f->notconv.ensure(1));
-        FTRY(hipMemsetAsync(f->ticket.p, 0, (size_t)ng * sizeof(int), s));
         FTRY(hipMemsetAsync(f->mx.p, 0, (size_t)ng * sizeof(int), s));
         FTRY(hipMemsetAsync(f->tot.p, 0, (size_t)ng * sizeof(long long), s));
         FTRY(hipMemsetAsync(f->notconv.p, 0, sizeof(int), s));
@@ -634,15 +625,30 @@ hipError_t ensure_width(FactOp* f, int W, int nsets, int order, hipStream_t s) {
         f->nsets_cap = nsets;
     }
     if (order > f->order_cap) {
-        FTRY(f->mpart.ensure((size_t)(order + 1) * (f->W / 64)));
+        FTRY(f->mpart.ensure((size_t)(order + 1) * (f->W / 64) * (f->Kr / kRowsWG)));
         f->order_cap = order;
     }
     return hipSuccess;
 }
 
+Tiles tiles_for(const FactOp* f, int W) {
+    Tiles t;
+    t.nx = f->Kr / kRowsWG;
+    t.ng = W / 64;
+    t.xcd_split = t.ng >= 8 ? 1 : 0;
+    return t;
+}
+
+// 1-D grid of the row kernels for these tiles
+dim3 tile_grid(const Tiles& t) {
+    if (t.xcd_split) return dim3((unsigned)(t.nx * 8 * ((t.ng + 7) / 8)));
+    return dim3((unsigned)(t.nx * t.ng));
+}
+
 CgArgs cg_args(FactOp* f, int W, double tol) {
     CgArgs a{};
     a.W = W;
+    a.t = tiles_for(f, W);
     a.B = f->B.p;
     a.X = f->X.p;
     a.R = f->R.p;
@@ -657,7 +663,6 @@ CgArgs cg_args(FactOp* f, int W, double tol) {
     a.done = f->done.p;
     a.active = f->active.p;
     a.iters = f->iters.p;
-    a.ticket = f->ticket.p;
     a.part = f->part.p;
     a.tol2 = tol * tol;
     a.first = 0;
@@ -669,9 +674,11 @@ CgArgs cg_args(FactOp* f, int W, double tol) {
 hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, hipStream_t s) {
     const int ng = W / 64;
     max_iter = std::max(max_iter, 1);
-    const dim3 grid(f->Kr / kRowsWG, ng), blk(1024);
     CgArgs a = cg_args(f, W, tol);
+    const dim3 grid = tile_grid(a.t), blk(1024);
+    const dim3 gsum(ng);
     hipLaunchKernelGGL(cg_init_kernel, grid, blk, 0, s, a);
+    hipLaunchKernelGGL(cg_colsum_kernel<kSumBB>, gsum, blk, 0, s, a);
     FTRY(hipGetLastError());
     // Z = G^T (G R): preconditioned residual, rz = R . Z
     {
@@ -679,6 +686,7 @@ hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, 
         p.first = 1;
         hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, grid, blk, 0, s, f->G.view(), (const double*)a.R, a.T, p);
         hipLaunchKernelGGL(rg_spmm_kernel<kRz>, grid, blk, 0, s, f->GT.view(), (const double*)a.T, a.Z, p);
+        hipLaunchKernelGGL(cg_colsum_kernel<kSumRZ>, gsum, blk, 0, s, p);
         FTRY(hipGetLastError());
     }
     int it = 0, chunk = 0;
@@ -695,9 +703,12 @@ hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, 
         const int n_it = std::min(kChunk, max_iter - it);
         for (int k = 0; k < n_it; ++k) {
             hipLaunchKernelGGL(rg_spmm_kernel<kPq>, grid, blk, 0, s, f->S.view(), (const double*)a.Z, a.Q, a);
+            hipLaunchKernelGGL(cg_colsum_kernel<kSumPQ>, gsum, blk, 0, s, a);
             hipLaunchKernelGGL(cg_update_kernel, grid, blk, 0, s, a);
+            hipLaunchKernelGGL(cg_colsum_kernel<kSumRR>, gsum, blk, 0, s, a);
             hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, grid, blk, 0, s, f->G.view(), (const double*)a.R, a.T, a);
             hipLaunchKernelGGL(rg_spmm_kernel<kRz>, grid, blk, 0, s, f->GT.view(), (const double*)a.T, a.Z, a);
+            hipLaunchKernelGGL(cg_colsum_kernel<kSumRZ>, gsum, blk, 0, s, a);
         }
         it += n_it;
         if ((err = hipGetLastError()) != hipSuccess) break;
@@ -892,7 +903,7 @@ hipError_t fact_apply(FactOp* f, const double* x, double* y, double tol, int max
     hipLaunchKernelGGL(to_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, 1, x, (long long)K, W, f->U0.p);
     CgArgs a = cg_args(f, W, tol);
     a.active = nullptr;
-    hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, dim3(f->Kr / kRowsWG, 1), dim3(1024), 0, s, f->F.view(),
+    hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, tile_grid(a.t), dim3(1024), 0, s, f->F.view(),
                        (const double*)f->U0.p, f->B.p, a);
     FTRY(hipGetLastError());
     FTRY(cg_solve(f, W, tol, max_iter, converged, s));
@@ -907,7 +918,8 @@ hipError_t fact_block(FactOp* f, const FactBlockArgs& b, int* converged, hipStre
     const int W = (nc + 63) / 64 * 64;
     FTRY(ensure_width(f, W, b.nsets, b.order, s));
     const int ng = W / 64;
-    const dim3 grid(f->Kr / kRowsWG, ng), blk(1024);
+    const Tiles tl = tiles_for(f, W);
+    const dim3 grid = tile_grid(tl), blk(1024);
     const size_t nb = (size_t)f->Kr * W;
     // start block and moment columns
     hipLaunchKernelGGL(fact_unit_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, f->Kr, W, nc, b.cols,
@@ -918,15 +930,14 @@ hipError_t fact_block(FactOp* f, const FactBlockArgs& b, int* converged, hipStre
     FTRY(hipGetLastError());
     StepArgs st{};
     st.W = W;
+    st.t = tl;
     st.nsets = b.nsets;
     st.cstride = b.cstride;
     st.coef = b.coef;
     st.P = f->P.p;
     st.pstride = (long long)nb;
     st.Zm = f->Zm.p;
-    st.wgpart = f->wgpart.p;
     st.mpart = f->mpart.p;
-    st.ticket = f->ticket.p;
     double* Ucur = f->U0.p;
     double* Uoth = f->U1.p;
     CgArgs plain = cg_args(f, W, b.tol);
@@ -965,7 +976,7 @@ hipError_t fact_block(FactOp* f, const FactBlockArgs& b, int* converged, hipStre
         FTRY(hipGetLastError());
         if (l > 0) std::swap(Ucur, Uoth);
     }
-    FTRY(reduce_moments(b.order, ng, f->mpart.p, b.mom, b.flag, s));
+    FTRY(reduce_moments(b.order, ng * tl.nx, f->mpart.p, b.mom, b.flag, s));
     for (int q = 0; q < b.nsets; ++q) {
         if (!b.P_out || !b.P_out[q]) continue;
         hipLaunchKernelGGL(from_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, nc,
