@@ -14,6 +14,13 @@ mu solved by the previous step (steady state of a self-consistent loop; the
 first warm-up step solves it from a pass at mu = 0) and checks the electron
 count of its own moments.
 
+Besides the headline line's own roofline (the FP64 recursion kernel), the
+JSON carries two more measured points: hbm_point (the FP32 recursion of the
+K = 32768 cluster against a 32-column block, HBM-bound) and factored_point
+(the paper's factored application of S^-1 F on the benchmark cluster: a
+sparse product with F and a preconditioned CG solve with S per step, with
+the roofline of its S products).
+
 Prints one JSON line.  --gpus N with N > 1 is not supported (one GPU).
 """
 from __future__ import annotations
@@ -47,10 +54,17 @@ COUNTERS_HBM = {"kernel_source_sha256_16": "b20b5ef62b97a939", "fetch_kib": 2124
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
-def kernel_source_hash():
+# the factored form (S^-1 F applied by a product with F and a CG solve with S
+# per step): all K columns of the benchmark cluster in one block, a bounded
+# number of recursion steps (each one solve); the rate scales to order N
+FACT_ORDER = 8
+COUNTERS_FACT = None  # rocprofv3 FETCH_SIZE / WRITE_SIZE of rg_spmm_kernel<1>, when taken
+
+
+def kernel_source_hash(name="gemm.hip"):
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2108_13478_amd", "csrc", "gemm.hip")
+    path = os.path.join(ROOT, "paper_2108_13478_amd", "csrc", name)
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
@@ -125,12 +139,91 @@ def hbm_point(stream):
             "tflops": flops / (launch_ms * 1e-3) / 1e12}
 
 
+def factored_point(stream, mu):
+    """The factored form on the benchmark cluster: every application of
+    H = S^-1 F is a sparse product with F and an FSAI-preconditioned CG solve
+    with S (the paper's route).  Times a pass over all K columns with
+    FACT_ORDER recursion steps (FACT_ORDER + 1 solves) with HIP events on the
+    library's stream, and the S products inside the CG iterations (the
+    dominant kernel) with the library's own per-launch HIP events.  P of the
+    pass is compared with the explicit-operator path at the same order."""
+    import numpy as np
+    import torch
+
+    import paper_2108_13478_amd as dmlib
+    from synth import WORKLOADS, workload
+
+    w = WORKLOADS[WORKLOAD]
+    beta, order = w["beta"], w["order"]
+    print("[bench] factored form", file=sys.stderr, flush=True)
+    c = workload(WORKLOAD)
+    K = c.K
+    dev = torch.device("cuda:0")
+    ctx = dmlib.Context(device=0, stream=stream.cuda_stream, precision=dmlib.DM_FP64)
+    ctx.dm_set_operator_form(dmlib.DM_FORM_FACTORED)
+    t0 = time.perf_counter()
+    ctx.set_cluster(c)
+    setup_s = time.perf_counter() - t0
+    lo, hi = ctx.dm_get_bounds()
+    cols = torch.arange(K, dtype=torch.int64, device=dev)
+    Pf = torch.empty((K, K), dtype=torch.float64, device=dev)
+    ctx.dm_chebyshev_block(cols, 2, mu, beta, None)  # warm-up pass
+    ctx.dm_cg_stats()
+    ctx.dm_cg_timing(1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.dm_chebyshev_block(cols, FACT_ORDER, mu, beta, Pf)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pass_ms = e0.elapsed_time(e1)
+    n_launch, spmm_ms = ctx.dm_cg_timing(0)
+    solves, iters, max_iters = ctx.dm_cg_stats()
+    ctx.close()
+    # the explicit-operator path on the same interval, order and columns
+    ctxd = dmlib.Context(device=0, stream=stream.cuda_stream, precision=dmlib.DM_FP64)
+    ctxd.set_cluster(c)
+    ctxd.dm_set_bounds(lo, hi)
+    Pd = torch.empty((K, K), dtype=torch.float64, device=dev)
+    ctxd.dm_chebyshev_block(cols, FACT_ORDER, mu, beta, Pd)
+    torch.cuda.synchronize()
+    ctxd.close()
+    diff = float((Pf - Pd).abs().max())
+    del Pf, Pd
+    col_steps = K * (FACT_ORDER + 1) / (pass_ms * 1e-3)
+    nnz_S = len(c.S_val)
+    launch_ms = spmm_ms / max(n_launch, 1)
+    # useful flops of one S product over the block (2 per stored entry and
+    # column), and its algorithmic bytes: S in CSR once, the block Z read
+    # once, the fused direction update (Pd, Q read and written)
+    flops = 2.0 * nnz_S * K
+    alg_bytes = 12.0 * nnz_S + 8.0 * (K + 1) + 5.0 * 8.0 * K * K
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+    gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
+    traffic = None
+    if COUNTERS_FACT and kernel_source_hash("factored.hip") == COUNTERS_FACT["kernel_source_sha256_16"]:
+        traffic = 1024.0 * (COUNTERS_FACT["fetch_kib"] * COUNTERS_FACT["fetch_scale"]
+                            + COUNTERS_FACT["write_kib"] * COUNTERS_FACT["write_scale"])
+    return {"workload": WORKLOAD, "K": K, "columns": K, "steps_timed": FACT_ORDER, "solves_timed": solves,
+            "precision": "fp64", "setup_s": setup_s, "pass_ms": pass_ms,
+            "column_steps_per_s": col_steps, "columns_per_s_at_order": col_steps / (order + 1),
+            "order": order, "cg_iterations_per_solve": iters / max(solves, 1),
+            "cg_max_iterations": max_iters, "cg_tol": 1e-11, "max_abs_dP_vs_explicit_operator": diff,
+            "roofline": {"bound": "alu", "kernel": "rg_spmm_kernel<1> (S product of the CG iteration)",
+                         "launches_timed": n_launch, "launch_ms": launch_ms, "achieved": achieved,
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                         "algorithmic_bytes": alg_bytes, "spmm_GBps": gbs, "spmm_hbm_frac": gbs / PEAK_HBM_GBS,
+                         "traffic": traffic}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-factored-point", action="store_true",
+                    help="skip the factored-form (sparse F, CG solve with S) measurement")
     ap.add_argument("--no-hbm-point", action="store_true",
                     help="skip the memory-bound FP32 K=32768 / 32-column measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -243,6 +336,8 @@ def main():
     ctx.close()
     if not args.no_hbm_point:
         out["hbm_point"] = hbm_point(stream)
+    if not args.no_factored_point:
+        out["factored_point"] = factored_point(stream, state["mu"])
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(c, order, beta, n_e)

@@ -192,6 +192,15 @@ dm_status dm_get_preconditioner(dm_ctx* ctx, long long* nnz, long long* rowptr, 
  * Errors: DM_E_STATE (no factored operator loaded). */
 dm_status dm_cg_stats(dm_ctx* ctx, long long* solves, long long* iterations, int* max_iterations);
 
+/* Timing of the factored form's dominant kernel, the product with S inside
+ * every conjugate-gradient iteration: with enable = 1 each such launch is
+ * bracketed by HIP events on the context's stream (a small cost per launch).
+ * Each call returns, and clears, the number of timed launches and their
+ * summed duration in ms (host pointers, may be NULL) of the iterations that
+ * ran since the previous call, then sets the switch to `enable`.
+ * Errors: DM_E_STATE (no factored operator loaded). */
+dm_status dm_cg_timing(dm_ctx* ctx, int enable, long long* launches, double* ms);
+
 /* Switch the recursion precision (DM_FP64 / DM_FP32) of a loaded operator;
  * resets the accumulated moments and forgets a tuned or pinned pass shape.
  * A loaded batch keeps only its H_N and so the precision it was loaded in:

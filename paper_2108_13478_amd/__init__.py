@@ -36,7 +36,8 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_mlp_gradients", "dm_mlp_train_step", "dm_mlp_features", "dm_mlp_predict",
             "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
             "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal", "dm_density_on_grid",
-            "dm_set_factored_options", "dm_solve_overlap", "dm_get_preconditioner", "dm_cg_stats"]
+            "dm_set_factored_options", "dm_solve_overlap", "dm_get_preconditioner", "dm_cg_stats",
+            "dm_cg_timing"]
 
 
 class DMError(RuntimeError):
@@ -114,6 +115,7 @@ def load(path: str = LIB_PATH):
         "dm_solve_overlap": (_I, [_P, _P, _LL, _P]),
         "dm_get_preconditioner": (_I, [_P, _P, _P, _P, _P]),
         "dm_cg_stats": (_I, [_P, _P, _P, _P]),
+        "dm_cg_timing": (_I, [_P, _I, _P, _P]),
         "dm_set_fock_orthonormal": (_I, [_P, _LL, _P, _P, _P]),
         "dm_density_on_grid": (_I, [_P, _LL, _P, _P, _P, _D, _P, _D, _P, _LL, _P, _P]),
         "dm_trace": (_I, [_P, _D, _D, _P, _P]),
@@ -318,6 +320,13 @@ class Context:
         ns, it, mx = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
         self._check(self._lib.dm_cg_stats(self.h, ctypes.byref(ns), ctypes.byref(it), ctypes.byref(mx)))
         return ns.value, it.value, mx.value
+
+    def dm_cg_timing(self, enable):
+        """(launches, ms) of the timed S products since the last call; then
+        switches the timing on or off."""
+        n, ms = ctypes.c_longlong(), ctypes.c_double()
+        self._check(self._lib.dm_cg_timing(self.h, int(enable), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def dm_dos(self, kind, energies, sigma=0.0):
         """Density of states at `energies` from the accumulated moments

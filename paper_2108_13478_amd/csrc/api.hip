@@ -951,6 +951,20 @@ dm_status dm_cg_stats(dm_ctx* c, long long* solves, long long* iterations, int* 
     return DM_OK;
 }
 
+dm_status dm_cg_timing(dm_ctx* c, int enable, long long* launches, double* ms) {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock || !c->op.fact) return set_err(c, DM_E_STATE, "no factored operator loaded");
+    long long n = 0;
+    double t = 0.0;
+    fact_take_timing(c->op.fact, &n, &t);
+    fact_set_timing(c->op.fact, enable != 0);
+    if (launches) *launches = n;
+    if (ms) *ms = t;
+    return DM_OK;
+}
+
 dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);

@@ -287,5 +287,10 @@ hipError_t fact_block(FactOp* f, const FactBlockArgs& a, int* converged, hipStre
 // the largest iteration count of one solve.
 hipError_t fact_stats(FactOp* f, long long* solves, long long* iters, int* max_iters, hipStream_t s);
 hipError_t fact_reset_stats(FactOp* f, hipStream_t s);
+// With timing on, each S product of the iterations is bracketed by HIP
+// events on the solve's stream; fact_take_timing returns and clears the
+// number of timed launches and their summed duration.
+void fact_set_timing(FactOp* f, bool on);
+void fact_take_timing(FactOp* f, long long* launches, double* ms);
 
 }  // namespace dm

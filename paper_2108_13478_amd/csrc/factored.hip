@@ -31,6 +31,8 @@
 #include <numeric>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "dm_common.hpp"
 
 namespace dm {
@@ -103,77 +105,117 @@ enum { kPlain = 0, kPq = 1, kRz = 2 };
 // vector updates and the per-workgroup parts of their dot products:
 //   kPq: Pd = Z + beta Pd, Q = A Z + beta Q (= A Pd), part = Pd . Q;
 //   kRz: Z = A T (the preconditioner's second factor), part = R . Z.
-template <int MODE>
+// Each lane takes CPL adjacent columns (CPL = 2: one 16-byte load per
+// gathered row and lane, half the matrix reads per multiply-add); a
+// workgroup covers 64 CPL columns, tiles.ng counts such column groups.
+template <int CPL>
+__device__ inline void load_cols(const double* p, double (&x)[CPL]) {
+    static_assert(CPL == 1 || CPL == 2, "one or two columns per lane");
+    if constexpr (CPL == 1) {
+        x[0] = *p;
+    } else {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        x[0] = v.x;
+        x[1] = v.y;
+    }
+}
+
+template <int MODE, int CPL>
 __global__ void __launch_bounds__(1024) rg_spmm_kernel(RgView A, const double* __restrict__ Xin,
-                                                       double* __restrict__ Yout, CgArgs a) {
-    __shared__ double red[kWv][64];
+                                                       double* __restrict__ Yout, CgArgs a, Tiles t) {
+    __shared__ double red[kWv][64 * CPL];
     int bx, y;
-    if (!tile_of(a.t, bx, y)) return;
-    if (a.active && a.active[y] == 0) return;
+    if (!tile_of(t, bx, y)) return;
+    if (a.active) {
+        bool live = false;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) live = live || a.active[y * CPL + q] != 0;
+        if (!live) return;
+    }
     const int W = a.W;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int g = bx * kWv + wv;
-    const int c = y * 64 + lane;
+    const int c = y * 64 * CPL + lane * CPL;  // first of this lane's columns
     const long long p0 = A.ptr[g], p1 = A.ptr[g + 1];
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    double acc[kRG][CPL];
+#pragma unroll
+    for (int r = 0; r < kRG; ++r)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) acc[r][q] = 0.0;
     const double* xc = Xin + c;
     long long p = p0;
     for (; p + 8 <= p1; p += 8) {
         int j[8];
-        double x[8];
+        double x[8][CPL];
 #pragma unroll
         for (int u = 0; u < 8; ++u) j[u] = A.col[p + u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = xc[(size_t)j[u] * W];
+        for (int u = 0; u < 8; ++u) load_cols<CPL>(xc + (size_t)j[u] * W, x[u]);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const double* v = A.val + (p + u) * kRG;
-            acc0 += v[0] * x[u];
-            acc1 += v[1] * x[u];
-            acc2 += v[2] * x[u];
-            acc3 += v[3] * x[u];
+#pragma unroll
+            for (int r = 0; r < kRG; ++r)
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) acc[r][q] += v[r] * x[u][q];
         }
     }
     for (; p < p1; ++p) {
-        const double x = xc[(size_t)A.col[p] * W];
+        double x[CPL];
+        load_cols<CPL>(xc + (size_t)A.col[p] * W, x);
         const double* v = A.val + p * kRG;
-        acc0 += v[0] * x;
-        acc1 += v[1] * x;
-        acc2 += v[2] * x;
-        acc3 += v[3] * x;
+#pragma unroll
+        for (int r = 0; r < kRG; ++r)
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) acc[r][q] += v[r] * x[q];
     }
-    const double acc[4] = {acc0, acc1, acc2, acc3};
     const size_t base = (size_t)g * kRG * W + c;
     if (MODE == kPlain) {
 #pragma unroll
-        for (int r = 0; r < kRG; ++r) Yout[base + (size_t)r * W] = acc[r];
+        for (int r = 0; r < kRG; ++r)
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) Yout[base + (size_t)r * W + q] = acc[r][q];
         return;
     }
-    double d = 0.0;
-    if (MODE == kPq) {
-        const double b = a.beta[c];
+    double d[CPL];
 #pragma unroll
-        for (int r = 0; r < kRG; ++r) {
-            const size_t e = base + (size_t)r * W;
-            // beta = 0 (first iteration, converged column): Pd and Q may
-            // hold anything, so they are not read
-            const double pd = b != 0.0 ? Xin[e] + b * a.Pd[e] : Xin[e];
-            const double q = b != 0.0 ? acc[r] + b * a.Q[e] : acc[r];
-            a.Pd[e] = pd;
-            a.Q[e] = q;
-            d += pd * q;
-        }
-    } else {
+    for (int q = 0; q < CPL; ++q) {
+        d[q] = 0.0;
+        if (MODE == kPq) {
+            const double b = a.beta[c + q];
 #pragma unroll
-        for (int r = 0; r < kRG; ++r) {
-            const size_t e = base + (size_t)r * W;
-            a.Z[e] = acc[r];
-            d += a.R[e] * acc[r];
+            for (int r = 0; r < kRG; ++r) {
+                const size_t e = base + (size_t)r * W + q;
+                // beta = 0 (first iteration, converged column): Pd and Q may
+                // hold anything, so they are not read
+                const double pd = b != 0.0 ? Xin[e] + b * a.Pd[e] : Xin[e];
+                const double qv = b != 0.0 ? acc[r][q] + b * a.Q[e] : acc[r][q];
+                a.Pd[e] = pd;
+                a.Q[e] = qv;
+                d[q] += pd * qv;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kRG; ++r) {
+                const size_t e = base + (size_t)r * W + q;
+                a.Z[e] = acc[r][q];
+                d[q] += a.R[e] * acc[r][q];
+            }
         }
     }
-    const double s = wg_column_sum(d, red);
-    if (threadIdx.x < 64) a.part[(size_t)bx * W + c] = s;
+    // column sums over the 16 waves (fixed order), wave 0 writes them
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) red[wv][lane * CPL + q] = d[q];
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            double sum = 0.0;
+            for (int k = 0; k < kWv; ++k) sum += red[k][lane * CPL + q];
+            a.part[(size_t)bx * W + c + q] = sum;
+        }
+    }
 }
 
 // X = 0, R = B, part = B . B.
@@ -556,6 +598,11 @@ struct FactOp {
     int h_cap = 0;
     int nsets_cap = 0, order_cap = 0;
     long long solves = 0;
+    // optional timing of the S products of the iterations (dispatch events)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    long long timed_launches = 0;
+    double timed_ms = 0.0;
     ~FactOp() {
         for (RgMat* m : {&S, &F, &G, &GT}) m->release();
         Srp.release(); Grp.release(); Scol.release(); Gcol.release(); Sval.release(); Gval.release();
@@ -565,6 +612,7 @@ struct FactOp {
         for (auto* b : {&done, &active, &iters, &mx, &notconv}) b->release();
         tot.release();
         if (h_active) (void)hipHostFree(h_active);
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
 };
 
@@ -645,6 +693,27 @@ dim3 tile_grid(const Tiles& t) {
     return dim3((unsigned)(t.nx * t.ng));
 }
 
+// Launch of a row-group product over the block: two columns per lane when
+// the width is a multiple of 128, else one.  (Measured at K = 4096 on the
+// whole block, per CG iteration: one column per lane 3.5 ms, two 2.2 ms,
+// four 2.9 ms - at 90 registers only one 1024-thread workgroup fits a CU.)
+template <int MODE>
+void launch_spmm(const FactOp* f, const RgMat& A, const double* X, double* Y, const CgArgs& a, hipStream_t s,
+                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
+    Tiles t = a.t;
+    const int cpl = a.W % 128 == 0 ? 2 : 1;
+    t.ng = a.W / (64 * cpl);
+    t.xcd_split = t.ng >= 8 ? 1 : 0;
+    const dim3 grid = tile_grid(t), blk(1024);
+    auto k2 = rg_spmm_kernel<MODE, 2>;
+    auto k1 = rg_spmm_kernel<MODE, 1>;
+    auto k = cpl == 2 ? k2 : k1;
+    if (t0)
+        hipExtLaunchKernelGGL(k, grid, blk, 0, s, t0, t1, 0, A.view(), X, Y, a, t);
+    else
+        hipLaunchKernelGGL(k, grid, blk, 0, s, A.view(), X, Y, a, t);
+}
+
 CgArgs cg_args(FactOp* f, int W, double tol) {
     CgArgs a{};
     a.W = W;
@@ -684,13 +753,22 @@ hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, 
     {
         CgArgs p = a;
         p.first = 1;
-        hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, grid, blk, 0, s, f->G.view(), (const double*)a.R, a.T, p);
-        hipLaunchKernelGGL(rg_spmm_kernel<kRz>, grid, blk, 0, s, f->GT.view(), (const double*)a.T, a.Z, p);
+        launch_spmm<kPlain>(f, f->G, a.R, a.T, p, s);
+        launch_spmm<kRz>(f, f->GT, a.T, a.Z, p, s);
         hipLaunchKernelGGL(cg_colsum_kernel<kSumRZ>, gsum, blk, 0, s, p);
         FTRY(hipGetLastError());
     }
-    int it = 0, chunk = 0;
+    int it = 0, chunk = 0, nev = 0;  // nev: timing events used by this solve
     bool conv = false;
+    auto timed_event = [&](hipEvent_t* out) -> hipError_t {
+        if ((size_t)nev == f->ev_pool.size()) {
+            hipEvent_t e;
+            FTRY(hipEventCreate(&e));
+            f->ev_pool.push_back(e);
+        }
+        *out = f->ev_pool[nev++];
+        return hipSuccess;
+    };
     hipEvent_t ev[2] = {nullptr, nullptr};
     FTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     hipError_t err = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
@@ -702,14 +780,18 @@ hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, 
     while (err == hipSuccess && it < max_iter) {
         const int n_it = std::min(kChunk, max_iter - it);
         for (int k = 0; k < n_it; ++k) {
-            hipLaunchKernelGGL(rg_spmm_kernel<kPq>, grid, blk, 0, s, f->S.view(), (const double*)a.Z, a.Q, a);
+            hipEvent_t t0 = nullptr, t1 = nullptr;  // start and stop taken by the dispatch itself
+            if (f->timing && ((err = timed_event(&t0)) != hipSuccess || (err = timed_event(&t1)) != hipSuccess))
+                break;
+            launch_spmm<kPq>(f, f->S, a.Z, a.Q, a, s, t0, t1);
             hipLaunchKernelGGL(cg_colsum_kernel<kSumPQ>, gsum, blk, 0, s, a);
             hipLaunchKernelGGL(cg_update_kernel, grid, blk, 0, s, a);
             hipLaunchKernelGGL(cg_colsum_kernel<kSumRR>, gsum, blk, 0, s, a);
-            hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, grid, blk, 0, s, f->G.view(), (const double*)a.R, a.T, a);
-            hipLaunchKernelGGL(rg_spmm_kernel<kRz>, grid, blk, 0, s, f->GT.view(), (const double*)a.T, a.Z, a);
+            launch_spmm<kPlain>(f, f->G, a.R, a.T, a, s);
+            launch_spmm<kRz>(f, f->GT, a.T, a.Z, a, s);
             hipLaunchKernelGGL(cg_colsum_kernel<kSumRZ>, gsum, blk, 0, s, a);
         }
+        if (err != hipSuccess) break;
         it += n_it;
         if ((err = hipGetLastError()) != hipSuccess) break;
         const int slot = chunk & 1;
@@ -734,6 +816,21 @@ hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, 
     (void)hipEventDestroy(ev[0]);
     if (ev[1]) (void)hipEventDestroy(ev[1]);
     FTRY(err);
+    if (f->timing && nev > 0) {
+        // launches after convergence return at once: count only the
+        // products of iterations that ran for some column group
+        std::vector<int> itg(ng);
+        FTRY(hipMemcpyAsync(itg.data(), f->iters.p, (size_t)ng * sizeof(int), hipMemcpyDeviceToHost, s));
+        FTRY(hipStreamSynchronize(s));
+        int ran = 0;
+        for (int v : itg) ran = std::max(ran, v);
+        for (int k = 0; k < std::min(ran, nev / 2); ++k) {
+            float ms = 0.0f;
+            FTRY(hipEventElapsedTime(&ms, f->ev_pool[2 * k], f->ev_pool[2 * k + 1]));
+            f->timed_ms += ms;
+            f->timed_launches += 1;
+        }
+    }
     hipLaunchKernelGGL(cg_fold_kernel, dim3(1), dim3(std::max(64, (ng + 63) / 64 * 64)), 0, s, ng, f->active.p,
                        f->iters.p, f->tot.p, f->mx.p, f->notconv.p);
     FTRY(hipGetLastError());
@@ -903,8 +1000,7 @@ hipError_t fact_apply(FactOp* f, const double* x, double* y, double tol, int max
     hipLaunchKernelGGL(to_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, 1, x, (long long)K, W, f->U0.p);
     CgArgs a = cg_args(f, W, tol);
     a.active = nullptr;
-    hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, tile_grid(a.t), dim3(1024), 0, s, f->F.view(),
-                       (const double*)f->U0.p, f->B.p, a);
+    launch_spmm<kPlain>(f, f->F, f->U0.p, f->B.p, a, s);
     FTRY(hipGetLastError());
     FTRY(cg_solve(f, W, tol, max_iter, converged, s));
     hipLaunchKernelGGL(from_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, 1, (const double*)f->X.p, W, y,
@@ -944,8 +1040,7 @@ hipError_t fact_block(FactOp* f, const FactBlockArgs& b, int* converged, hipStre
     plain.active = nullptr;
     for (int l = 0; l <= b.order; ++l) {
         if (l > 0) {
-            hipLaunchKernelGGL(rg_spmm_kernel<kPlain>, grid, blk, 0, s, f->F.view(), (const double*)Ucur, f->B.p,
-                               plain);
+            launch_spmm<kPlain>(f, f->F, Ucur, f->B.p, plain, s);
             FTRY(hipGetLastError());
         }
         int conv = 1;
@@ -1003,6 +1098,15 @@ hipError_t fact_stats(FactOp* f, long long* solves, long long* iters, int* max_i
         *max_iters = std::max(*max_iters, m[y]);
     }
     return hipSuccess;
+}
+
+void fact_set_timing(FactOp* f, bool on) { f->timing = on; }
+
+void fact_take_timing(FactOp* f, long long* launches, double* ms) {
+    *launches = f->timed_launches;
+    *ms = f->timed_ms;
+    f->timed_launches = 0;
+    f->timed_ms = 0.0;
 }
 
 hipError_t fact_reset_stats(FactOp* f, hipStream_t s) {
