@@ -58,7 +58,11 @@ COUNTERS_HBM = {"kernel_source_sha256_16": "b20b5ef62b97a939", "fetch_kib": 2124
 # per step): all K columns of the benchmark cluster in one block, a bounded
 # number of recursion steps (each one solve); the rate scales to order N
 FACT_ORDER = 8
-COUNTERS_FACT = None  # rocprofv3 FETCH_SIZE / WRITE_SIZE of rg_spmm_kernel<1>, when taken
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of the S product (rg_spmm_kernel<1,2>)
+# of the factored point, averaged over the launches that did work (launches
+# queued after every column converged return at once and are left out)
+COUNTERS_FACT = {"kernel_source_sha256_16": "e0316dc77c11e6ed", "fetch_kib": 3218459.4, "write_kib": 506217.0,
+                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def kernel_source_hash(name="gemm.hip"):
@@ -209,11 +213,12 @@ def factored_point(stream, mu):
             "column_steps_per_s": col_steps, "columns_per_s_at_order": col_steps / (order + 1),
             "order": order, "cg_iterations_per_solve": iters / max(solves, 1),
             "cg_max_iterations": max_iters, "cg_tol": 1e-11, "max_abs_dP_vs_explicit_operator": diff,
-            "roofline": {"bound": "alu", "kernel": "rg_spmm_kernel<1> (S product of the CG iteration)",
+            "roofline": {"bound": "alu", "kernel": "rg_spmm_kernel<1,2> (S product of the CG iteration)",
                          "launches_timed": n_launch, "launch_ms": launch_ms, "achieved": achieved,
                          "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                          "algorithmic_bytes": alg_bytes, "spmm_GBps": gbs, "spmm_hbm_frac": gbs / PEAK_HBM_GBS,
-                         "traffic": traffic}}
+                         "traffic": traffic,
+                         "counter_GBps": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9}}
 
 
 def main():
@@ -224,6 +229,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-factored-point", action="store_true",
                     help="skip the factored-form (sparse F, CG solve with S) measurement")
+    ap.add_argument("--factored-only", action="store_true",
+                    help="only the factored-form measurement (at mu = 0), for profiling")
     ap.add_argument("--no-hbm-point", action="store_true",
                     help="skip the memory-bound FP32 K=32768 / 32-column measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -251,6 +258,12 @@ def main():
 
     import paper_2108_13478_amd as dmlib
     from synth import WORKLOADS, workload
+
+    if args.factored_only:
+        stream = torch.cuda.Stream()
+        torch.cuda.set_stream(stream)
+        print(json.dumps({"factored_point": factored_point(stream, 0.0)}), flush=True)
+        return
 
     w = WORKLOADS[WORKLOAD]
     order, beta, n_e = w["order"], w["beta"], w["n_electrons"]
