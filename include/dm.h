@@ -151,8 +151,9 @@ dm_status dm_get_operator(dm_ctx* ctx, int which, double* out);
  *   DM_E_STATE under DM_FP32).  P matches the other forms to within the
  *   solve tolerance amplified by the recursion (about 10 x cg_tol x the
  *   largest |P| entry).  The Lanczos interval is computed through the same
- *   solves.  Not for dm_batch_set_focks, dm_stoch_moments, dm_autotune,
- *   dm_set_pass_shape or dm_get_operator (DM_E_STATE).
+ *   solves, to a tolerance of at most 1e-8.  dm_stoch_moments runs the same
+ *   factored recursion from the probe vectors.  Not for dm_batch_set_focks,
+ *   dm_autotune, dm_set_pass_shape or dm_get_operator (DM_E_STATE).
  * Errors: DM_E_ARG (unknown form). */
 enum { DM_FORM_GENERAL = 0, DM_FORM_SYMMETRIC = 1, DM_FORM_FACTORED = 2 };
 dm_status dm_set_operator_form(dm_ctx* ctx, int form);
@@ -427,7 +428,8 @@ dm_status dm_mlp_predict(dm_ctx* ctx, const double* m_stoch, int n_mom, double b
 /* Stochastic moments (1/n_vec) sum_s xi_s^T T_l(H_N) xi_s, l < n_mom, with
  * caller-supplied probe vectors xi (host or device, K x n_vec column-major
  * FP64, e.g. independent +-1 entries).  m_out: host, n_mom FP64.
- * Does not touch the accumulated moments. */
+ * Does not touch the accumulated moments.  In the factored form every step
+ * is one solve with S (DM_E_NOCONV when one reaches the iteration limit). */
 dm_status dm_stoch_moments(dm_ctx* ctx, int n_mom, int n_vec, const double* xi, double* m_out);
 
 #ifdef __cplusplus

@@ -283,6 +283,11 @@ struct FactBlockArgs {
     double* const* P_out;   // nsets destinations (K x nc column-major, host or device) or null
 };
 hipError_t fact_block(FactOp* f, const FactBlockArgs& a, int* converged, hipStream_t s);
+// Stochastic moments sum_s xi_s^T T_l(H_N) xi_s, l < n_mom, added to mom
+// (device, n_mom): the recursion from U_0 = xi (K x n_vec column-major,
+// host or device) with one solve per step.
+hipError_t fact_stoch(FactOp* f, int n_vec, const double* xi, int n_mom, double ebar, double de, double tol,
+                      int max_iter, double* mom, int* flag, int* converged, hipStream_t s);
 // Solves since the last reset, the largest per-group sum of iterations and
 // the largest iteration count of one solve.
 hipError_t fact_stats(FactOp* f, long long* solves, long long* iters, int* max_iters, hipStream_t s);

@@ -1082,6 +1082,71 @@ hipError_t fact_block(FactOp* f, const FactBlockArgs& b, int* converged, hipStre
     return hipSuccess;
 }
 
+hipError_t fact_stoch(FactOp* f, int n_vec, const double* xi, int n_mom, double ebar, double de, double tol,
+                      int max_iter, double* mom, int* flag, int* converged, hipStream_t s) {
+    *converged = 1;
+    const int K = f->K;
+    const int W = (n_vec + 63) / 64 * 64;
+    FTRY(ensure_width(f, W, 1, n_mom, s));
+    const Tiles tl = tiles_for(f, W);
+    const dim3 grid = tile_grid(tl), blk(1024);
+    const size_t nb = (size_t)f->Kr * W;
+    // the probe vectors become U_0 (through the solution slot X) and the
+    // moment vectors Zm
+    FTRY(hipMemcpy2DAsync(f->Pout.p, (size_t)K * 8, xi, (size_t)K * 8, (size_t)K * 8, n_vec, hipMemcpyDefault, s));
+    hipLaunchKernelGGL(to_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, n_vec, (const double*)f->Pout.p,
+                       (long long)K, W, f->X.p);
+    hipLaunchKernelGGL(to_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, n_vec, (const double*)f->Pout.p,
+                       (long long)K, W, f->Zm.p);
+    FTRY(hipGetLastError());
+    StepArgs st{};
+    st.W = W;
+    st.t = tl;
+    st.nsets = 0;  // moments only
+    st.P = f->P.p;
+    st.pstride = (long long)nb;
+    st.Zm = f->Zm.p;
+    st.mpart = f->mpart.p;
+    double* Ucur = f->U0.p;
+    double* Uoth = f->U1.p;
+    CgArgs plain = cg_args(f, W, tol);
+    plain.active = nullptr;
+    for (int l = 0; l < n_mom; ++l) {
+        if (l > 0) {
+            launch_spmm<kPlain>(f, f->F, Ucur, f->B.p, plain, s);
+            FTRY(hipGetLastError());
+            int conv = 1;
+            FTRY(cg_solve(f, W, tol, max_iter, &conv, s));
+            if (!conv) {
+                *converged = 0;
+                return hipSuccess;
+            }
+        }
+        st.l = l;
+        st.X = f->X.p;
+        if (l == 0) {
+            st.sx = 1.0;
+            st.su = 0.0;
+            st.has_prev = 0;
+            st.Ucur = nullptr;
+            st.Uprev = nullptr;
+            st.Uout = Ucur;
+        } else {
+            const double al = l == 1 ? 1.0 : 2.0;
+            st.sx = al / de;
+            st.su = -al * ebar / de;
+            st.has_prev = l > 1;
+            st.Ucur = Ucur;
+            st.Uprev = Uoth;
+            st.Uout = Uoth;
+        }
+        hipLaunchKernelGGL(fact_step_kernel, grid, blk, 0, s, st);
+        FTRY(hipGetLastError());
+        if (l > 0) std::swap(Ucur, Uoth);
+    }
+    return reduce_moments(n_mom - 1, tl.ng * tl.nx, f->mpart.p, mom, flag, s);
+}
+
 hipError_t fact_stats(FactOp* f, long long* solves, long long* iters, int* max_iters, hipStream_t s) {
     *solves = f->solves;
     *iters = 0;

@@ -19,7 +19,7 @@ import scipy.linalg
 import oracle as O
 from oracle import factored_oracle as FO
 import paper_2108_13478_amd as dmlib
-from synth import make_cluster, workload
+from synth import WORKLOADS, make_cluster, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -170,8 +170,6 @@ def test_factored_edge_cases(c1):
     with pytest.raises(dmlib.DMError):
         ctx.dm_get_operator(dmlib.DM_OP_SINV)
     with pytest.raises(dmlib.DMError):
-        ctx.dm_stoch_moments(8, np.ones((c.K, 2)))
-    with pytest.raises(dmlib.DMError):
         ctx.dm_autotune(64, 1)
     with pytest.raises(dmlib.DMError):
         ctx.dm_set_factored_options(cg_tol=0.0)
@@ -221,3 +219,21 @@ def test_factored_K4096_sampled(c2):
     say(f"  {len(cols)} columns N={N}: max|dP| = {err:.3e} (|P|max {np.abs(ref).max():.1f}); "
         f"{ns} solves, {it / max(ns, 1):.1f} iterations per solve, at most {mx}")
     assert err <= TOL_P
+
+
+
+def test_factored_stochastic_moments(c1):
+    """xi^T T_l(H_N) xi with H applied through solves, against the oracle's
+    eigen-route value of the same probes; m_0 = xi . xi exactly."""
+    c, sp, (emin, emax) = c1
+    from synth import rademacher
+
+    ctx = fact_ctx(c, (emin, emax))
+    xi = rademacher(c.K, 8, 5)
+    n_mom = 48
+    ms = ctx.dm_stoch_moments(n_mom, xi)
+    ref = O.stochastic_moments(sp, xi, n_mom, emin, emax)
+    err = np.abs(ms - ref).max()
+    say(f"case: factored stochastic moments K={c.K}, 8 probes, {n_mom} moments: max|dm| = {err:.2e}")
+    assert ms[0] == c.K
+    assert err < 1e-8 * c.K
