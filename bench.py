@@ -61,7 +61,7 @@ FACT_ORDER = 8
 # rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of the S product (rg_spmm_kernel<1,2>)
 # of the factored point, averaged over the launches that did work (launches
 # queued after every column converged return at once and are left out)
-COUNTERS_FACT = {"kernel_source_sha256_16": "e0316dc77c11e6ed", "fetch_kib": 3218459.4, "write_kib": 506217.0,
+COUNTERS_FACT = {"kernel_source_sha256_16": "1bf092a6eb692a8f", "fetch_kib": 3211764.2, "write_kib": 505374.3,
                  "fetch_scale": 2.0, "write_scale": 1.0}
 
 

@@ -164,12 +164,12 @@ dm_status dm_set_operator_form(dm_ctx* ctx, int form);
  * the call with DM_E_NOCONV).  fsai_drop, fsai_max_per_row: pattern of row
  * i of G, the lower entries j < i of S with |S_ij| >= fsai_drop
  * sqrt(S_ii S_jj), at most fsai_max_per_row - 1 of them (the largest), and
- * the diagonal (defaults 1e-3 and 128); row i of G is then the solution of
+ * the diagonal (defaults 1e-5 and 192); row i of G is then the solution of
  * S[J, J] g = e_i scaled so that (G S G^T)_ii = 1 (Kolotilina-Yeremin
  * factorised sparse approximate inverse).  The tolerance and limit apply
  * from the next call; the pattern from the next dm_set_fock.
  * Errors: DM_E_ARG (cg_tol not in (0, 1), cg_max_iter < 1, fsai_drop < 0,
- * fsai_max_per_row not in [1, 128]). */
+ * fsai_max_per_row not in [1, 192]). */
 dm_status dm_set_factored_options(dm_ctx* ctx, double cg_tol, int cg_max_iter, double fsai_drop,
                                   int fsai_max_per_row);
 

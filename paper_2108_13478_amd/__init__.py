@@ -290,7 +290,7 @@ class Context:
             ptrs if P_outs is not None else None))
         return P_outs
 
-    def dm_set_factored_options(self, cg_tol=1e-11, cg_max_iter=2000, fsai_drop=1e-3, fsai_max_per_row=128):
+    def dm_set_factored_options(self, cg_tol=1e-11, cg_max_iter=2000, fsai_drop=1e-5, fsai_max_per_row=192):
         self._check(self._lib.dm_set_factored_options(self.h, float(cg_tol), int(cg_max_iter), float(fsai_drop),
                                                       int(fsai_max_per_row)))
 

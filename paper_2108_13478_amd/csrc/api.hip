@@ -105,8 +105,8 @@ struct dm_ctx {
     // factored form: solve tolerance and iteration limit, FSAI pattern
     double cg_tol = 1e-11;
     int cg_max_iter = 2000;
-    double fsai_drop = 1e-3;
-    int fsai_cap = 128;
+    double fsai_drop = 1e-5;
+    int fsai_cap = 192;
 
     // workspace
     DevBuf<double> Ua, Ub, Z, P;  // sized in bytes via double slots
@@ -903,8 +903,8 @@ dm_status dm_set_factored_options(dm_ctx* c, double cg_tol, int cg_max_iter, dou
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (!(cg_tol > 0.0 && cg_tol < 1.0) || cg_max_iter < 1 || !(fsai_drop >= 0.0) || !std::isfinite(fsai_drop) ||
-        fsai_max_per_row < 1 || fsai_max_per_row > 128)
-        return set_err(c, DM_E_ARG, "need 0 < cg_tol < 1, cg_max_iter >= 1, fsai_drop >= 0, 1 <= max_per_row <= 128");
+        fsai_max_per_row < 1 || fsai_max_per_row > 192)
+        return set_err(c, DM_E_ARG, "need 0 < cg_tol < 1, cg_max_iter >= 1, fsai_drop >= 0, 1 <= max_per_row <= 192");
     c->cg_tol = cg_tol;
     c->cg_max_iter = cg_max_iter;
     c->fsai_drop = fsai_drop;

@@ -251,7 +251,7 @@ FactOp* fact_create();
 void fact_destroy(FactOp* f);
 // Host CSR F and S (K x K, sorted columns).  The FSAI pattern of row i keeps
 // the lower entries with |S_ij| >= drop sqrt(S_ii S_jj), at most cap - 1 of
-// them (the largest), plus the diagonal; cap <= 128.  *bad_row = row + 1 of
+// them (the largest), plus the diagonal; cap <= 192.  *bad_row = row + 1 of
 // a row whose S[J, J] is not positive definite (0 = none).
 hipError_t fact_setup(FactOp* f, int K, const long long* Frp, const int* Fcol, const double* Fval,
                       const long long* Srp, const int* Scol, const double* Sval, double drop, int cap,

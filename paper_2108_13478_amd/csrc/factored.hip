@@ -41,7 +41,7 @@ namespace {
 constexpr int kRG = 4;              // rows per group
 constexpr int kWv = 16;             // waves per workgroup of the row kernels
 constexpr int kRowsWG = kRG * kWv;  // 64 rows per workgroup
-constexpr int kFsaiMax = 128;       // largest pattern of one FSAI row (LDS)
+constexpr int kFsaiMax = 192;       // largest pattern of one FSAI row (packed triangle in LDS)
 constexpr int kChunk = 8;           // iterations between convergence polls
 
 struct RgView {
@@ -441,11 +441,15 @@ __global__ void gather_vals_kernel(long long n, const int* idx, const double* sr
 // One FSAI row per workgroup: with J the row's pattern (sorted, ending with
 // the row itself), factor S[J, J] = L L^T in LDS and solve L^T g = e_last;
 // g is row i of G on J (G S G^T then has a unit diagonal, and G = L_S^-1
-// when J is the whole lower triangle).  info[0] = some failing row + 1.
+// when J is the whole lower triangle).  The lower triangle is stored packed
+// (row r at r (r + 1) / 2), so patterns of up to 192 entries fit.
+// info[0] = some failing row + 1.
+__device__ inline int tri(int r, int t) { return r * (r + 1) / 2 + t; }
+
 __global__ void __launch_bounds__(256) fsai_kernel(const long long* Srp, const int* Scol,
                                                    const double* Sval, const long long* Grp,
                                                    const int* Gcol, double* Gval, int* info) {
-    __shared__ double A[kFsaiMax][kFsaiMax + 1];
+    __shared__ double A[kFsaiMax * (kFsaiMax + 1) / 2];
     __shared__ int J[kFsaiMax];
     __shared__ double acc[kFsaiMax];
     __shared__ int bad;
@@ -454,7 +458,7 @@ __global__ void __launch_bounds__(256) fsai_kernel(const long long* Srp, const i
     const long long q0 = Grp[i];
     const int n = (int)(Grp[i + 1] - q0);
     for (int t = tid; t < n; t += 256) J[t] = Gcol[q0 + t];
-    for (int e = tid; e < n * kFsaiMax; e += 256) A[e / kFsaiMax][e % kFsaiMax] = 0.0;
+    for (int e = tid; e < n * (n + 1) / 2; e += 256) A[e] = 0.0;
     if (tid == 0) bad = 0;
     __syncthreads();
     // lower triangle of S[J, J]: row J[r] of S, columns found in J[0..r]
@@ -468,24 +472,26 @@ __global__ void __launch_bounds__(256) fsai_kernel(const long long* Srp, const i
                 const int mid = (lo + hi) >> 1;
                 if (J[mid] < k) lo = mid + 1; else hi = mid;
             }
-            if (J[lo] == k) A[r][lo] = Sval[p];
+            if (J[lo] == k) A[tri(r, lo)] = Sval[p];
         }
     }
     __syncthreads();
     // right-looking Cholesky, lower
     for (int k = 0; k < n; ++k) {
         if (tid == 0) {
-            const double dkk = A[k][k];
+            const double dkk = A[tri(k, k)];
             if (!(dkk > 0.0)) bad = 1;
-            A[k][k] = dkk > 0.0 ? sqrt(dkk) : 1.0;
+            A[tri(k, k)] = dkk > 0.0 ? sqrt(dkk) : 1.0;
         }
         __syncthreads();
         if (bad) break;
-        const double piv = A[k][k];
-        for (int r = k + 1 + tid; r < n; r += 256) A[r][k] /= piv;
+        const double piv = A[tri(k, k)];
+        for (int r = k + 1 + tid; r < n; r += 256) A[tri(r, k)] /= piv;
         __syncthreads();
-        for (int r = k + 1 + w; r < n; r += 4)
-            for (int t = k + 1 + lane; t <= r; t += 64) A[r][t] -= A[r][k] * A[t][k];
+        for (int r = k + 1 + w; r < n; r += 4) {
+            const double ark = A[tri(r, k)];
+            for (int t = k + 1 + lane; t <= r; t += 64) A[tri(r, t)] -= ark * A[tri(t, k)];
+        }
         __syncthreads();
     }
     if (bad) {
@@ -497,10 +503,10 @@ __global__ void __launch_bounds__(256) fsai_kernel(const long long* Srp, const i
     for (int t = tid; t < n; t += 256) acc[t] = t == n - 1 ? 1.0 : 0.0;
     __syncthreads();
     for (int t = n - 1; t >= 0; --t) {
-        const double gt = acc[t] / A[t][t];
+        const double gt = acc[t] / A[tri(t, t)];
         __syncthreads();
         if (tid == 0) acc[t] = gt;
-        for (int r = tid; r < t; r += 256) acc[r] -= A[t][r] * gt;
+        for (int r = tid; r < t; r += 256) acc[r] -= A[tri(t, r)] * gt;
         __syncthreads();
     }
     for (int t = tid; t < n; t += 256) Gval[q0 + t] = acc[t];

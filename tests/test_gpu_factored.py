@@ -50,7 +50,7 @@ def fact_ctx(c, bounds=None, **opts):
     return ctx
 
 
-def check_rows(S, rp, col, val, rows, drop=1e-3, cap=128):
+def check_rows(S, rp, col, val, rows, drop=1e-5, cap=192):
     pats = FO.fsai_pattern(S, drop, cap, rows=rows)
     worst = 0.0
     for i, J in zip(rows, pats):
