@@ -513,10 +513,15 @@ __global__ void __launch_bounds__(256) fsai_kernel(const long long* Srp, const i
 }
 
 // --------------------------------------------------------------- host side
+// Device buffer owned by its holder (freed on release or destruction).
 template <typename T>
 struct Buf {
     T* p = nullptr;
     size_t n = 0;
+    Buf() = default;
+    Buf(const Buf&) = delete;
+    Buf& operator=(const Buf&) = delete;
+    ~Buf() { release(); }
     hipError_t ensure(size_t m) {
         if (m <= n && p) return hipSuccess;
         if (p) (void)hipFree(p);
@@ -607,6 +612,7 @@ struct FactOp {
     // optional timing of the S products of the iterations (dispatch events)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
+    hipEvent_t poll[2] = {nullptr, nullptr};  // convergence polling, one per chunk parity
     long long timed_launches = 0;
     double timed_ms = 0.0;
     ~FactOp() {
@@ -619,6 +625,8 @@ struct FactOp {
         tot.release();
         if (h_active) (void)hipHostFree(h_active);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : poll)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -775,9 +783,10 @@ hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, 
         *out = f->ev_pool[nev++];
         return hipSuccess;
     };
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    FTRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    hipError_t err = hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+    for (hipEvent_t& e : f->poll)
+        if (!e) FTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipEvent_t* ev = f->poll;
+    hipError_t err = hipSuccess;
     auto check = [&](int k) -> int {  // active columns seen after chunk k
         int n = 0;
         for (int y = 0; y < ng; ++y) n += f->h_active[(k & 1) * f->h_cap + y];
@@ -819,8 +828,6 @@ hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, 
         const int last = (chunk > 0 && it >= max_iter) ? chunk - 1 : chunk;
         if ((err = hipEventSynchronize(ev[last & 1])) == hipSuccess) conv = check(last) == 0;
     }
-    (void)hipEventDestroy(ev[0]);
-    if (ev[1]) (void)hipEventDestroy(ev[1]);
     FTRY(err);
     if (f->timing && nev > 0) {
         // launches after convergence return at once: count only the
