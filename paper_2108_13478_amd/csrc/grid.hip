@@ -5,77 +5,123 @@
 //
 // One workgroup per cell of 4 x 4 x 4 grid points.  The host lists, per
 // cell, the functions whose window reaches the cell (b-list) and those of
-// them whose column is in the pass (a-list, with the column position).  The
-// 64 points x 64 b values of phi are staged in LDS chunk by chunk; wave q
-// accumulates t_a(g) = sum_b phi_b(g) P_ba for a-list entries q, q+4, ...
-// (the P reads are the same address across the wave, i.e. broadcasts), and
-// finally n(g) += 2 sum_a phi_a(g) t_a(g), reduced over the 4 waves in a
-// fixed order.  Cells own disjoint points, so no atomics are needed.
+// them whose column is in the pass (a-list, with the column position).  For
+// a chunk of 64 a-entries the workgroup forms t(g, a) = sum_b phi_b(g) P_ba,
+// a 64 x 64 x n_b product, 64 b at a time: phi of the b chunk at the 64
+// points and the 64 x 64 block of P are staged in LDS, and each thread
+// accumulates a 4-point x 4-column block in registers.  Then n(g) +=
+// 2 sum_a phi_a(g) t(g, a), reduced over the threads of a point in a fixed
+// order.  A Gaussian and its cube window factor over x, y and z, so phi of
+// one function on the cell's 4 x 4 x 4 points takes 12 exponentials.  Cells
+// own disjoint points, so no atomics are needed.
 #include "dm_common.hpp"
 
 namespace dm {
 namespace {
 
-__device__ inline double sgauss(const GridArgs& a, int b, double x, double y, double z) {
-    const double dx = x - a.cx[b], dy = y - a.cy[b], dz = z - a.cz[b];
-    const double R = a.R[b];
-    if (!(fabs(dx) <= R && fabs(dy) <= R && fabs(dz) <= R)) return 0.0;
-    return a.norm[b] * exp(-a.ex[b] * (dx * dx + dy * dy + dz * dz));
+constexpr int kPs = 66;  // row stride of the staged P block (doubles): 16-byte rows, few bank conflicts
+
+// exp(-a d^2) inside the window |d| <= R, else 0
+__device__ inline double axis_factor(double a, double R, double d) {
+    return fabs(d) <= R ? exp(-a * d * d) : 0.0;
 }
 
 __global__ void __launch_bounds__(256) density_kernel(GridArgs a) {
-    constexpr int NA = 16;  // a-list entries per wave and chunk (4 waves x 16 = 64)
-    __shared__ double phb[64][64];
-    __shared__ double red[4][64];
+    __shared__ __align__(16) double phb[64][64];  // phi_b(point), b of the chunk x 64 points
+    __shared__ __align__(16) double pb[64][kPs];  // P_ba, b of the chunk x a of the chunk
+    __shared__ double red[16][64];    // per-thread point sums before the final reduction
     const int cell = blockIdx.x;
     const int ccx = cell % a.ncx, ccy = (cell / a.ncx) % a.ncy, ccz = cell / (a.ncx * a.ncy);
     const int tid = threadIdx.x;
-    const int p = tid & 63, q = tid >> 6;
-    const int gi = 4 * ccx + (p & 3), gj = 4 * ccy + ((p >> 2) & 3), gk = 4 * ccz + (p >> 4);
-    const bool valid = gi < a.nx && gj < a.ny && gk < a.nz;
-    const double x = a.ox + a.h * gi, y = a.oy + a.h * gj, z = a.oz + a.h * gk;
+    const int tp = tid & 15, ta = tid >> 4;  // points 4 tp .. 4 tp + 3 (x = 0..3), a-entries 4 ta .. 4 ta + 3
+    const int py = tp & 3, pz = tp >> 2;     // the thread's four points differ in x only
+    const double x0 = a.ox + a.h * (4 * ccx), y = a.oy + a.h * (4 * ccy + py), z = a.oz + a.h * (4 * ccz + pz);
     const int a0 = a.alpha_ptr[cell], a1 = a.alpha_ptr[cell + 1];
     const int b0 = a.beta_ptr[cell], b1 = a.beta_ptr[cell + 1];
-    double nacc = 0.0;
-    for (int as = a0; as < a1; as += 4 * NA) {
-        double t[NA];
+    double npt[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int as = a0; as < a1; as += 64) {
+        const int na = min(64, a1 - as);
+        double t[4][4];
 #pragma unroll
-        for (int m = 0; m < NA; ++m) t[m] = 0.0;
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) t[i][j] = 0.0;
         for (int bs = b0; bs < b1; bs += 64) {
             const int nb = min(64, b1 - bs);
-            // phi of this b-chunk at the cell's 64 points
-            for (int e = tid; e < 64 * 64; e += 256) {
-                const int pt = e & 63, bb = e >> 6;
-                double v = 0.0;
+            // phi of the b chunk: thread (bb = tid / 4, z-plane q = tid % 4)
+            // writes the 16 points of its plane
+            {
+                const int bb = tid >> 2, q = tid & 3;
+                double fxv[4], fyv[4], fz = 0.0, nrm = 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) fxv[u] = fyv[u] = 0.0;
                 if (bb < nb) {
-                    const int px = 4 * ccx + (pt & 3), py = 4 * ccy + ((pt >> 2) & 3), pz = 4 * ccz + (pt >> 4);
-                    v = sgauss(a, a.beta_idx[bs + bb], a.ox + a.h * px, a.oy + a.h * py, a.oz + a.h * pz);
+                    const int b = a.beta_idx[bs + bb];
+                    const double e = a.ex[b], R = a.R[b];
+                    nrm = a.norm[b];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        fxv[u] = axis_factor(e, R, a.ox + a.h * (4 * ccx + u) - a.cx[b]);
+                        fyv[u] = axis_factor(e, R, a.oy + a.h * (4 * ccy + u) - a.cy[b]);
+                    }
+                    fz = axis_factor(e, R, a.oz + a.h * (4 * ccz + q) - a.cz[b]);
                 }
-                phb[bb][pt] = v;
+                const double s = nrm * fz;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) phb[bb][u + 4 * v + 16 * q] = s * fyv[v] * fxv[u];
+            }
+            // P block: lane k = b of the chunk (rows of one P column are
+            // close together), wave w takes a-entries w, w + 4, ...
+            {
+                const int k = tid & 63, w = tid >> 6;
+                const long long brow = k < nb ? a.beta_idx[bs + k] : 0;
+                for (int aa = w; aa < 64; aa += 4) {
+                    double v = 0.0;
+                    if (k < nb && aa < na) v = a.P[(long long)a.alpha_col[as + aa] * a.ldp + brow];
+                    pb[k][aa] = v;
+                }
             }
             __syncthreads();
-            for (int bb = 0; bb < nb; ++bb) {
-                const double f = phb[bb][p];
-                const long long b = a.beta_idx[bs + bb];
+            for (int k = 0; k < nb; ++k) {
+                const double2 f01 = *reinterpret_cast<const double2*>(&phb[k][4 * tp]);
+                const double2 f23 = *reinterpret_cast<const double2*>(&phb[k][4 * tp + 2]);
+                const double2 p01 = *reinterpret_cast<const double2*>(&pb[k][4 * ta]);
+                const double2 p23 = *reinterpret_cast<const double2*>(&pb[k][4 * ta + 2]);
+                const double f[4] = {f01.x, f01.y, f23.x, f23.y};
+                const double p[4] = {p01.x, p01.y, p23.x, p23.y};
 #pragma unroll
-                for (int m = 0; m < NA; ++m) {
-                    const int ai = as + q + 4 * m;
-                    if (ai < a1) t[m] += f * a.P[(long long)a.alpha_col[ai] * a.ldp + b];
-                }
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) t[i][j] += f[i] * p[j];
             }
             __syncthreads();
         }
+        // n(g) += 2 phi_a(g) t(g, a) for the thread's four a-entries
 #pragma unroll
-        for (int m = 0; m < NA; ++m) {
-            const int ai = as + q + 4 * m;
-            if (ai < a1) nacc += 2.0 * sgauss(a, a.alpha_idx[ai], x, y, z) * t[m];
+        for (int j = 0; j < 4; ++j) {
+            const int aa = 4 * ta + j;
+            if (aa >= na) continue;
+            const int f = a.alpha_idx[as + aa];
+            const double e = a.ex[f], R = a.R[f];
+            const double s = 2.0 * a.norm[f] * axis_factor(e, R, y - a.cy[f]) * axis_factor(e, R, z - a.cz[f]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) npt[i] += s * axis_factor(e, R, x0 + a.h * i - a.cx[f]) * t[i][j];
         }
     }
-    red[q][p] = nacc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[ta][4 * tp + i] = npt[i];
     __syncthreads();
-    if (q == 0 && valid) {
-        const long long g = gi + (long long)a.nx * (gj + (long long)a.ny * gk);
-        a.n[g] += ((red[0][p] + red[1][p]) + red[2][p]) + red[3][p];
+    if (tid < 64) {
+        const int p = tid;
+        const int gi = 4 * ccx + (p & 3), gj = 4 * ccy + ((p >> 2) & 3), gk = 4 * ccz + (p >> 4);
+        if (gi < a.nx && gj < a.ny && gk < a.nz) {
+            double sum = 0.0;
+            for (int q = 0; q < 16; ++q) sum += red[q][p];
+            const long long g = gi + (long long)a.nx * (gj + (long long)a.ny * gk);
+            a.n[g] += sum;
+        }
     }
 }
 
