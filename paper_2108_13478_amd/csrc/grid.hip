@@ -12,8 +12,9 @@
 // accumulates a 4-point x 4-column block in registers.  Then n(g) +=
 // 2 sum_a phi_a(g) t(g, a), reduced over the threads of a point in a fixed
 // order.  A Gaussian and its cube window factor over x, y and z, so phi of
-// one function on the cell's 4 x 4 x 4 points takes 12 exponentials.  Cells
-// own disjoint points, so no atomics are needed.
+// one function on the cell's 4 x 4 x 4 points takes 12 exponentials, each
+// computed by one lane and shared by wave shuffles.  Cells own disjoint
+// points, so no atomics are needed.
 #include "dm_common.hpp"
 
 namespace dm {
@@ -35,7 +36,6 @@ __global__ void __launch_bounds__(256) density_kernel(GridArgs a) {
     const int tid = threadIdx.x;
     const int tp = tid & 15, ta = tid >> 4;  // points 4 tp .. 4 tp + 3 (x = 0..3), a-entries 4 ta .. 4 ta + 3
     const int py = tp & 3, pz = tp >> 2;     // the thread's four points differ in x only
-    const double x0 = a.ox + a.h * (4 * ccx), y = a.oy + a.h * (4 * ccy + py), z = a.oz + a.h * (4 * ccz + pz);
     const int a0 = a.alpha_ptr[cell], a1 = a.alpha_ptr[cell + 1];
     const int b0 = a.beta_ptr[cell], b1 = a.beta_ptr[cell + 1];
     double npt[4] = {0.0, 0.0, 0.0, 0.0};
@@ -48,25 +48,28 @@ __global__ void __launch_bounds__(256) density_kernel(GridArgs a) {
             for (int j = 0; j < 4; ++j) t[i][j] = 0.0;
         for (int bs = b0; bs < b1; bs += 64) {
             const int nb = min(64, b1 - bs);
-            // phi of the b chunk: thread (bb = tid / 4, z-plane q = tid % 4)
-            // writes the 16 points of its plane
+            // phi of the b chunk: the four lanes of function bb = tid / 4
+            // compute its x, y and z factors at coordinate q = tid % 4, share
+            // them, and each writes the 16 points of z-plane q
             {
                 const int bb = tid >> 2, q = tid & 3;
-                double fxv[4], fyv[4], fz = 0.0, nrm = 0.0;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) fxv[u] = fyv[u] = 0.0;
+                double fxq = 0.0, fyq = 0.0, fzq = 0.0, nrm = 0.0;
                 if (bb < nb) {
                     const int b = a.beta_idx[bs + bb];
                     const double e = a.ex[b], R = a.R[b];
                     nrm = a.norm[b];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        fxv[u] = axis_factor(e, R, a.ox + a.h * (4 * ccx + u) - a.cx[b]);
-                        fyv[u] = axis_factor(e, R, a.oy + a.h * (4 * ccy + u) - a.cy[b]);
-                    }
-                    fz = axis_factor(e, R, a.oz + a.h * (4 * ccz + q) - a.cz[b]);
+                    fxq = axis_factor(e, R, a.ox + a.h * (4 * ccx + q) - a.cx[b]);
+                    fyq = axis_factor(e, R, a.oy + a.h * (4 * ccy + q) - a.cy[b]);
+                    fzq = axis_factor(e, R, a.oz + a.h * (4 * ccz + q) - a.cz[b]);
                 }
-                const double s = nrm * fz;
+                const int base = (tid & 63) & ~3;
+                double fxv[4], fyv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    fxv[u] = __shfl(fxq, base + u, 64);
+                    fyv[u] = __shfl(fyq, base + u, 64);
+                }
+                const double s = nrm * fzq;
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -98,16 +101,32 @@ __global__ void __launch_bounds__(256) density_kernel(GridArgs a) {
             }
             __syncthreads();
         }
-        // n(g) += 2 phi_a(g) t(g, a) for the thread's four a-entries
+        // n(g) += 2 phi_a(g) t(g, a) for the thread's four a-entries.  The
+        // 16 lanes sharing an a-entry (same ta) compute its 12 axis factors,
+        // lane tp: x (tp < 4), y (4..7) or z (8..11) at coordinate tp % 4.
+        {
+            const int base = (tid & 63) & ~15;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int aa = 4 * ta + j;
-            if (aa >= na) continue;
-            const int f = a.alpha_idx[as + aa];
-            const double e = a.ex[f], R = a.R[f];
-            const double s = 2.0 * a.norm[f] * axis_factor(e, R, y - a.cy[f]) * axis_factor(e, R, z - a.cz[f]);
+            for (int j = 0; j < 4; ++j) {
+                const int aa = 4 * ta + j;
+                double fac = 0.0, nrm = 0.0;
+                if (aa < na) {
+                    const int f = a.alpha_idx[as + aa];
+                    const double e = a.ex[f], R = a.R[f];
+                    nrm = 2.0 * a.norm[f];
+                    const int c = tp & 3;
+                    if (tp < 4)
+                        fac = axis_factor(e, R, a.ox + a.h * (4 * ccx + c) - a.cx[f]);
+                    else if (tp < 8)
+                        fac = axis_factor(e, R, a.oy + a.h * (4 * ccy + c) - a.cy[f]);
+                    else if (tp < 12)
+                        fac = axis_factor(e, R, a.oz + a.h * (4 * ccz + c) - a.cz[f]);
+                }
+                const double fyv = __shfl(fac, base + 4 + py, 64), fzv = __shfl(fac, base + 8 + pz, 64);
+                const double s = nrm * fyv * fzv;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) npt[i] += s * axis_factor(e, R, x0 + a.h * i - a.cx[f]) * t[i][j];
+                for (int i = 0; i < 4; ++i) npt[i] += s * __shfl(fac, base + i, 64) * t[i][j];
+            }
         }
     }
 #pragma unroll
