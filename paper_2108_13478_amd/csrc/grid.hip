@@ -20,6 +20,7 @@
 namespace dm {
 namespace {
 
+constexpr int kBc = 32;  // b-functions per staged chunk
 constexpr int kPs = 66;  // row stride of the staged P block (doubles): 16-byte rows, few bank conflicts
 
 // exp(-a d^2) inside the window |d| <= R, else 0
@@ -27,10 +28,11 @@ __device__ inline double axis_factor(double a, double R, double d) {
     return fabs(d) <= R ? exp(-a * d * d) : 0.0;
 }
 
-__global__ void __launch_bounds__(256) density_kernel(GridArgs a) {
-    __shared__ __align__(16) double phb[64][64];  // phi_b(point), b of the chunk x 64 points
-    __shared__ __align__(16) double pb[64][kPs];  // P_ba, b of the chunk x a of the chunk
-    __shared__ double red[16][64];    // per-thread point sums before the final reduction
+// 33 KB of LDS and at most 168 registers: three workgroups per CU
+__global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
+    __shared__ __align__(16) double phb[kBc][64];  // phi_b(point), b of the chunk x 64 points
+    __shared__ __align__(16) double pb[kBc][kPs];  // P_ba, b of the chunk x a of the chunk
+    double(*red)[64] = phb;  // after the last chunk: per-thread point sums, 16 x 64
     const int cell = blockIdx.x;
     const int ccx = cell % a.ncx, ccy = (cell / a.ncx) % a.ncy, ccz = cell / (a.ncx * a.ncy);
     const int tid = threadIdx.x;
@@ -46,13 +48,14 @@ __global__ void __launch_bounds__(256) density_kernel(GridArgs a) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) t[i][j] = 0.0;
-        for (int bs = b0; bs < b1; bs += 64) {
-            const int nb = min(64, b1 - bs);
-            // phi of the b chunk: the four lanes of function bb = tid / 4
-            // compute its x, y and z factors at coordinate q = tid % 4, share
-            // them, and each writes the 16 points of z-plane q
+        for (int bs = b0; bs < b1; bs += kBc) {
+            const int nb = min(kBc, b1 - bs);
+            // phi of the b chunk: the eight lanes of function bb = tid / 8
+            // compute its x, y and z factors at coordinate q = tid % 4 (the
+            // two halves alike), share them, and lane (q, half) writes the 8
+            // points of z-plane q with y = 2 half, 2 half + 1
             {
-                const int bb = tid >> 2, q = tid & 3;
+                const int bb = tid >> 3, q = tid & 3, half = (tid >> 2) & 1;
                 double fxq = 0.0, fyq = 0.0, fzq = 0.0, nrm = 0.0;
                 if (bb < nb) {
                     const int b = a.beta_idx[bs + bb];
@@ -62,25 +65,25 @@ __global__ void __launch_bounds__(256) density_kernel(GridArgs a) {
                     fyq = axis_factor(e, R, a.oy + a.h * (4 * ccy + q) - a.cy[b]);
                     fzq = axis_factor(e, R, a.oz + a.h * (4 * ccz + q) - a.cz[b]);
                 }
-                const int base = (tid & 63) & ~3;
-                double fxv[4], fyv[4];
+                const int base = (tid & 63) & ~7;
+                double fxv[4], fyv[2];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    fxv[u] = __shfl(fxq, base + u, 64);
-                    fyv[u] = __shfl(fyq, base + u, 64);
-                }
+                for (int u = 0; u < 4; ++u) fxv[u] = __shfl(fxq, base + u, 64);
+#pragma unroll
+                for (int v = 0; v < 2; ++v) fyv[v] = __shfl(fyq, base + 2 * half + v, 64);
                 const double s = nrm * fzq;
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
+                for (int v = 0; v < 2; ++v)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) phb[bb][u + 4 * v + 16 * q] = s * fyv[v] * fxv[u];
+                    for (int u = 0; u < 4; ++u) phb[bb][u + 4 * (2 * half + v) + 16 * q] = s * fyv[v] * fxv[u];
             }
             // P block: lane k = b of the chunk (rows of one P column are
-            // close together), wave w takes a-entries w, w + 4, ...
+            // close together), thread group w = tid / 32 takes a-entries
+            // w, w + 8, ...
             {
-                const int k = tid & 63, w = tid >> 6;
+                const int k = tid & (kBc - 1), w = tid >> 5;
                 const long long brow = k < nb ? a.beta_idx[bs + k] : 0;
-                for (int aa = w; aa < 64; aa += 4) {
+                for (int aa = w; aa < 64; aa += 8) {
                     double v = 0.0;
                     if (k < nb && aa < na) v = a.P[(long long)a.alpha_col[as + aa] * a.ldp + brow];
                     pb[k][aa] = v;
