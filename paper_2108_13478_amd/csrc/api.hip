@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <array>
+#include <thread>
 #include <vector>
 
 #include "../../include/dm.h"
@@ -1383,14 +1384,32 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
             continue;
         box[b] = {xl / 4, xh / 4, yl / 4, yh / 4, zl / 4, zh / 4};
         reach[b] = 1;
-        for (int cz = zl / 4; cz <= zh / 4; ++cz)
-            for (int cy = yl / 4; cy <= yh / 4; ++cy)
-                for (int cx = xl / 4; cx <= xh / 4; ++cx) {
-                    const long long cell = cx + (long long)ncx * (cy + (long long)ncy * cz);
-                    ++bcount[cell + 1];
-                    if (colpos[b] >= 0) ++acount[cell + 1];
-                }
     }
+    // count and fill per slab of cell planes on host threads; every thread
+    // walks the functions in ascending order, so each cell lists them in
+    // ascending order whatever the number of threads
+    const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto slabs = [&](auto&& body) {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nthr; ++t) {
+            const int z0 = (int)((long long)ncz * t / nthr), z1 = (int)((long long)ncz * (t + 1) / nthr);
+            if (z0 < z1) th.emplace_back(body, z0, z1);
+        }
+        for (auto& x : th) x.join();
+    };
+    slabs([&](int z0, int z1) {
+        for (long long b = 0; b < K; ++b) {
+            if (!reach[b]) continue;
+            const auto& bx = box[b];
+            for (int cz = std::max(bx[4], z0); cz <= std::min(bx[5], z1 - 1); ++cz)
+                for (int cy = bx[2]; cy <= bx[3]; ++cy)
+                    for (int cx = bx[0]; cx <= bx[1]; ++cx) {
+                        const long long cell = cx + (long long)ncx * (cy + (long long)ncy * cz);
+                        ++bcount[cell + 1];
+                        if (colpos[b] >= 0) ++acount[cell + 1];
+                    }
+        }
+    });
     for (long long i = 0; i < ncell; ++i) {
         bcount[i + 1] += bcount[i];
         acount[i + 1] += acount[i];
@@ -1398,20 +1417,22 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
     std::vector<int> bidx((size_t)bcount[ncell]), aidx((size_t)acount[ncell]), acol((size_t)acount[ncell]);
     {
         std::vector<int> bfill(bcount.begin(), bcount.end() - 1), afill(acount.begin(), acount.end() - 1);
-        for (long long b = 0; b < K; ++b) {
-            if (!reach[b]) continue;
-            const auto& bx = box[b];
-            for (int cz = bx[4]; cz <= bx[5]; ++cz)
-                for (int cy = bx[2]; cy <= bx[3]; ++cy)
-                    for (int cx = bx[0]; cx <= bx[1]; ++cx) {
-                        const long long cell = cx + (long long)ncx * (cy + (long long)ncy * cz);
-                        bidx[bfill[cell]++] = (int)b;
-                        if (colpos[b] >= 0) {
-                            aidx[afill[cell]] = (int)b;
-                            acol[afill[cell]++] = colpos[b];
+        slabs([&](int z0, int z1) {
+            for (long long b = 0; b < K; ++b) {
+                if (!reach[b]) continue;
+                const auto& bx = box[b];
+                for (int cz = std::max(bx[4], z0); cz <= std::min(bx[5], z1 - 1); ++cz)
+                    for (int cy = bx[2]; cy <= bx[3]; ++cy)
+                        for (int cx = bx[0]; cx <= bx[1]; ++cx) {
+                            const long long cell = cx + (long long)ncx * (cy + (long long)ncy * cz);
+                            bidx[bfill[cell]++] = (int)b;
+                            if (colpos[b] >= 0) {
+                                aidx[afill[cell]] = (int)b;
+                                acol[afill[cell]++] = colpos[b];
+                            }
                         }
-                    }
-        }
+            }
+        });
     }
     hipStream_t s = c->stream;
     DevBuf<double> dfx, dfy, dfz, dfe, dfn, dfr, dP, dn;
