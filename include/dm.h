@@ -15,7 +15,8 @@
  *
  * Conventions for every entry point:
  *  - Return value: a dm_status; DM_OK on success.  No C++ exception crosses
- *    the ABI.  dm_last_error() gives a message for the last failure.
+ *    the ABI: one raised inside a call (a host allocation failure) returns
+ *    DM_E_OOM.  dm_last_error() gives a message for the last failure.
  *  - After DM_E_HIP the context is poisoned: every later call except
  *    dm_last_error and dm_destroy returns DM_E_STATE.
  *  - Pointers marked "host or device" may point to host memory or to device
@@ -44,7 +45,7 @@ typedef enum {
     DM_E_ARG = -1,     /* invalid argument (null pointer, size, range, NaN) */
     DM_E_STATE = -2,   /* call out of order, or context poisoned */
     DM_E_HIP = -3,     /* HIP runtime error; context poisoned */
-    DM_E_OOM = -4,     /* device allocation failed */
+    DM_E_OOM = -4,     /* device or host allocation failed */
     DM_E_NOTSPD = -5,  /* overlap matrix not positive definite (Cholesky) */
     DM_E_BOUNDS = -6,  /* recursion diverged: spectral bounds do not enclose */
     DM_E_NOCONV = -7   /* iteration did not reach its tolerance */

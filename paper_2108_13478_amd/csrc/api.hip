@@ -180,6 +180,13 @@ struct MlpState {
 
 namespace {
 
+// A C++ exception (host allocation failure, no thread) caught at the ABI:
+// no exception crosses it.
+dm_status host_exception(dm_ctx* c) {
+    if (c) c->err = "host allocation failed (C++ exception)";
+    return DM_E_OOM;
+}
+
 dm_status set_err(dm_ctx* c, dm_status st, const std::string& msg) {
     c->err = msg;
     return st;
@@ -740,7 +747,7 @@ void dm_default_options(dm_options* opt) {
     opt->seed = 12345;
 }
 
-dm_status dm_init(dm_ctx** out, const dm_options* opt) {
+dm_status dm_init(dm_ctx** out, const dm_options* opt) try {
     if (!out) {
         g_init_error = "dm_init: out is NULL";
         return DM_E_ARG;
@@ -793,6 +800,9 @@ dm_status dm_init(dm_ctx** out, const dm_options* opt) {
     }
     *out = c;
     return DM_OK;
+} catch (...) {
+    g_init_error = "dm_init: host exception";
+    return DM_E_OOM;
 }
 
 void dm_destroy(dm_ctx* c) {
@@ -820,7 +830,7 @@ const char* dm_last_error(const dm_ctx* c) {
 
 dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const int* F_col,
                       const double* F_val, const long long* S_rowptr, const int* S_col,
-                      const double* S_val, int atom_block) {
+                      const double* S_val, int atom_block) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -839,10 +849,12 @@ dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const i
     if (st != DM_OK) return st;
     c->have_fock = true;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_set_fock_orthonormal(dm_ctx* c, long long K, const long long* F_rowptr, const int* F_col,
-                                  const double* F_val) {
+                                  const double* F_val) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -863,9 +875,11 @@ dm_status dm_set_fock_orthonormal(dm_ctx* c, long long K, const long long* F_row
     if (st != DM_OK) return st;
     c->have_fock = true;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_get_bounds(dm_ctx* c, double* emin, double* emax) {
+dm_status dm_get_bounds(dm_ctx* c, double* emin, double* emax) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -873,9 +887,11 @@ dm_status dm_get_bounds(dm_ctx* c, double* emin, double* emax) {
     if (emin) *emin = c->op.emin;
     if (emax) *emax = c->op.emax;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_set_bounds(dm_ctx* c, double emin, double emax) {
+dm_status dm_set_bounds(dm_ctx* c, double emin, double emax) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -886,9 +902,11 @@ dm_status dm_set_bounds(dm_ctx* c, double emin, double emax) {
     c->op.emax = emax;
     reset_moments(c);
     return normalize(c, c->op);
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_set_operator_form(dm_ctx* c, int form) {
+dm_status dm_set_operator_form(dm_ctx* c, int form) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -896,10 +914,12 @@ dm_status dm_set_operator_form(dm_ctx* c, int form) {
         return set_err(c, DM_E_ARG, "unknown operator form");
     c->form = form;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_set_factored_options(dm_ctx* c, double cg_tol, int cg_max_iter, double fsai_drop,
-                                  int fsai_max_per_row) {
+                                  int fsai_max_per_row) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -911,9 +931,11 @@ dm_status dm_set_factored_options(dm_ctx* c, double cg_tol, int cg_max_iter, dou
     c->fsai_drop = fsai_drop;
     c->fsai_cap = fsai_max_per_row;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_solve_overlap(dm_ctx* c, const double* B, long long nrhs, double* X) {
+dm_status dm_solve_overlap(dm_ctx* c, const double* B, long long nrhs, double* X) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -927,9 +949,11 @@ dm_status dm_solve_overlap(dm_ctx* c, const double* B, long long nrhs, double* X
     if (e != hipSuccess) return fail_hip(c, e, "solve with S");
     if (!conv) return set_err(c, DM_E_NOCONV, "the conjugate-gradient solve with S did not converge within the iteration limit");
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_get_preconditioner(dm_ctx* c, long long* nnz, long long* rowptr, int* col, double* val) {
+dm_status dm_get_preconditioner(dm_ctx* c, long long* nnz, long long* rowptr, int* col, double* val) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -937,9 +961,11 @@ dm_status dm_get_preconditioner(dm_ctx* c, long long* nnz, long long* rowptr, in
     if (nnz) *nnz = fact_precond_nnz(c->op.fact);
     HIPTRY(c, fact_precond_copy(c->op.fact, rowptr, col, val, c->stream));
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_cg_stats(dm_ctx* c, long long* solves, long long* iterations, int* max_iterations) {
+dm_status dm_cg_stats(dm_ctx* c, long long* solves, long long* iterations, int* max_iterations) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -952,9 +978,11 @@ dm_status dm_cg_stats(dm_ctx* c, long long* solves, long long* iterations, int* 
     if (iterations) *iterations = it;
     if (max_iterations) *max_iterations = mx;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_cg_timing(dm_ctx* c, int enable, long long* launches, double* ms) {
+dm_status dm_cg_timing(dm_ctx* c, int enable, long long* launches, double* ms) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -966,9 +994,11 @@ dm_status dm_cg_timing(dm_ctx* c, int enable, long long* launches, double* ms) {
     if (launches) *launches = n;
     if (ms) *ms = t;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
+dm_status dm_get_operator(dm_ctx* c, int which, double* out) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1000,9 +1030,11 @@ dm_status dm_get_operator(dm_ctx* c, int which, double* out) {
     }
     HIPTRY(c, hipStreamSynchronize(s));
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_set_precision(dm_ctx* c, int precision) {
+dm_status dm_set_precision(dm_ctx* c, int precision) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1013,6 +1045,8 @@ dm_status dm_set_precision(dm_ctx* c, int precision) {
     reset_moments(c);
     if (!c->have_fock) return DM_OK;
     return normalize(c, c->op);
+} catch (...) {
+    return host_exception(c);
 }
 
 // End of a pass: the moments accumulated so far must be finite and bounded.
@@ -1219,15 +1253,17 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
 }
 
 dm_status dm_chebyshev_block(dm_ctx* c, const long long* cols, long long ncols, int order,
-                             double mu, double beta, double* P_out) {
+                             double mu, double beta, double* P_out) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     return run_pass(c, cols, ncols, order, 1, &mu, &beta, &P_out);
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_chebyshev_block_multi(dm_ctx* c, const long long* cols, long long ncols, int order,
-                                   int n_sets, const double* mu, const double* beta, double* const* P_out) {
+                                   int n_sets, const double* mu, const double* beta, double* const* P_out) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1237,6 +1273,8 @@ dm_status dm_chebyshev_block_multi(dm_ctx* c, const long long* cols, long long n
     std::copy(mu, mu + n_sets, hmu.begin());
     std::copy(beta, beta + n_sets, hbeta.begin());
     return run_pass(c, cols, ncols, order, n_sets, hmu.data(), hbeta.data(), P_out);
+} catch (...) {
+    return host_exception(c);
 }
 
 static dm_status eval_trace(dm_ctx* c, double beta, double target, double tol, double mu_in,
@@ -1257,7 +1295,7 @@ static dm_status eval_trace(dm_ctx* c, double beta, double target, double tol, d
     return DM_OK;
 }
 
-dm_status dm_trace(dm_ctx* c, double mu, double beta, double* tr_PS, double* e_band) {
+dm_status dm_trace(dm_ctx* c, double mu, double beta, double* tr_PS, double* e_band) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1268,9 +1306,11 @@ dm_status dm_trace(dm_ctx* c, double mu, double beta, double* tr_PS, double* e_b
     if (tr_PS) *tr_PS = out[1];
     if (e_band) *e_band = c->opt.spin * out[2];
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_solve_mu(dm_ctx* c, double n_e, double beta, double tol, double* mu) {
+dm_status dm_solve_mu(dm_ctx* c, double n_e, double beta, double tol, double* mu) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1282,9 +1322,11 @@ dm_status dm_solve_mu(dm_ctx* c, double n_e, double beta, double tol, double* mu
     if (out[3] == 0.0)
         return set_err(c, DM_E_NOCONV, "bisection bracket collapsed before reaching the tolerance");
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_dos(dm_ctx* c, int kind, int n, const double* energies, double sigma, double* dos) {
+dm_status dm_dos(dm_ctx* c, int kind, int n, const double* energies, double sigma, double* dos) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1324,11 +1366,13 @@ dm_status dm_dos(dm_ctx* c, int kind, int n, const double* energies, double sigm
 #undef DOS
     rel();
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, const double* exponents,
                              const double* origin, double h, const int* dims, double eta, const long long* cols,
-                             long long ncols, const double* P_cols, double* n_out) {
+                             long long ncols, const double* P_cols, double* n_out) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1391,9 +1435,20 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
     const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     auto slabs = [&](auto&& body) {
         std::vector<std::thread> th;
-        for (int t = 0; t < nthr; ++t) {
+        th.reserve((size_t)nthr);
+        int t = 0;
+        for (; t < nthr; ++t) {
             const int z0 = (int)((long long)ncz * t / nthr), z1 = (int)((long long)ncz * (t + 1) / nthr);
-            if (z0 < z1) th.emplace_back(body, z0, z1);
+            if (z0 >= z1) continue;
+            try {
+                th.emplace_back(body, z0, z1);
+            } catch (...) {  // no thread available: this slab and the rest on the calling thread
+                break;
+            }
+        }
+        for (; t < nthr; ++t) {
+            const int z0 = (int)((long long)ncz * t / nthr), z1 = (int)((long long)ncz * (t + 1) / nthr);
+            if (z0 < z1) body(z0, z1);
         }
         for (auto& x : th) x.join();
     };
@@ -1489,9 +1544,11 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
 #undef GR
     rel();
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_moments(dm_ctx* c, double* m, int n, long long* ncols_done) {
+dm_status dm_moments(dm_ctx* c, double* m, int n, long long* ncols_done) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1506,16 +1563,20 @@ dm_status dm_moments(dm_ctx* c, double* m, int n, long long* ncols_done) {
         }
     }
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_reset_moments(dm_ctx* c) {
+dm_status dm_reset_moments(dm_ctx* c) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     return reset_moments(c);
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_set_pass_shape(dm_ctx* c, int width, int cfg) {
+dm_status dm_set_pass_shape(dm_ctx* c, int width, int cfg) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1527,6 +1588,8 @@ dm_status dm_set_pass_shape(dm_ctx* c, int width, int cfg) {
     c->tuned_width = width;
     c->tuned_cfg = cfg;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 int dm_num_tile_shapes(void) { return cheb_num_tile_configs(); }
@@ -1540,7 +1603,7 @@ dm_status dm_tile_shape(int cfg, int* rows, int* cols, int* split) {
 }
 
 dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int* ntable,
-                      int* best_width, int* best_cfg) {
+                      int* best_width, int* best_cfg) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1661,13 +1724,15 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
         *ntable = (int)cands.size();
     }
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 namespace {
 dm_status stoch_moments_op(dm_ctx* c, Op& op, int n_mom, int n_vec, const double* xi, double* m_out);
 }
 
-dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, double* m_out) {
+dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, double* m_out) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1697,9 +1762,11 @@ dm_status dm_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* xi, do
         return DM_OK;
     }
     return stoch_moments_op(c, c->op, n_mom, n_vec, xi, m_out);
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_batch_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* const* xi, double* m_out) {
+dm_status dm_batch_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* const* xi, double* m_out) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1712,6 +1779,8 @@ dm_status dm_batch_stoch_moments(dm_ctx* c, int n_mom, int n_vec, const double* 
         if (st != DM_OK) return st;
     }
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 }  // extern "C"
@@ -1939,7 +2008,7 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
 
 extern "C" {
 
-dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) {
+dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -1980,10 +2049,12 @@ dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) {
         HIPTRY(c, hipMemcpy(b.cols.p, ar.data(), (size_t)K * 8, hipMemcpyHostToDevice));
     }
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, double tol,
-                       double* mu_out, double* const* P_out, int flags) {
+                       double* mu_out, double* const* P_out, int flags) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2051,9 +2122,11 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
     if (flag) return set_err(c, DM_E_BOUNDS, "batch recursion diverged");
     if (!conv) return set_err(c, DM_E_NOCONV, "a cluster's mu bisection stopped before the tolerance");
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_batch_get_bounds(dm_ctx* c, int i, double* emin, double* emax) {
+dm_status dm_batch_get_bounds(dm_ctx* c, int i, double* emin, double* emax) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2061,9 +2134,11 @@ dm_status dm_batch_get_bounds(dm_ctx* c, int i, double* emin, double* emax) {
     if (emin) *emin = c->batch[i].emin;
     if (emax) *emax = c->batch[i].emax;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, int* best_cfg) {
+dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, int* best_cfg) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2113,6 +2188,8 @@ dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, in
         *ntable = (int)res.size();
     }
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 }  // extern "C"
@@ -2188,7 +2265,7 @@ dm_status mlp_ready(dm_ctx* c) {
 
 extern "C" {
 
-dm_status dm_mlp_init(dm_ctx* c, int n_layers, const int* sizes, unsigned long long seed) {
+dm_status dm_mlp_init(dm_ctx* c, int n_layers, const int* sizes, unsigned long long seed) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2218,18 +2295,22 @@ dm_status dm_mlp_init(dm_ctx* c, int n_layers, const int* sizes, unsigned long l
     HIPTRY(c, hipMemsetAsync(M.v.p, 0, (size_t)off * 4, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_mlp_num_params(dm_ctx* c, long long* n) {
+dm_status dm_mlp_num_params(dm_ctx* c, long long* n) try {
     if (!c || !n) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if ((st = mlp_ready(c)) != DM_OK) return st;
     *n = c->mlp->n_params;
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_mlp_get_params(dm_ctx* c, float* out) {
+dm_status dm_mlp_get_params(dm_ctx* c, float* out) try {
     if (!c || !out) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2237,9 +2318,11 @@ dm_status dm_mlp_get_params(dm_ctx* c, float* out) {
     HIPTRY(c, hipMemcpyAsync(out, c->mlp->params.p, (size_t)c->mlp->n_params * 4, hipMemcpyDefault, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_mlp_set_params(dm_ctx* c, const float* in) {
+dm_status dm_mlp_set_params(dm_ctx* c, const float* in) try {
     if (!c || !in) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2251,9 +2334,11 @@ dm_status dm_mlp_set_params(dm_ctx* c, const float* in) {
     HIPTRY(c, hipMemsetAsync(c->mlp->v.p, 0, (size_t)c->mlp->n_params * 4, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
-dm_status dm_mlp_forward(dm_ctx* c, const float* X, int batch, float* Y) {
+dm_status dm_mlp_forward(dm_ctx* c, const float* X, int batch, float* Y) try {
     if (!c || !X || !Y || batch < 1) return c ? set_err(c, DM_E_ARG, "bad forward arguments") : DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2264,10 +2349,12 @@ dm_status dm_mlp_forward(dm_ctx* c, const float* X, int batch, float* Y) {
     HIPTRY(c, hipMemcpyAsync(Y, M.acts.p + M.act_off[L], (size_t)batch * M.sizes[L] * 4, hipMemcpyDefault, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_mlp_gradients(dm_ctx* c, const float* X, const float* T, int batch, float* loss,
-                           float* grads) {
+                           float* grads) try {
     if (!c || !X || !T || batch < 1) return c ? set_err(c, DM_E_ARG, "bad gradient arguments") : DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2278,10 +2365,12 @@ dm_status dm_mlp_gradients(dm_ctx* c, const float* X, const float* T, int batch,
         HIPTRY(c, hipMemcpyAsync(grads, c->mlp->grads.p, (size_t)c->mlp->n_params * 4, hipMemcpyDefault, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_mlp_train_step(dm_ctx* c, const float* X, const float* T, int batch, float lr,
-                            float* loss) {
+                            float* loss) try {
     if (!c || !X || !T || batch < 1 || !(lr > 0)) return c ? set_err(c, DM_E_ARG, "bad training arguments") : DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2295,10 +2384,12 @@ dm_status dm_mlp_train_step(dm_ctx* c, const float* X, const float* T, int batch
         HIPTRY(c, hipStreamSynchronize(c->stream));
     }
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_mlp_features(dm_ctx* c, const double* m_stoch, int n_mom, double emin, double emax,
-                          double beta, double n_e, long long K, float* x) {
+                          double beta, double n_e, long long K, float* x) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2317,6 +2408,8 @@ dm_status dm_mlp_features(dm_ctx* c, const double* m_stoch, int n_mom, double em
     xd.release();
     if (e != hipSuccess) return fail_hip(c, e, "features");
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 }  // extern "C"
@@ -2324,7 +2417,7 @@ dm_status dm_mlp_features(dm_ctx* c, const double* m_stoch, int n_mom, double em
 extern "C" {
 
 dm_status dm_cheb_order(dm_ctx* c, double emin, double emax, double mu, double beta, double tol,
-                        int max_order, int* order) {
+                        int max_order, int* order) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2348,10 +2441,12 @@ dm_status dm_cheb_order(dm_ctx* c, double emin, double emax, double mu, double b
     o.release();
     if (e != hipSuccess) return fail_hip(c, e, "order estimate");
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 dm_status dm_mlp_predict(dm_ctx* c, const double* m_stoch, int n_mom, double beta, double n_e,
-                         int max_order, double* mu, int* order) {
+                         int max_order, double* mu, int* order) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
@@ -2386,6 +2481,8 @@ dm_status dm_mlp_predict(dm_ctx* c, const double* m_stoch, int n_mom, double bet
     const double N = std::pow(2.0, 10.0 * ((double)y[1] + 1.0));
     *order = (int)std::lround(std::min<double>(std::max<double>(N, 16.0), (double)max_order));
     return DM_OK;
+} catch (...) {
+    return host_exception(c);
 }
 
 }  // extern "C"
