@@ -267,9 +267,12 @@ enum { kSumBB = 0, kSumPQ = 1, kSumRR = 2, kSumRZ = 3 };
 // Column totals of the producer's parts (x < nx, fixed order: 16 strided
 // slices, then the slices in order) and the scalar step of the iteration,
 // one workgroup per 64-column group:
-//   kSumBB: bb = B . B, done = (bb == 0), beta = alpha = 0, active count;
+//   kSumBB: bb = B . B, done = (bb == 0 or not finite), beta = alpha = 0,
+//           active count;
 //   kSumPQ: alpha = rz / (Pd . Q) (0 for converged columns);
-//   kSumRR: done once R . R <= tol^2 bb, active count, iteration count;
+//   kSumRR: done once R . R <= tol^2 bb (or R . R is not finite: a diverged
+//           recursion stops its solves at once, its moments report it),
+//           active count, iteration count;
 //   kSumRZ: beta = rz_new / rz (0 on the first iteration), rz = rz_new.
 template <int MODE>
 __global__ void __launch_bounds__(1024) cg_colsum_kernel(CgArgs a) {
@@ -283,7 +286,7 @@ __global__ void __launch_bounds__(1024) cg_colsum_kernel(CgArgs a) {
     const double tot = wg_column_sum(s, red);
     if (w != 0) return;
     if (MODE == kSumBB) {
-        const bool dn = !(tot > 0.0);
+        const bool dn = !(tot > 0.0) || !isfinite(tot);
         a.bb[c] = tot;
         a.done[c] = dn ? 1 : 0;
         a.beta[c] = 0.0;
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(1024) cg_colsum_kernel(CgArgs a) {
         a.alpha[c] = al;
     } else if (MODE == kSumRR) {
         bool dn = a.done[c] != 0;
-        if (!dn && tot <= a.tol2 * a.bb[c]) {
+        if (!dn && (tot <= a.tol2 * a.bb[c] || !isfinite(tot))) {
             dn = true;
             a.done[c] = 1;
         }

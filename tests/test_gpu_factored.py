@@ -237,3 +237,30 @@ def test_factored_stochastic_moments(c1):
     say(f"case: factored stochastic moments K={c.K}, 8 probes, {n_mom} moments: max|dm| = {err:.2e}")
     assert ms[0] == c.K
     assert err < 1e-8 * c.K
+
+
+def test_factored_error_paths():
+    """The factored form rejects an indefinite overlap (its FSAI row factor
+    fails), a NaN in F, and an interval that misses most of the spectrum."""
+    say("case: factored error paths")
+    ctx = dmlib.Context()
+    ctx.dm_set_operator_form(dmlib.DM_FORM_FACTORED)
+    rp = np.array([0, 2, 4], dtype=np.int64)
+    ci = np.array([0, 1, 0, 1], dtype=np.int32)
+    S = np.array([1.0, 2.0, 2.0, 1.0])  # positive diagonal, eigenvalue -1
+    F = np.array([0.5, 0.1, 0.1, 0.3])
+    with pytest.raises(dmlib.DMError) as ei:
+        ctx.dm_set_fock(2, rp, ci, F, rp, ci, S)
+    assert ei.value.status == dmlib.DM_E_NOTSPD
+    c = make_cluster(8, seed=1, geometry="cube")
+    bad = c.F_val.copy()
+    bad[3] = np.nan
+    with pytest.raises(dmlib.DMError) as ei:
+        ctx.dm_set_fock(c.K, c.F_rowptr, c.F_col, bad, c.S_rowptr, c.S_col, c.S_val)
+    assert ei.value.status == dmlib.DM_E_ARG
+    ctx.set_cluster(c)
+    lo, hi = ctx.dm_get_bounds()
+    ctx.dm_set_bounds(lo + 0.45 * (hi - lo), hi - 0.45 * (hi - lo))
+    with pytest.raises(dmlib.DMError) as ei:
+        ctx.dm_chebyshev_block(np.arange(c.K, dtype=np.int64), 400, 0.0, 1.0, None)
+    assert ei.value.status == dmlib.DM_E_BOUNDS
