@@ -195,8 +195,10 @@ dm_status dm_get_preconditioner(dm_ctx* ctx, long long* nnz, long long* rowptr, 
 dm_status dm_cg_stats(dm_ctx* ctx, long long* solves, long long* iterations, int* max_iterations);
 
 /* Timing of the factored form's dominant kernel, the product with S inside
- * every conjugate-gradient iteration: with enable = 1 each such launch is
- * bracketed by HIP events on the context's stream (a small cost per launch).
+ * every conjugate-gradient iteration of a block solve (single-vector solves,
+ * as in the Lanczos bounds, are not timed): with enable = 1 each such launch
+ * is bracketed by HIP events on the context's stream (a small cost per
+ * launch).
  * Each call returns, and clears, the number of timed launches and their
  * summed duration in ms (host pointers, may be NULL) of the iterations that
  * ran since the previous call, then sets the switch to `enable`.

@@ -274,6 +274,42 @@ enum { kSumBB = 0, kSumPQ = 1, kSumRR = 2, kSumRZ = 3 };
 //           recursion stops its solves at once, its moments report it),
 //           active count, iteration count;
 //   kSumRZ: beta = rz_new / rz (0 on the first iteration), rz = rz_new.
+// The scalar step of column c from its total; returns whether the column is
+// still iterating (meaningful for kSumBB and kSumRR).
+template <int MODE>
+__device__ inline bool cg_column_step(const CgArgs& a, int c, double tot) {
+    if (MODE == kSumBB) {
+        const bool dn = !(tot > 0.0) || !isfinite(tot);
+        a.bb[c] = tot;
+        a.done[c] = dn ? 1 : 0;
+        a.beta[c] = 0.0;
+        a.alpha[c] = 0.0;
+        return !dn;
+    } else if (MODE == kSumPQ) {
+        double al = 0.0;
+        if (a.done[c] == 0) {
+            if (tot > 0.0)
+                al = a.rz[c] / tot;
+            else
+                a.done[c] = 1;  // zero search direction: the residual is already zero
+        }
+        a.alpha[c] = al;
+        return false;
+    } else if (MODE == kSumRR) {
+        bool dn = a.done[c] != 0;
+        if (!dn && (tot <= a.tol2 * a.bb[c] || !isfinite(tot))) {
+            dn = true;
+            a.done[c] = 1;
+        }
+        return !dn;
+    } else {
+        const bool dn = a.done[c] != 0;
+        a.beta[c] = (a.first || dn || !(a.rz[c] > 0.0)) ? 0.0 : tot / a.rz[c];
+        a.rz[c] = tot;
+        return false;
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(1024) cg_colsum_kernel(CgArgs a) {
     __shared__ double red[kWv][64];
@@ -285,41 +321,144 @@ __global__ void __launch_bounds__(1024) cg_colsum_kernel(CgArgs a) {
     for (int x = w; x < a.t.nx; x += kWv) s += a.part[(size_t)x * a.W + c];
     const double tot = wg_column_sum(s, red);
     if (w != 0) return;
-    if (MODE == kSumBB) {
-        const bool dn = !(tot > 0.0) || !isfinite(tot);
-        a.bb[c] = tot;
-        a.done[c] = dn ? 1 : 0;
-        a.beta[c] = 0.0;
-        a.alpha[c] = 0.0;
-        const unsigned long long live = __ballot(!dn);
+    const bool live = cg_column_step<MODE>(a, c, tot);
+    if (MODE == kSumBB || MODE == kSumRR) {
+        const unsigned long long lv = __ballot(live);
         if (lane == 0) {
-            a.active[y] = __popcll(live);
-            a.iters[y] = 0;
-        }
-    } else if (MODE == kSumPQ) {
-        double al = 0.0;
-        if (a.done[c] == 0) {
-            if (tot > 0.0)
-                al = a.rz[c] / tot;
+            a.active[y] = __popcll(lv);
+            if (MODE == kSumBB)
+                a.iters[y] = 0;
             else
-                a.done[c] = 1;  // zero search direction: the residual is already zero
+                a.iters[y] += 1;
         }
-        a.alpha[c] = al;
+    }
+}
+
+// ------------------------------------------------------ single-vector solves
+// The Lanczos bounds apply H to one vector at a time, where a block kernel
+// would leave 63 of its 64 lanes idle.  One vector (v[i], i < Kr) has its
+// own kernels: a wave per row group with the lanes over the group's listed
+// columns (one gathered value per entry), the four row sums reduced by
+// butterfly shuffles; one partial dot product per workgroup, added in index
+// order by a one-workgroup kernel that takes the same scalar step as the
+// block's column sums.  Results do not depend on timing.
+constexpr int kVecWv = 4;  // waves per workgroup of the vector product
+
+// Sum of v over a 256-thread workgroup, valid in thread 0 (butterfly within
+// each wave, then the four waves in order).
+__device__ inline double wg256_sum(double v, double* red4) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
+// y = A x for one vector (kPlain); kPq: Pd = Z + beta Pd, Q = A Z + beta Q,
+// part = Pd . Q; kRz: Z = A T, part = R . Z (x and y as for the block).
+template <int MODE>
+__global__ void __launch_bounds__(256) rg_spmv_kernel(RgView A, const double* __restrict__ x,
+                                                      double* __restrict__ y, CgArgs a) {
+    __shared__ double red[kVecWv];
+    if (a.active && a.active[0] == 0) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = blockIdx.x * kVecWv + wv;
+    const long long p0 = A.ptr[g], p1 = A.ptr[g + 1];
+    double acc[kRG];
+#pragma unroll
+    for (int r = 0; r < kRG; ++r) acc[r] = 0.0;
+    for (long long p = p0 + lane; p < p1; p += 64) {
+        const double xv = x[A.col[p]];
+        const double2* v = reinterpret_cast<const double2*>(A.val + p * kRG);
+#pragma unroll
+        for (int h = 0; h < kRG / 2; ++h) {
+            const double2 w = v[h];
+            acc[2 * h] += w.x * xv;
+            acc[2 * h + 1] += w.y * xv;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kRG; ++r)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off, 64);
+    // every lane holds the row sums; lane r < kRG handles row kRG g + r
+    double sr = acc[0];
+#pragma unroll
+    for (int r = 1; r < kRG; ++r) sr = lane == r ? acc[r] : sr;
+    const int i = g * kRG + lane;
+    double d = 0.0;
+    if (lane < kRG) {
+        if (MODE == kPlain) {
+            y[i] = sr;
+        } else if (MODE == kPq) {
+            const double b = a.beta[0];
+            const double pd = b != 0.0 ? x[i] + b * a.Pd[i] : x[i];
+            const double qv = b != 0.0 ? sr + b * a.Q[i] : sr;
+            a.Pd[i] = pd;
+            a.Q[i] = qv;
+            d = pd * qv;
+        } else {
+            y[i] = sr;
+            d = a.R[i] * sr;
+        }
+    }
+    if (MODE == kPlain) return;
+    double dg = __shfl(d, 0, 64);
+#pragma unroll
+    for (int r = 1; r < kRG; ++r) dg += __shfl(d, r, 64);
+    if (lane == 0) red[wv] = dg;
+    __syncthreads();
+    if (threadIdx.x == 0) a.part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// X = 0, R = B, part = B . B over v[0..n).
+__global__ void __launch_bounds__(256) vec_init_kernel(int n, CgArgs a) {
+    __shared__ double red[4];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double d = 0.0;
+    if (i < n) {
+        const double b = a.B[i];
+        a.X[i] = 0.0;
+        a.R[i] = b;
+        d = b * b;
+    }
+    const double s = wg256_sum(d, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+// X += alpha Pd, R -= alpha Q, part = R . R.
+__global__ void __launch_bounds__(256) vec_update_kernel(int n, CgArgs a) {
+    __shared__ double red[4];
+    if (a.active[0] == 0) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double d = 0.0;
+    if (i < n) {
+        const double al = a.alpha[0];
+        a.X[i] += al * a.Pd[i];
+        const double rv = a.R[i] - al * a.Q[i];
+        a.R[i] = rv;
+        d = rv * rv;
+    }
+    const double s = wg256_sum(d, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+// Total of part[0..nparts) in a fixed order and the scalar step.
+template <int MODE>
+__global__ void __launch_bounds__(256) vec_sum_kernel(int nparts, CgArgs a) {
+    __shared__ double red[4];
+    if (MODE != kSumBB && a.active[0] == 0) return;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += 256) s += a.part[k];
+    const double tot = wg256_sum(s, red);
+    if (threadIdx.x != 0) return;
+    const bool live = cg_column_step<MODE>(a, 0, tot);
+    if (MODE == kSumBB) {
+        a.active[0] = live ? 1 : 0;
+        a.iters[0] = 0;
     } else if (MODE == kSumRR) {
-        bool dn = a.done[c] != 0;
-        if (!dn && (tot <= a.tol2 * a.bb[c] || !isfinite(tot))) {
-            dn = true;
-            a.done[c] = 1;
-        }
-        const unsigned long long live = __ballot(!dn);
-        if (lane == 0) {
-            a.active[y] = __popcll(live);
-            a.iters[y] += 1;
-        }
-    } else {
-        const bool dn = a.done[c] != 0;
-        a.beta[c] = (a.first || dn || !(a.rz[c] > 0.0)) ? 0.0 : tot / a.rz[c];
-        a.rz[c] = tot;
+        a.active[0] = live ? 1 : 0;
+        a.iters[0] += 1;
     }
 }
 
@@ -755,24 +894,70 @@ CgArgs cg_args(FactOp* f, int W, double tol) {
     return a;
 }
 
-// X = S^-1 B on the block (width W <= f->W), B and X in the workspace.
-// *converged = 0 when some column needed more than max_iter iterations.
+// Launches of one CG solve: on a block of width W (a multiple of 64), or,
+// with W = 1, on one vector v[0..Kr) in the first Kr elements of the
+// workspace buffers.
+struct CgLaunch {
+    FactOp* f;
+    bool vec;
+    int ng;          // column groups (1 for a vector)
+    int nvp, nve;    // vector: partials of the products and of the element kernels
+    dim3 grid, gsum; // block: row-kernel grid, column-sum grid
+    hipStream_t s;
+    template <int MODE>
+    void spmm(const RgMat& A, const double* X, double* Y, const CgArgs& a, hipEvent_t t0 = nullptr,
+              hipEvent_t t1 = nullptr) const {
+        if (!vec) {
+            launch_spmm<MODE>(f, A, X, Y, a, s, t0, t1);
+            return;
+        }
+        auto k = rg_spmv_kernel<MODE>;
+        if (t0)
+            hipExtLaunchKernelGGL(k, dim3(nvp), dim3(256), 0, s, t0, t1, 0, A.view(), X, Y, a);
+        else
+            hipLaunchKernelGGL(k, dim3(nvp), dim3(256), 0, s, A.view(), X, Y, a);
+    }
+    template <int MODE>
+    void sum(const CgArgs& a) const {
+        if (vec)
+            hipLaunchKernelGGL(vec_sum_kernel<MODE>, dim3(1), dim3(256), 0, s,
+                               (MODE == kSumPQ || MODE == kSumRZ) ? nvp : nve, a);
+        else
+            hipLaunchKernelGGL(cg_colsum_kernel<MODE>, gsum, dim3(1024), 0, s, a);
+    }
+    void init(const CgArgs& a) const {
+        if (vec)
+            hipLaunchKernelGGL(vec_init_kernel, dim3(nve), dim3(256), 0, s, f->Kr, a);
+        else
+            hipLaunchKernelGGL(cg_init_kernel, grid, dim3(1024), 0, s, a);
+    }
+    void update(const CgArgs& a) const {
+        if (vec)
+            hipLaunchKernelGGL(vec_update_kernel, dim3(nve), dim3(256), 0, s, f->Kr, a);
+        else
+            hipLaunchKernelGGL(cg_update_kernel, grid, dim3(1024), 0, s, a);
+    }
+};
+
+// X = S^-1 B on the block (width W <= f->W) or on one vector (W = 1), B and
+// X in the workspace.  *converged = 0 when some column needed more than
+// max_iter iterations.
 hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, hipStream_t s) {
-    const int ng = W / 64;
+    const bool vec = W == 1;
+    const int ng = vec ? 1 : W / 64;
     max_iter = std::max(max_iter, 1);
     CgArgs a = cg_args(f, W, tol);
-    const dim3 grid = tile_grid(a.t), blk(1024);
-    const dim3 gsum(ng);
-    hipLaunchKernelGGL(cg_init_kernel, grid, blk, 0, s, a);
-    hipLaunchKernelGGL(cg_colsum_kernel<kSumBB>, gsum, blk, 0, s, a);
+    CgLaunch L{f, vec, ng, f->Kr / (kRG * kVecWv), (f->Kr + 255) / 256, vec ? dim3(1) : tile_grid(a.t), dim3(ng), s};
+    L.init(a);
+    L.sum<kSumBB>(a);
     FTRY(hipGetLastError());
     // Z = G^T (G R): preconditioned residual, rz = R . Z
     {
         CgArgs p = a;
         p.first = 1;
-        launch_spmm<kPlain>(f, f->G, a.R, a.T, p, s);
-        launch_spmm<kRz>(f, f->GT, a.T, a.Z, p, s);
-        hipLaunchKernelGGL(cg_colsum_kernel<kSumRZ>, gsum, blk, 0, s, p);
+        L.spmm<kPlain>(f->G, a.R, a.T, p);
+        L.spmm<kRz>(f->GT, a.T, a.Z, p);
+        L.sum<kSumRZ>(p);
         FTRY(hipGetLastError());
     }
     int it = 0, chunk = 0, nev = 0;  // nev: timing events used by this solve
@@ -799,15 +984,16 @@ hipError_t cg_solve(FactOp* f, int W, double tol, int max_iter, int* converged, 
         const int n_it = std::min(kChunk, max_iter - it);
         for (int k = 0; k < n_it; ++k) {
             hipEvent_t t0 = nullptr, t1 = nullptr;  // start and stop taken by the dispatch itself
-            if (f->timing && ((err = timed_event(&t0)) != hipSuccess || (err = timed_event(&t1)) != hipSuccess))
+            if (f->timing && !vec &&
+                ((err = timed_event(&t0)) != hipSuccess || (err = timed_event(&t1)) != hipSuccess))
                 break;
-            launch_spmm<kPq>(f, f->S, a.Z, a.Q, a, s, t0, t1);
-            hipLaunchKernelGGL(cg_colsum_kernel<kSumPQ>, gsum, blk, 0, s, a);
-            hipLaunchKernelGGL(cg_update_kernel, grid, blk, 0, s, a);
-            hipLaunchKernelGGL(cg_colsum_kernel<kSumRR>, gsum, blk, 0, s, a);
-            launch_spmm<kPlain>(f, f->G, a.R, a.T, a, s);
-            launch_spmm<kRz>(f, f->GT, a.T, a.Z, a, s);
-            hipLaunchKernelGGL(cg_colsum_kernel<kSumRZ>, gsum, blk, 0, s, a);
+            L.spmm<kPq>(f->S, a.Z, a.Q, a, t0, t1);
+            L.sum<kSumPQ>(a);
+            L.update(a);
+            L.sum<kSumRR>(a);
+            L.spmm<kPlain>(f->G, a.R, a.T, a);
+            L.spmm<kRz>(f->GT, a.T, a.Z, a);
+            L.sum<kSumRZ>(a);
         }
         if (err != hipSuccess) break;
         it += n_it;
@@ -988,6 +1174,17 @@ hipError_t fact_solve(FactOp* f, int n, const double* B, long long ldb, double* 
     const int K = f->K;
     for (int off = 0; off < n; off += wmax) {
         const int nc = std::min(wmax, n - off);
+        if (nc == 1) {
+            // one right-hand side: the single-vector kernels
+            FTRY(ensure_width(f, 64, 1, 1, s));
+            if (f->Kr > K) FTRY(fill_f64(f->B.p + K, 0.0, f->Kr - K, s));
+            FTRY(hipMemcpyAsync(f->B.p, B + (size_t)off * ldb, (size_t)K * 8, hipMemcpyDefault, s));
+            int conv = 1;
+            FTRY(cg_solve(f, 1, tol, max_iter, &conv, s));
+            if (!conv) *converged = 0;
+            FTRY(hipMemcpyAsync(X + (size_t)off * ldx, f->X.p, (size_t)K * 8, hipMemcpyDefault, s));
+            continue;
+        }
         const int W = (nc + 63) / 64 * 64;
         FTRY(ensure_width(f, W, 1, 1, s));
         // stage B through device memory when it lives on the host
@@ -1011,17 +1208,17 @@ hipError_t fact_solve(FactOp* f, int n, const double* B, long long ldb, double* 
 
 hipError_t fact_apply(FactOp* f, const double* x, double* y, double tol, int max_iter, int* converged,
                       hipStream_t s) {
-    const int K = f->K, W = 64;
-    FTRY(ensure_width(f, W, 1, 1, s));
-    hipLaunchKernelGGL(to_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, 1, x, (long long)K, W, f->U0.p);
-    CgArgs a = cg_args(f, W, tol);
+    const int K = f->K, Kr = f->Kr;
+    FTRY(ensure_width(f, 64, 1, 1, s));  // the vector lives in the first Kr elements of each buffer
+    if (Kr > K) FTRY(fill_f64(f->U0.p + K, 0.0, Kr - K, s));
+    FTRY(hipMemcpyAsync(f->U0.p, x, (size_t)K * 8, hipMemcpyDeviceToDevice, s));
+    CgArgs a = cg_args(f, 1, tol);
     a.active = nullptr;
-    launch_spmm<kPlain>(f, f->F, f->U0.p, f->B.p, a, s);
+    hipLaunchKernelGGL(rg_spmv_kernel<kPlain>, dim3(Kr / (kRG * kVecWv)), dim3(256), 0, s, f->F.view(),
+                       (const double*)f->U0.p, f->B.p, a);
     FTRY(hipGetLastError());
-    FTRY(cg_solve(f, W, tol, max_iter, converged, s));
-    hipLaunchKernelGGL(from_block_kernel, dim3(f->Kr / 32, W / 32), dim3(256), 0, s, K, 1, (const double*)f->X.p, W, y,
-                       (long long)K);
-    return hipGetLastError();
+    FTRY(cg_solve(f, 1, tol, max_iter, converged, s));
+    return hipMemcpyAsync(y, f->X.p, (size_t)K * 8, hipMemcpyDeviceToDevice, s);
 }
 
 hipError_t fact_block(FactOp* f, const FactBlockArgs& b, int* converged, hipStream_t s) {

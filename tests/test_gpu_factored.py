@@ -93,6 +93,37 @@ def test_solve_overlap_matches_direct_solve(c1):
     assert ns == 1 and 0 < mx <= it  # 70 columns fit one block
 
 
+def test_solve_overlap_single_vector(c1):
+    """One right-hand side takes the single-vector kernels (a wave per row
+    group, lanes over its entries): the same residual bound as the block,
+    the block's answer for that column to within the tolerance, a zero
+    right-hand side answered with zero, and the same result twice."""
+    c, _, _ = c1
+    S = c.S_dense()
+    rng = np.random.default_rng(7)
+    B = rng.standard_normal((c.K, 70))
+    say(f"case: single-vector solve K={c.K}")
+    ctx = fact_ctx(c, cg_tol=1e-12)
+    Xb = ctx.dm_solve_overlap(B)
+    x1 = ctx.dm_solve_overlap(B[:, 3:4])
+    x1b = ctx.dm_solve_overlap(B[:, 3:4])
+    ns, it, mx = ctx.dm_cg_stats()
+    res = np.linalg.norm(S @ x1[:, 0] - B[:, 3]) / np.linalg.norm(B[:, 3])
+    ref = scipy.linalg.cho_solve(scipy.linalg.cho_factor(S), B[:, 3])
+    fwd = np.linalg.norm(x1[:, 0] - ref) / np.linalg.norm(ref)
+    dblk = np.linalg.norm(x1[:, 0] - Xb[:, 3]) / np.linalg.norm(ref)
+    say(f"  rel residual {res:.2e}, rel error {fwd:.2e}, vs block column {dblk:.2e}; "
+        f"{ns} solves, {it} iterations, at most {mx}")
+    cond = np.linalg.cond(S)
+    assert res < 1e-11 and fwd < cond * 1e-11 and dblk < 2 * cond * 1e-11
+    assert np.array_equal(x1, x1b)
+    assert ns == 3 and mx > 0
+    z = ctx.dm_solve_overlap(np.zeros((c.K, 1)))
+    assert np.all(z == 0.0)
+    ns, it, mx = ctx.dm_cg_stats()
+    assert ns == 1 and it == 0
+
+
 def test_factored_fp64_matches_oracle(c1):
     """All 256 columns in one block, N = 400: P, the moments and the traces."""
     c, sp, (emin, emax) = c1
