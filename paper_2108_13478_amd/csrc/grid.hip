@@ -7,16 +7,17 @@
 // cell, the functions whose window reaches the cell (b-list) and those of
 // them whose column is in the pass (a-list, with the column position).  For
 // a chunk of 64 a-entries the workgroup forms t(g, a) = sum_b phi_b(g) P_ba,
-// a 64 x 64 x n_b product, 32 b at a time: phi of the b chunk at the 64
-// points and the 32 x 64 block of P are staged in LDS, and each thread
-// accumulates a 4-point x 4-column block in registers.  The global loads of
-// the next b chunk (its P block and its functions' parameters) are issued
-// into registers before the products of the current chunk, so their latency
-// overlaps the arithmetic.  Then n(g) += 2 sum_a phi_a(g) t(g, a), reduced
-// over the threads of a point in a fixed order.  A Gaussian and its cube
-// window factor over x, y and z, so phi of one function on the cell's
-// 4 x 4 x 4 points takes 12 exponentials, each computed by one lane and
-// shared by wave shuffles.  Cells own disjoint points, so no atomics are
+// a 64 x 64 x n_b product, on the matrix cores (FP64 MFMA 16 x 16 x 4, one
+// z-plane of the cell per wave), 32 b at a time: phi of the b chunk at the
+// 64 points and the 32 x 64 block of P are staged in LDS.  The global loads
+// of the next b chunk (its P block and its functions' parameters) are
+// issued into registers before the products of the current chunk, and the
+// list entries they are indexed by one chunk earlier still, so their
+// latency overlaps the arithmetic.  Then n(g) += 2 sum_a phi_a(g) t(g, a)
+// from the result registers, reduced over lanes in a fixed order.  A
+// Gaussian and its cube window factor over x, y and z, so phi of one
+// function on the cell's 4 x 4 x 4 points takes 12 exponentials, each
+// computed by one lane.  Cells own disjoint points, so no atomics are
 // needed.
 #include "dm_common.hpp"
 
@@ -39,20 +40,31 @@ struct BChunk {
     double e, R, nrm, cx, cy, cz;
 };
 
-__device__ inline void load_bchunk(const GridArgs& a, int bs, int nb, int na, const long long (&acol)[8],
-                                   BChunk& c) {
+// List entries of a b chunk the thread's loads need: the P row of b =
+// tid % 32 and the function tid / 8 (-1 beyond the chunk).  They are loaded
+// one chunk before the values, so each chunk's value loads wait for one
+// memory latency, not two.
+struct BIdx {
+    int brow, bfn;
+};
+
+__device__ inline void load_bidx(const GridArgs& a, int bs, int nb, BIdx& x) {
     const int tid = threadIdx.x;
-    const int k = tid & (kBc - 1);
-    const long long brow = k < nb ? a.beta_idx[bs + k] : 0;
+    const int k = tid & (kBc - 1), bb = tid >> 3;
+    x.brow = k < nb ? a.beta_idx[bs + k] : -1;
+    x.bfn = bb < nb ? a.beta_idx[bs + bb] : -1;
+}
+
+__device__ inline void load_bchunk(const GridArgs& a, int na, const int (&acol)[8], const BIdx& x, BChunk& c) {
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int aa = (tid >> 5) + 8 * i;
-        c.pv[i] = (k < nb && aa < na) ? a.P[acol[i] * a.ldp + brow] : 0.0;
+        c.pv[i] = (x.brow >= 0 && aa < na) ? a.P[(long long)acol[i] * a.ldp + x.brow] : 0.0;
     }
-    const int bb = tid >> 3;
     c.e = 0.0, c.R = -1.0, c.nrm = 0.0, c.cx = 0.0, c.cy = 0.0, c.cz = 0.0;
-    if (bb < nb) {
-        const int b = a.beta_idx[bs + bb];
+    if (x.bfn >= 0) {
+        const int b = x.bfn;
         c.e = a.ex[b];
         c.R = a.R[b];
         c.nrm = a.norm[b];
@@ -62,34 +74,53 @@ __device__ inline void load_bchunk(const GridArgs& a, int bs, int nb, int na, co
     }
 }
 
-// 33 KB of LDS and at most 168 registers: three workgroups per CU
+// 40 KB of LDS: three workgroups per CU
 __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
     __shared__ __align__(16) double phb[kBc][kPs];  // phi_b(point), b of the chunk x 64 points
     __shared__ __align__(16) double pb[kBc][kPs];   // P_ba, b of the chunk x a of the chunk
-    double(*red)[64] = reinterpret_cast<double(*)[64]>(&phb[0][0]);  // after the last chunk: 16 x 64 sums
+    __shared__ double fa[64][13];  // per a-entry: 2 norm fx(x), fy(y), fz(z) at coordinates 0..3
     const int cell = blockIdx.x;
     const int ccx = cell % a.ncx, ccy = (cell / a.ncx) % a.ncy, ccz = cell / (a.ncx * a.ncy);
     const int tid = threadIdx.x;
-    const int tp = tid & 15, ta = tid >> 4;  // points 4 tp .. 4 tp + 3 (x = 0..3), a-entries 4 ta .. 4 ta + 3
-    const int py = tp & 3, pz = tp >> 2;     // the thread's four points differ in x only
+    const int w = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
+    // MFMA rows: lane li feeds point (x, y) = (li / 4, li % 4) of z-plane w,
+    // so result element e of lane (li, lq) is point (e, lq, w) and column li
+    const int arow = 16 * w + (li >> 2) + 4 * (li & 3);
     const int a0 = a.alpha_ptr[cell], a1 = a.alpha_ptr[cell + 1];
     const int b0 = a.beta_ptr[cell], b1 = a.beta_ptr[cell + 1];
     double npt[4] = {0.0, 0.0, 0.0, 0.0};
     for (int as = a0; as < a1; as += 64) {
         const int na = min(64, a1 - as);
-        long long acol[8];  // columns of the thread's P loads
+        int acol[8];  // columns of the thread's P loads
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int aa = (tid >> 5) + 8 * i;
             acol[i] = aa < na ? a.alpha_col[as + aa] : 0;
         }
-        double t[4][4];
+        __syncthreads();  // the previous chunk's epilogue has read fa
+        // axis factors of the chunk's a-entries: entry tid / 4 at coordinate tid % 4
+        {
+            const int e = tid >> 2, q = tid & 3;
+            double fx = 0.0, fy = 0.0, fz = 0.0;
+            if (e < na) {
+                const int f = a.alpha_idx[as + e];
+                const double ex = a.ex[f], R = a.R[f];
+                fx = 2.0 * a.norm[f] * axis_factor(ex, R, a.ox + a.h * (4 * ccx + q) - a.cx[f]);
+                fy = axis_factor(ex, R, a.oy + a.h * (4 * ccy + q) - a.cy[f]);
+                fz = axis_factor(ex, R, a.oz + a.h * (4 * ccz + q) - a.cz[f]);
+            }
+            fa[e][q] = fx;
+            fa[e][4 + q] = fy;
+            fa[e][8 + q] = fz;
+        }
+        double4_t acc[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) t[i][j] = 0.0;
+        for (int c = 0; c < 4; ++c) acc[c] = double4_t{0.0, 0.0, 0.0, 0.0};
         BChunk cur;
-        load_bchunk(a, b0, min(kBc, b1 - b0), na, acol, cur);
+        BIdx nxt;
+        load_bidx(a, b0, min(kBc, b1 - b0), nxt);
+        load_bchunk(a, na, acol, nxt, cur);
+        if (b0 + kBc < b1) load_bidx(a, b0 + kBc, min(kBc, b1 - b0 - kBc), nxt);
         for (int bs = b0; bs < b1; bs += kBc) {
             const int nb = min(kBc, b1 - bs);
             // phi of the b chunk: the eight lanes of function bb = tid / 8
@@ -113,68 +144,55 @@ __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) phb[bb][u + 4 * (2 * half + v) + 16 * q] = s * fyv[v] * fxv[u];
             }
-            // P block: lane k = b of the chunk, thread group w = tid / 32
-            // holds a-entries w, w + 8, ...
+            // P block: lane k = b of the chunk, thread group tid / 32 holds
+            // a-entries tid / 32 + 8 i
             {
-                const int k = tid & (kBc - 1), w = tid >> 5;
+                const int k = tid & (kBc - 1), g = tid >> 5;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) pb[k][w + 8 * i] = cur.pv[i];
+                for (int i = 0; i < 8; ++i) pb[k][g + 8 * i] = cur.pv[i];
             }
             __syncthreads();
-            if (bs + kBc < b1) load_bchunk(a, bs + kBc, min(kBc, b1 - bs - kBc), na, acol, cur);
-            for (int k = 0; k < nb; ++k) {
-                const double2 f01 = *reinterpret_cast<const double2*>(&phb[k][4 * tp]);
-                const double2 f23 = *reinterpret_cast<const double2*>(&phb[k][4 * tp + 2]);
-                const double2 p01 = *reinterpret_cast<const double2*>(&pb[k][4 * ta]);
-                const double2 p23 = *reinterpret_cast<const double2*>(&pb[k][4 * ta + 2]);
-                const double f[4] = {f01.x, f01.y, f23.x, f23.y};
-                const double p[4] = {p01.x, p01.y, p23.x, p23.y};
+            if (bs + kBc < b1) {
+                load_bchunk(a, na, acol, nxt, cur);
+                if (bs + 2 * kBc < b1) load_bidx(a, bs + 2 * kBc, min(kBc, b1 - bs - 2 * kBc), nxt);
+            }
+            // t(g, a) += sum_b phi_b(g) P_ba: wave w takes the 16 points of
+            // z-plane w and the 64 a-entries (four 16 x 16 tiles), 4 b per
+            // MFMA; rows beyond nb hold zeros
+            const int nk = (nb + 3) >> 2;
+            for (int st = 0; st < nk; ++st) {
+                const int kb = 4 * st + lq;
+                const double av = phb[kb][arow];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) t[i][j] += f[i] * p[j];
+                for (int c = 0; c < 4; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, pb[kb][16 * c + li], acc[c], 0, 0, 0);
             }
             __syncthreads();
         }
-        // n(g) += 2 phi_a(g) t(g, a) for the thread's four a-entries.  The
-        // 16 lanes sharing an a-entry (same ta) compute its 12 axis factors,
-        // lane tp: x (tp < 4), y (4..7) or z (8..11) at coordinate tp % 4.
-        {
-            const int base = (tid & 63) & ~15;
+        // n(g) += 2 phi_a(g) t(g, a): lane (li, lq) of wave w holds points
+        // (e, lq, w), e = 0..3, for a-entries 16 c + li (entries beyond na
+        // have zero factors)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int aa = 4 * ta + j;
-                double fac = 0.0, nrm = 0.0;
-                if (aa < na) {
-                    const int f = a.alpha_idx[as + aa];
-                    const double e = a.ex[f], R = a.R[f];
-                    nrm = 2.0 * a.norm[f];
-                    const int c = tp & 3;
-                    if (tp < 4)
-                        fac = axis_factor(e, R, a.ox + a.h * (4 * ccx + c) - a.cx[f]);
-                    else if (tp < 8)
-                        fac = axis_factor(e, R, a.oy + a.h * (4 * ccy + c) - a.cy[f]);
-                    else if (tp < 12)
-                        fac = axis_factor(e, R, a.oz + a.h * (4 * ccz + c) - a.cz[f]);
-                }
-                const double fyv = __shfl(fac, base + 4 + py, 64), fzv = __shfl(fac, base + 8 + pz, 64);
-                const double s = nrm * fyv * fzv;
+        for (int c = 0; c < 4; ++c) {
+            const int aa = 16 * c + li;
+            const double s = fa[aa][4 + lq] * fa[aa][8 + w];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) npt[i] += s * __shfl(fac, base + i, 64) * t[i][j];
-            }
+            for (int e = 0; e < 4; ++e) npt[e] += s * fa[aa][e] * acc[c][e];
         }
     }
+    // sums over the 16 lanes of a point row (fixed butterfly order)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) red[ta][4 * tp + i] = npt[i];
-    __syncthreads();
-    if (tid < 64) {
-        const int p = tid;
-        const int gi = 4 * ccx + (p & 3), gj = 4 * ccy + ((p >> 2) & 3), gk = 4 * ccz + (p >> 4);
-        if (gi < a.nx && gj < a.ny && gk < a.nz) {
-            double sum = 0.0;
-            for (int q = 0; q < 16; ++q) sum += red[q][p];
-            const long long g = gi + (long long)a.nx * (gj + (long long)a.ny * gk);
-            a.n[g] += sum;
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) npt[e] += __shfl_xor(npt[e], off, 64);
+    if (li == 0) {
+        const int gj = 4 * ccy + lq, gk = 4 * ccz + w;
+        if (gj < a.ny && gk < a.nz) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gi = 4 * ccx + e;
+                if (gi < a.nx) a.n[gi + (long long)a.nx * (gj + (long long)a.ny * gk)] += npt[e];
+            }
         }
     }
 }
