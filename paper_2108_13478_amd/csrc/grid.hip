@@ -79,7 +79,13 @@ __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
     __shared__ __align__(16) double phb[kBc][kPs];  // phi_b(point), b of the chunk x 64 points
     __shared__ __align__(16) double pb[kBc][kPs];   // P_ba, b of the chunk x a of the chunk
     __shared__ double fa[64][13];  // per a-entry: 2 norm fx(x), fy(y), fz(z) at coordinates 0..3
-    const int cell = blockIdx.x;
+    // workgroups go to the 8 XCDs round robin; XCD x takes the groups of 16
+    // consecutive cells x, x + 8, ..., a group at a time, so the 16 cells
+    // of a group, which read nearly the same block of P, run together on
+    // one L2, and every XCD gets cells from all over the grid
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int cell = (((slot >> 4) << 3) + xcd) * 16 + (slot & 15);
+    if (cell >= a.ncx * a.ncy * a.ncz) return;
     const int ccx = cell % a.ncx, ccy = (cell / a.ncx) % a.ncy, ccz = cell / (a.ncx * a.ncy);
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
@@ -202,8 +208,9 @@ __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
 hipError_t density_on_grid(const GridArgs& a, hipStream_t s) {
     const long long ncell = (long long)a.ncx * a.ncy * a.ncz;
     if (ncell <= 0) return hipSuccess;
-    if (ncell > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(density_kernel, dim3((unsigned)ncell), dim3(256), 0, s, a);
+    const long long nwg = (ncell + 127) / 128 * 128;  // whole rounds of 8 groups of 16 cells
+    if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(density_kernel, dim3((unsigned)nwg), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
