@@ -1,0 +1,54 @@
+"""CPU checks of the benchmark script and the committed profile summaries:
+the one-GPU contract of bench.py, the byte counters it reports being taken
+at the current kernel sources, and every profile summary naming the kernel
+source it was taken at and a command that runs committed files."""
+import glob
+import hashlib
+import json
+import os
+import re
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_counters_match_current_kernel_sources():
+    # bench.py reports traffic only while these hold; a kernel change must
+    # come with counters taken again
+    assert bench.kernel_source_hash("gemm.hip") == bench.COUNTERS["kernel_source_sha256_16"]
+    assert bench.kernel_source_hash("gemm.hip") == bench.COUNTERS_HBM["kernel_source_sha256_16"]
+    assert (bench.kernel_source_hash("factored.hip", bench.FACT_DEVICE_END)
+            == bench.COUNTERS_FACT["kernel_source_sha256_16"])
+
+
+def test_profiles_name_their_source_and_a_committed_command():
+    files = sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md")))
+    assert files
+    csrc = os.path.join(ROOT, "paper_2108_13478_amd", "csrc")
+    for path in files:
+        text = open(path).read()
+        name = os.path.basename(path)
+        cmds = [l.strip() for l in text.splitlines() if l.strip().startswith("rocprofv3 ")]
+        assert cmds, f"{name}: no rocprofv3 command"
+        for c in cmds:
+            assert "_work" not in c and "/root/reference" not in c, f"{name}: {c}"
+            prog = c.split(" -- ", 1)[1].split()
+            assert prog[0] in ("python3", "python"), f"{name}: {c}"
+            for arg in prog[1:]:
+                if arg.endswith(".py") or arg.startswith("tests/"):
+                    assert os.path.exists(os.path.join(ROOT, arg.split("::")[0])), f"{name}: {arg}"
+        # a profile of a kernel of grid.hip states that file's hash
+        if name.startswith("density_kernel"):
+            h = hashlib.sha256(open(os.path.join(csrc, "grid.hip"), "rb").read()).hexdigest()[:16]
+            assert re.search(rf"`{h}`", text), f"{name}: grid.hip hash {h} not stated"
