@@ -171,7 +171,8 @@ __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
                 const double av = phb[kb][arow];
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, pb[kb][16 * c + li], acc[c], 0, 0, 0);
+                    if (16 * c < na)  // tiles past the chunk's a-entries stay zero
+                        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, pb[kb][16 * c + li], acc[c], 0, 0, 0);
             }
             __syncthreads();
         }
@@ -180,6 +181,7 @@ __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
         // have zero factors)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
+            if (16 * c >= na) break;
             const int aa = 16 * c + li;
             const double s = fa[aa][4 + lq] * fa[aa][8 + w];
 #pragma unroll
