@@ -16,9 +16,9 @@
 // latency overlaps the arithmetic.  Then n(g) += 2 sum_a phi_a(g) t(g, a)
 // from the result registers, reduced over lanes in a fixed order.  A
 // Gaussian and its cube window factor over x, y and z, so phi of one
-// function on the cell's 4 x 4 x 4 points takes 12 exponentials, each
-// computed by one lane.  Cells own disjoint points, so no atomics are
-// needed.
+// function on the cell's 4 x 4 x 4 points takes 12 exponentials instead of
+// 64, computed by the function's lanes and shared by wave shuffles.  Cells
+// own disjoint points, so no atomics are needed.
 #include "dm_common.hpp"
 
 namespace dm {
