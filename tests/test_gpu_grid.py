@@ -110,3 +110,19 @@ def test_density_k4096_from_full_pass_timed():
     say(f"case: K={c.K} grid {dims} ({int(np.prod(dims)) / 1e6:.1f} M points), eta 1e-6: {dt * 1e3:.0f} ms "
         f"(call, lists and copies included); h^3 sum n = {total:.6f}, 2 Tr[P_N S] = {2 * tr:.6f}")
     assert abs(total - 2 * tr) < 1e-4 * 2 * tr
+    # sampled points against the grid oracle, each computed on its own
+    # (a one-point grid at that point) from the same P: 48 anywhere on the
+    # grid, 48 in the central third where the most functions overlap
+    nh = nd.cpu().numpy()
+    Pc = Pd.cpu().numpy().T  # column j is column j of P
+    rng = np.random.default_rng(11)
+    lo = [d // 3 for d in dims]
+    idx = np.concatenate([rng.integers(0, dims, size=(48, 3)),
+                          rng.integers(lo, [2 * d // 3 for d in dims], size=(48, 3))])
+    worst = 0.0
+    for i, j, k in idx:
+        pt = np.asarray(origin, dtype=np.float64) + h * np.array([i, j, k], dtype=np.float64)
+        ref = GO.density_on_grid(Pc, np.arange(c.K), centres, exps, pt, h, (1, 1, 1), 1e-6)[0]
+        worst = max(worst, abs(nh[i + dims[0] * (j + dims[1] * k)] - ref))
+    say(f"  96 sampled points vs oracle: max|dn| = {worst:.2e} (max|n| {np.abs(nh).max():.3f})")
+    assert worst < 1e-12 * np.abs(nh).max()
