@@ -1404,6 +1404,54 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
         fe[b] = a;
         fn[b] = std::pow(2.0 * a / 3.14159265358979323846, 0.75);
         fr[b] = std::sqrt(lninv / a);
+        if (!std::isfinite(fx[b]) || !std::isfinite(fy[b]) || !std::isfinite(fz[b]))
+            return set_err(c, DM_E_ARG, "centres must be finite");
+    }
+    // Functions in Morton (Z-curve) order of their centres, ties by index:
+    // the functions that reach one cell are then a few runs of consecutive
+    // indices, so the kernel reads a column of P in long runs instead of one
+    // atom's rows here and there.  The per-function arrays, the column
+    // positions and the rows of P are permuted alike (perm: new -> old); the
+    // density does not depend on the order of the sum over functions.
+    std::vector<int> perm((size_t)K);
+    {
+        double lo[3], hi[3];
+        const std::vector<double>* axes[3] = {&fx, &fy, &fz};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = *std::min_element(axes[d]->begin(), axes[d]->end());
+            hi[d] = *std::max_element(axes[d]->begin(), axes[d]->end());
+        }
+        const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
+        const double cell = ext > 0 ? ext / 1023.0 : 1.0;
+        auto spread = [](unsigned long long v) {  // bit i of v -> bit 3 i
+            v &= 0x3ffULL;
+            v = (v | (v << 16)) & 0x30000ffULL;
+            v = (v | (v << 8)) & 0x300f00fULL;
+            v = (v | (v << 4)) & 0x30c30c3ULL;
+            v = (v | (v << 2)) & 0x9249249ULL;
+            return v;
+        };
+        std::vector<std::pair<unsigned long long, int>> key((size_t)K);
+        for (long long b = 0; b < K; ++b) {
+            unsigned long long q[3];
+            for (int d = 0; d < 3; ++d)
+                q[d] = (unsigned long long)std::min(1023.0, std::max(0.0, std::floor(((*axes[d])[b] - lo[d]) / cell)));
+            key[b] = {spread(q[0]) | (spread(q[1]) << 1) | (spread(q[2]) << 2), (int)b};
+        }
+        std::sort(key.begin(), key.end());
+        for (long long i = 0; i < K; ++i) perm[i] = key[i].second;
+        auto apply = [&](auto& v) {
+            std::remove_reference_t<decltype(v)> t(v.size());
+            for (long long i = 0; i < K; ++i) t[i] = v[perm[i]];
+            v.swap(t);
+        };
+        apply(fx);
+        apply(fy);
+        apply(fz);
+        apply(fe);
+        apply(fn);
+        apply(fr);
+        apply(colpos);
     }
     // cell lists: function b reaches the grid indices [lo, hi] along each axis
     const int ncx = (nx + 3) / 4, ncy = (ny + 3) / 4, ncz = (nz + 3) / 4;
@@ -1490,11 +1538,11 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
         });
     }
     hipStream_t s = c->stream;
-    DevBuf<double> dfx, dfy, dfz, dfe, dfn, dfr, dP, dn;
-    DevBuf<int> dbp, dbi, dap, dai, dac;
+    DevBuf<double> dfx, dfy, dfz, dfe, dfn, dfr, dP, dPp, dn;
+    DevBuf<int> dbp, dbi, dap, dai, dac, dperm;
     auto rel = [&]() {
-        for (auto* x : {&dfx, &dfy, &dfz, &dfe, &dfn, &dfr, &dP, &dn}) x->release();
-        for (auto* x : {&dbp, &dbi, &dap, &dai, &dac}) x->release();
+        for (auto* x : {&dfx, &dfy, &dfz, &dfe, &dfn, &dfr, &dP, &dPp, &dn}) x->release();
+        for (auto* x : {&dbp, &dbi, &dap, &dai, &dac, &dperm}) x->release();
     };
     hipError_t e;
 #define GR(expr)                          \
@@ -1525,9 +1573,13 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
     GR(up_i(dap, acount));
     GR(up_i(dai, aidx));
     GR(up_i(dac, acol));
-    // P and n through device buffers (either may be host memory)
+    GR(up_i(dperm, perm));
+    // P and n through device buffers (either may be host memory); the rows
+    // of P in the functions' new order
     GR(ensure(dP, (size_t)K * ncols));
     GR(hipMemcpyAsync(dP.p, P_cols, (size_t)K * ncols * 8, hipMemcpyDefault, s));
+    GR(ensure(dPp, (size_t)K * ncols));
+    GR(permute_rows((int)K, ncols, dperm.p, dP.p, dPp.p, s));
     GR(ensure(dn, (size_t)G));
     GR(hipMemcpyAsync(dn.p, n_out, (size_t)G * 8, hipMemcpyDefault, s));
     GridArgs ga{};
@@ -1535,7 +1587,7 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
     ga.ox = origin[0]; ga.oy = origin[1]; ga.oz = origin[2]; ga.h = h;
     ga.cx = dfx.p; ga.cy = dfy.p; ga.cz = dfz.p; ga.ex = dfe.p; ga.norm = dfn.p; ga.R = dfr.p;
     ga.beta_ptr = dbp.p; ga.beta_idx = dbi.p; ga.alpha_ptr = dap.p; ga.alpha_idx = dai.p; ga.alpha_col = dac.p;
-    ga.P = dP.p;
+    ga.P = dPp.p;
     ga.ldp = K;
     ga.n = dn.p;
     GR(density_on_grid(ga, s));

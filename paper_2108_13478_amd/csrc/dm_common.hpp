@@ -208,6 +208,9 @@ struct GridArgs {
     double* n;
 };
 hipError_t density_on_grid(const GridArgs& a, hipStream_t s);
+// dst[j K + r] = src[j K + perm[r]]: the rows of a K x ncols column-major
+// block in the order perm (new -> old)
+hipError_t permute_rows(int K, long long ncols, const int* perm, const double* src, double* dst, hipStream_t s);
 
 // ----------------------------------------------------------------- setup
 hipError_t fill_f64(double* x, double v, long long n, hipStream_t s);

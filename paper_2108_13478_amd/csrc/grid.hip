@@ -205,7 +205,26 @@ __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
     }
 }
 
+// dst[j K + r] = src[j K + perm[r]] for r < K, j < ncols
+__global__ void permute_rows_kernel(int K, long long ncols, const int* __restrict__ perm,
+                                    const double* __restrict__ src, double* __restrict__ dst) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)K * ncols) return;
+    const long long j = e / K;
+    const int r = (int)(e - j * K);
+    dst[e] = src[j * K + perm[r]];
+}
+
 }  // namespace
+
+hipError_t permute_rows(int K, long long ncols, const int* perm, const double* src, double* dst, hipStream_t s) {
+    const long long n = (long long)K * ncols;
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(permute_rows_kernel, dim3((unsigned)nb), dim3(256), 0, s, K, ncols, perm, src, dst);
+    return hipGetLastError();
+}
 
 hipError_t density_on_grid(const GridArgs& a, hipStream_t s) {
     const long long ncell = (long long)a.ncx * a.ncy * a.ncz;
