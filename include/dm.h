@@ -282,9 +282,12 @@ dm_status dm_dos(dm_ctx* ctx, int kind, int n, const double* energies, double si
  * g = i + nx (j + ny k).  cols (int64, host or device, ncols distinct
  * indices); P_cols (host or device, K x ncols column-major FP64, as written
  * by dm_chebyshev_block); n_out (host or device, nx ny nz FP64) is
- * accumulated.  Independent of any loaded Fock matrix.
- * Errors: DM_E_ARG (bad sizes, exponents <= 0, h <= 0, eta outside (0, 1),
- * bad or repeated columns), DM_E_OOM, DM_E_HIP. */
+ * accumulated.  Independent of any loaded Fock matrix.  Needs device
+ * memory for two copies of P_cols (the second with its rows in the
+ * library's spatial order of the functions) besides the grid; the result
+ * does not depend on timing.
+ * Errors: DM_E_ARG (bad sizes, exponents <= 0, non-finite centres, h <= 0,
+ * eta outside (0, 1), bad or repeated columns), DM_E_OOM, DM_E_HIP. */
 dm_status dm_density_on_grid(dm_ctx* ctx, long long K, const double* centres, const double* exponents,
                              const double* origin, double h, const int* dims, double eta,
                              const long long* cols, long long ncols, const double* P_cols, double* n_out);
