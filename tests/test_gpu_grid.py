@@ -72,6 +72,11 @@ def test_density_from_a_pass_integrates_to_electron_count():
         ctx.dm_density_on_grid(centres, exps, origin, -1.0, dims, 1e-6, cols, Pd, nd)
     with pytest.raises(dmlib.DMError):
         ctx.dm_density_on_grid(centres, exps, origin, h, dims, 2.0, cols, Pd, nd)
+    bad = centres.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(dmlib.DMError) as ei:
+        ctx.dm_density_on_grid(bad, exps, origin, h, dims, 1e-6, cols, Pd, nd)
+    assert ei.value.status == dmlib.DM_E_ARG
 
 
 def test_density_k4096_from_full_pass_timed():
