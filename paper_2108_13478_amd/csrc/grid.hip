@@ -25,7 +25,10 @@ namespace dm {
 namespace {
 
 constexpr int kBc = 32;  // b-functions per staged chunk
-constexpr int kPs = 66;  // row stride of the staged blocks (doubles): 16-byte rows, few bank conflicts
+constexpr int kPs = 66;  // row stride of the staged P block (doubles)
+// phi rows: z-plane q of the cell at 17 q, point (x, y) at x + 4 y; the
+// padding puts the four planes in different LDS banks for the stores
+constexpr int kPlane = 17, kPhs = 67;
 
 // exp(-a d^2) inside the window |d| <= R, else 0
 __device__ inline double axis_factor(double a, double R, double d) {
@@ -76,7 +79,7 @@ __device__ inline void load_bchunk(const GridArgs& a, int na, const int (&acol)[
 
 // 40 KB of LDS: three workgroups per CU
 __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
-    __shared__ __align__(16) double phb[kBc][kPs];  // phi_b(point), b of the chunk x 64 points
+    __shared__ __align__(16) double phb[kBc][kPhs];  // phi_b(point), b of the chunk x 64 points
     __shared__ __align__(16) double pb[kBc][kPs];   // P_ba, b of the chunk x a of the chunk
     __shared__ double fa[64][13];  // per a-entry: 2 norm fx(x), fy(y), fz(z) at coordinates 0..3
     // workgroups go to the 8 XCDs round robin; XCD x takes the groups of 16
@@ -91,7 +94,7 @@ __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
     const int w = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
     // MFMA rows: lane li feeds point (x, y) = (li / 4, li % 4) of z-plane w,
     // so result element e of lane (li, lq) is point (e, lq, w) and column li
-    const int arow = 16 * w + (li >> 2) + 4 * (li & 3);
+    const int arow = kPlane * w + (li >> 2) + 4 * (li & 3);
     const int a0 = a.alpha_ptr[cell], a1 = a.alpha_ptr[cell + 1];
     const int b0 = a.beta_ptr[cell], b1 = a.beta_ptr[cell + 1];
     double npt[4] = {0.0, 0.0, 0.0, 0.0};
@@ -148,7 +151,7 @@ __global__ void __launch_bounds__(256, 3) density_kernel(GridArgs a) {
 #pragma unroll
                 for (int v = 0; v < 2; ++v)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) phb[bb][u + 4 * (2 * half + v) + 16 * q] = s * fyv[v] * fxv[u];
+                    for (int u = 0; u < 4; ++u) phb[bb][u + 4 * (2 * half + v) + kPlane * q] = s * fyv[v] * fxv[u];
             }
             // P block: lane k = b of the chunk, thread group tid / 32 holds
             // a-entries tid / 32 + 8 i
