@@ -276,8 +276,10 @@ dm_status dm_dos(dm_ctx* ctx, int kind, int n, const double* energies, double si
  * eq. density (the paper's reduce over processors).  The basis is K
  * normalised s-type Gaussians (2a/pi)^{3/4} exp(-a |r - R|^2): centres (host,
  * K x 3 row-major) and exponents (host, K), in the order of F and S; each is
- * zero outside the cube of half-width sqrt(ln(1/eta)/a) around its centre
- * (the grid windows of the paper, 0 < eta < 1).  Grid: r_g = origin (host,
+ * zero outside the cube of half-width L = d / sqrt(a) around its centre, the
+ * grid window of eq. WindowLength that keeps the fraction 1 - eta of the
+ * function's charge, c(d, 0) = erf(d) = 1 - eta (0 < eta < 1; d = 3.459 at
+ * eta = 1e-6).  Grid: r_g = origin (host,
  * 3) + h (i, j, k), dims (host, 3) = (nx, ny, nz), flattened index
  * g = i + nx (j + ny k).  cols (int64, host or device, ncols distinct
  * indices); P_cols (host or device, K x ncols column-major FP64, as written

@@ -8,22 +8,37 @@ ElectronDensity): the density carried by column a of P is
 n_a(r_g) = 2 phi_a(r_g) sum_b phi_b(r_g) P_ba, and the density of a set of
 columns is the sum over the set (the paper's reduce over processors).  The
 basis functions are normalised s-type Gaussians phi(r) = (2a/pi)^{3/4}
-exp(-a |r - R|^2).  Each is set to zero outside its window, read from the
-paper's figure as a cube centred on the atom; its half-width R is where the
-Gaussian factor reaches eta, R = sqrt(ln(1/eta) / a) (the paper studies
-eta = 1e-3 .. 1e-6).  Grid points are r_g = origin + h (i, j, k), with i
-fastest in the flattened index g = i + nx (j + ny k).
+exp(-a |r - R|^2).  Each is set to zero outside its window, a cube centred
+on the function's centre whose half-width L keeps the fraction 1 - eta of
+the "charge" of the most protruding primitive (grid-window section, eq.
+WindowLength): c(L sqrt(zeta), l) = 1 - eta with
+c(d, l) = int_0^d x^l exp(-x^2) dx / int_0^inf x^l exp(-x^2) dx, the
+regularised incomplete gamma function P((l + 1)/2, d^2).  The basis here is
+s-type (l = 0), where c(d, 0) = erf(d).  Grid points are
+r_g = origin + h (i, j, k), with i fastest in the flattened index
+g = i + nx (j + ny k).
 """
 from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["window_halfwidth", "grid_points", "basis_on_grid", "density_on_grid"]
+__all__ = ["window_depth", "window_halfwidth", "grid_points", "basis_on_grid", "density_on_grid"]
 
 
-def window_halfwidth(exponents, eta):
-    """Half-width of each function's cube window, sqrt(ln(1/eta) / a)."""
-    return np.sqrt(np.log(1.0 / eta) / np.asarray(exponents, dtype=np.float64))
+def window_depth(eta, l=0):
+    """d = L sqrt(zeta) solving c(d, l) = 1 - eta (eq. WindowLength).
+
+    c(d, l) = P((l + 1)/2, d^2), so d^2 is the inverse of the upper
+    regularised incomplete gamma function at eta (exact for eta far below
+    the rounding of 1 - eta)."""
+    from scipy.special import gammainccinv
+
+    return np.sqrt(gammainccinv(0.5 * (l + 1), eta))
+
+
+def window_halfwidth(exponents, eta, l=0):
+    """Half-width L of each function's cube window: window_depth / sqrt(zeta)."""
+    return window_depth(eta, l) / np.sqrt(np.asarray(exponents, dtype=np.float64))
 
 
 def grid_points(origin, h, shape):

@@ -1370,6 +1370,25 @@ dm_status dm_dos(dm_ctx* c, int kind, int n, const double* energies, double sigm
     return host_exception(c);
 }
 
+// Window depth d = L sqrt(zeta) of an s-type Gaussian (grid-window section,
+// eq. WindowLength): the window keeps the fraction 1 - eta of the function's
+// one-dimensional integral, c(d, 0) = erf(d) = 1 - eta, i.e. erfc(d) = eta.
+// Solved by Newton's method on ln erfc (convex and decreasing for d >= 0),
+// which stays accurate for eta far below the rounding of 1 - eta.
+static double window_depth_s(double eta) {
+    const double two_over_sqrtpi = 1.1283791670955126;
+    double d = eta < 0.5 ? std::sqrt(std::log(1.0 / eta)) : 0.5;
+    for (int it = 0; it < 100; ++it) {
+        const double q = std::erfc(d);
+        const double g = std::log(q) - std::log(eta);
+        const double dg = -two_over_sqrtpi * std::exp(-d * d) / q;
+        const double nd = std::max(0.0, d - g / dg);
+        if (std::fabs(nd - d) <= 1e-15 * std::max(1.0, d)) return nd;
+        d = nd;
+    }
+    return d;
+}
+
 dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, const double* exponents,
                              const double* origin, double h, const int* dims, double eta, const long long* cols,
                              long long ncols, const double* P_cols, double* n_out) try {
@@ -1394,7 +1413,7 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
     }
     // per-function data and window half-widths (host arrays, K entries)
     std::vector<double> fx(K), fy(K), fz(K), fe(K), fn(K), fr(K);
-    const double lninv = std::log(1.0 / eta);
+    const double dwin = window_depth_s(eta);
     for (long long b = 0; b < K; ++b) {
         const double a = exponents[b];
         if (!(a > 0) || !std::isfinite(a)) return set_err(c, DM_E_ARG, "exponents must be > 0");
@@ -1403,7 +1422,7 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
         fz[b] = centres[3 * b + 2];
         fe[b] = a;
         fn[b] = std::pow(2.0 * a / 3.14159265358979323846, 0.75);
-        fr[b] = std::sqrt(lninv / a);
+        fr[b] = dwin / std::sqrt(a);
         if (!std::isfinite(fx[b]) || !std::isfinite(fy[b]) || !std::isfinite(fz[b]))
             return set_err(c, DM_E_ARG, "centres must be finite");
     }
@@ -1457,7 +1476,10 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
     const int ncx = (nx + 3) / 4, ncy = (ny + 3) / 4, ncz = (nz + 3) / 4;
     const long long ncell = (long long)ncx * ncy * ncz;
     if (ncell > (1LL << 31) - 1) return set_err(c, DM_E_ARG, "grid too large");
-    std::vector<int> bcount((size_t)ncell + 1, 0), acount((size_t)ncell + 1, 0);
+    // per-cell counts (each at most K), prefix sums in 64 bits: the number of
+    // (function, cell) pairs can pass 2^31 on fine grids, and the kernel's
+    // offsets are 32-bit, so such a call is refused below
+    std::vector<long long> bcount((size_t)ncell + 1, 0), acount((size_t)ncell + 1, 0);
     // grid indices a window reaches, with one point of slack on each side (the
     // kernel tests every point exactly), clamped before the integer conversion
     auto range = [&](double ctr, double R, double o, int n, int& lo, int& hi) {
@@ -1517,9 +1539,11 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
         bcount[i + 1] += bcount[i];
         acount[i + 1] += acount[i];
     }
+    if (bcount[ncell] > (long long)INT32_MAX)
+        return set_err(c, DM_E_ARG, "grid too fine for the windows: more than 2^31 - 1 (function, cell) pairs");
     std::vector<int> bidx((size_t)bcount[ncell]), aidx((size_t)acount[ncell]), acol((size_t)acount[ncell]);
     {
-        std::vector<int> bfill(bcount.begin(), bcount.end() - 1), afill(acount.begin(), acount.end() - 1);
+        std::vector<long long> bfill(bcount.begin(), bcount.end() - 1), afill(acount.begin(), acount.end() - 1);
         slabs([&](int z0, int z1) {
             for (long long b = 0; b < K; ++b) {
                 if (!reach[b]) continue;
@@ -1568,9 +1592,9 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
     GR(up_d(dfe, fe));
     GR(up_d(dfn, fn));
     GR(up_d(dfr, fr));
-    GR(up_i(dbp, bcount));
+    GR(up_i(dbp, std::vector<int>(bcount.begin(), bcount.end())));
     GR(up_i(dbi, bidx));
-    GR(up_i(dap, acount));
+    GR(up_i(dap, std::vector<int>(acount.begin(), acount.end())));
     GR(up_i(dai, aidx));
     GR(up_i(dac, acol));
     GR(up_i(dperm, perm));

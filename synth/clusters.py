@@ -226,13 +226,20 @@ def _make_one(args):
 
 
 def make_batch(sizes, seeds, processes: int = 8, onsite: str = "diagonal"):
-    """Clusters of the given atom counts and seeds (spheres), built in parallel."""
+    """Clusters of the given atom counts and seeds (spheres), built on
+    `processes` threads of this process.
+
+    Threads, never a process pool: a process forked after the GPU runtime
+    has been initialised inherits its state, and such workers have died
+    with fatal signals.  The heavy parts (pair search, integrals, CSR
+    assembly) run in numpy/scipy code that releases the GIL, so threads are
+    as fast here as processes were."""
     import concurrent.futures
 
     jobs = [(n, s, onsite) for n, s in zip(sizes, seeds)]
-    if processes <= 1 or len(jobs) < 4:
+    if processes <= 1 or len(jobs) < 2:
         return [_make_one(j) for j in jobs]
-    with concurrent.futures.ProcessPoolExecutor(max_workers=processes) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(processes, 16)) as ex:
         return list(ex.map(_make_one, jobs))
 
 

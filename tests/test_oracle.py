@@ -322,6 +322,18 @@ def test_truncated_dos_converges_to_broadened(small):
     assert np.abs(coarse - ref).max() > 1e-3 * ref.max()  # too few terms: visibly different
 
 
+def test_jackson_kernel_hand_values():
+    """Weisse et al. (2006), Jackson kernel for N moments,
+    g_n = [(N - n + 1) cos(pi n/(N+1)) + sin(pi n/(N+1)) cot(pi/(N+1))]/(N+1),
+    evaluated by hand: N = 3 (angle pi/4) gives 1, sqrt(2)/2, 1/4; N = 4
+    (angle pi/5, with cos(pi/5) = (1 + sqrt 5)/4) gives 1, (1 + sqrt 5)/4,
+    sqrt(5)/5, (5 - sqrt 5)/20.  An off-by-one in N or N + 1 changes them."""
+    r5 = np.sqrt(5.0)
+    assert np.allclose(O.jackson_kernel(3), [1.0, np.sqrt(2.0) / 2.0, 0.25], rtol=0, atol=1e-15)
+    assert np.allclose(O.jackson_kernel(4), [1.0, (1.0 + r5) / 4.0, r5 / 5.0, (5.0 - r5) / 20.0],
+                       rtol=0, atol=1e-15)
+
+
 def test_jackson_kernel_and_kpm_dos_properties(small):
     """g_0 = 1 and g_l decreasing to ~0; the KPM DOS is non-negative,
     integrates to g K, and counts the levels in windows wide compared with
