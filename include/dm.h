@@ -403,6 +403,14 @@ dm_status dm_batch_autotune(dm_ctx* ctx, int steps, double* table, int* ntable, 
 dm_status dm_cheb_order(dm_ctx* ctx, double emin, double emax, double mu, double beta, double tol,
                         int max_order, int* order);
 
+/* The paper's expansion-length rule N_C ~ 2 dE beta, dE = (emax - emin)/2
+ * (supplement "Chebyshev expansion"): *order = ceil(2 dE beta) clamped to
+ * [min_order, max_order].  Host arithmetic only; no context.
+ * Errors: DM_E_ARG (emax <= emin, beta <= 0, non-finite, min_order < 2,
+ * max_order < min_order, order NULL). */
+dm_status dm_cheb_order_rule(double emin, double emax, double beta, int min_order, int max_order,
+                             int* order);
+
 /* ---------------------------------------------------------------- predictor
  * A small multilayer perceptron: n_layers affine maps sizes[j] -> sizes[j+1]
  * with tanh between them and a linear output, FP32 weights, mean-squared
@@ -425,6 +433,12 @@ dm_status dm_mlp_train_step(dm_ctx* ctx, const float* X, const float* T, int bat
  *      4 n_e/(g K) - 2), n_mom + 4 floats (host or device). */
 dm_status dm_mlp_features(dm_ctx* ctx, const double* m_stoch, int n_mom, double emin, double emax,
                           double beta, double n_e, long long K, float* x);
+/* Training targets of the predictor, the inverse of dm_mlp_predict's
+ * decoding: y[0] = 10 (mu - Ebar)/dE, y[1] = log2(order)/10 - 1 on the
+ * interval [emin, emax] (host, 2 floats).  No context.
+ * Errors: DM_E_ARG (emax <= emin, order < 1, non-finite, y NULL). */
+dm_status dm_mlp_encode_targets(double mu, double emin, double emax, int order, float* y);
+
 /* mu and expansion order for the loaded operator from its stochastic
  * moments: features as dm_mlp_features with the operator's interval, one
  * forward pass (network n_mom + 4 -> ... -> 2), decoded as

@@ -37,7 +37,7 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
             "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal", "dm_density_on_grid",
             "dm_set_factored_options", "dm_solve_overlap", "dm_get_preconditioner", "dm_cg_stats",
-            "dm_cg_timing"]
+            "dm_cg_timing", "dm_cheb_order_rule", "dm_mlp_encode_targets"]
 
 
 class DMError(RuntimeError):
@@ -142,6 +142,8 @@ def load(path: str = LIB_PATH):
         "dm_mlp_train_step": (_I, [_P, _P, _P, _I, ctypes.c_float, _P]),
         "dm_mlp_features": (_I, [_P, _P, _I, _D, _D, _D, _D, _LL, _P]),
         "dm_mlp_predict": (_I, [_P, _P, _I, _D, _D, _I, _P, _P]),
+        "dm_cheb_order_rule": (_I, [_D, _D, _D, _I, _I, _P]),
+        "dm_mlp_encode_targets": (_I, [_D, _D, _D, _I, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -178,6 +180,28 @@ def tile_shapes():
             raise DMError(DM_E_ARG, f"tile shape {cfg}")
         out.append((r.value, c.value, sp.value))
     return out
+
+
+def dm_cheb_order_rule(emin, emax, beta, min_order=16, max_order=1 << 16):
+    """The paper's expansion length N_C ~ 2 dE beta, clamped (dm_cheb_order_rule)."""
+    lib = load()
+    o = ctypes.c_int()
+    st = lib.dm_cheb_order_rule(float(emin), float(emax), float(beta), int(min_order), int(max_order),
+                                ctypes.byref(o))
+    if st != DM_OK:
+        raise DMError(st, "dm_cheb_order_rule: bad arguments")
+    return o.value
+
+
+def dm_mlp_encode_targets(mu, emin, emax, order):
+    """Predictor targets (2 float32) for (mu, order) on [emin, emax]."""
+    lib = load()
+    y = np.zeros(2, dtype=np.float32)
+    st = lib.dm_mlp_encode_targets(float(mu), float(emin), float(emax), int(order),
+                                   ctypes.c_void_p(y.ctypes.data))
+    if st != DM_OK:
+        raise DMError(st, "dm_mlp_encode_targets: bad arguments")
+    return y
 
 
 def _numel(x):

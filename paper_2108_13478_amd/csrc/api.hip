@@ -2521,6 +2521,25 @@ dm_status dm_cheb_order(dm_ctx* c, double emin, double emax, double mu, double b
     return host_exception(c);
 }
 
+dm_status dm_cheb_order_rule(double emin, double emax, double beta, int min_order, int max_order,
+                             int* order) {
+    if (!order || !std::isfinite(emin) || !std::isfinite(emax) || !(emax > emin) || !(beta > 0) ||
+        !std::isfinite(beta) || min_order < 2 || max_order < min_order)
+        return DM_E_ARG;
+    const double n = std::ceil(2.0 * 0.5 * (emax - emin) * beta);
+    *order = n >= (double)max_order ? max_order : std::max(min_order, (int)n);
+    return DM_OK;
+}
+
+dm_status dm_mlp_encode_targets(double mu, double emin, double emax, int order, float* y) {
+    if (!y || !std::isfinite(mu) || !std::isfinite(emin) || !std::isfinite(emax) || !(emax > emin) || order < 1)
+        return DM_E_ARG;
+    const double ebar = 0.5 * (emax + emin), de = 0.5 * (emax - emin);
+    y[0] = (float)(10.0 * (mu - ebar) / de);
+    y[1] = (float)(std::log2((double)order) / 10.0 - 1.0);
+    return DM_OK;
+}
+
 dm_status dm_mlp_predict(dm_ctx* c, const double* m_stoch, int n_mom, double beta, double n_e,
                          int max_order, double* mu, int* order) try {
     if (!c) return DM_E_ARG;

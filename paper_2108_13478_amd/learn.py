@@ -16,8 +16,6 @@ Targets are encoded as dm_mlp_predict decodes them:
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
 import paper_2108_13478_amd as dmlib
@@ -25,16 +23,6 @@ import paper_2108_13478_amd as dmlib
 N_MOM = 64
 N_VEC = 16
 SIZES = [N_MOM + 4, 128, 128, 128, 2]
-
-
-def encode_targets(mu, emin, emax, order):
-    ebar, de = 0.5 * (emax + emin), 0.5 * (emax - emin)
-    return np.array([10.0 * (mu - ebar) / de, math.log2(order) / 10.0 - 1.0], dtype=np.float32)
-
-
-def paper_order(emin, emax, beta, cap):
-    """The expansion length rule N_C ~ 2 dE beta (supplement "Chebyshev expansion")."""
-    return int(min(cap, max(16, math.ceil(2.0 * 0.5 * (emax - emin) * beta))))
 
 
 def make_dataset(ctx, clusters, betas, probes, label_order, tol_order, max_order, chunk=48, log=None):
@@ -62,7 +50,7 @@ def make_dataset(ctx, clusters, betas, probes, label_order, tol_order, max_order
                 order = ctx.dm_cheb_order(lo, hi, mu[j], beta, tol_order, max_order)
                 order = min(order, max_order)
                 X[i] = ctx.dm_mlp_features(ms[j], lo, hi, beta, cl[j].n_electrons, cl[j].K)
-                T[i] = encode_targets(mu[j], lo, hi, order)
+                T[i] = dmlib.dm_mlp_encode_targets(mu[j], lo, hi, order)
                 rec[i] = dict(K=cl[j].K, beta=float(beta), mu=float(mu[j]), emin=lo, emax=hi, order=int(order))
             if log:
                 log(f"  labels: beta={beta:g} clusters {s}..{s + len(part) - 1} of {len(idx)}")

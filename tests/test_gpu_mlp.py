@@ -153,7 +153,7 @@ def test_trained_network_gain():
         t0 = time.perf_counter()
         p64.set_cluster(c)
         lo, hi = p64.dm_get_bounds()
-        N_rule = learn.paper_order(lo, hi, beta, 8192)
+        N_rule = dmlib.dm_cheb_order_rule(lo, hi, beta, 16, 8192)
         p64.dm_chebyshev_block(cols, N_rule, 0.0, beta, None)
         mu_p = p64.dm_solve_mu(c.n_electrons, beta, tol=1e-6)
         p64.dm_chebyshev_block(cols, N_rule, mu_p, beta, P)
