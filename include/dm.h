@@ -227,6 +227,35 @@ dm_status dm_set_precision(dm_ctx* ctx, int precision);
 dm_status dm_chebyshev_block(dm_ctx* ctx, const long long* cols, long long ncols, int order,
                              double mu, double beta, double* P_out);
 
+/* Allocation-free variant of dm_chebyshev_block, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  One pass over all ncols columns with the
+ * same kernels, tile shape and arithmetic as dm_chebyshev_block on the
+ * general-form or orthonormal operator (DM_E_STATE for the symmetric and
+ * factored forms).  It calls no hipMalloc or hipFree: every pass buffer
+ * (U_l, U_{l-1}, the moment vectors, the P accumulator, the coefficients,
+ * the moment partial sums, a copy of cols) lives in one library-owned device
+ * array of DM_NOALLOC_SCRATCH_BYTES per GPU, resident from library load to
+ * process end.  A call needs about Kp Bp (2 p + 16) + 8 (order + 1)
+ * (Kp Bp / 16384 + 2) + 4 K bytes of it (Kp = K rounded up to 256, Bp =
+ * ncols rounded up to the tile width, p = 8 in FP64 and 4 in FP32), e.g.
+ * K = 4096 with 512 FP64 columns at order 1000; larger calls fail with
+ * DM_E_ARG (the message states the size needed).
+ * cols (int64, host or device): ncols distinct indices in [0, K), checked on
+ * the device.  P_out (host or device, may be NULL): K x ncols column-major
+ * FP64.  m_out (host or device, may be NULL): the order + 1 moments of these
+ * columns; they are NOT added to the context's accumulator (dm_trace and
+ * dm_solve_mu do not see them).  The array is shared by every call on one
+ * GPU and keeps the last call's contents; calls that overlap in time on one
+ * GPU (other threads, other streams) race and must not be issued.
+ * Synchronises the context's stream before returning.
+ * Errors: DM_E_STATE (no operator, other form, array unavailable), DM_E_ARG
+ * (as dm_chebyshev_block, or the call does not fit the array), DM_E_BOUNDS,
+ * DM_E_HIP. */
+#define DM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+dm_status dm_chebyshev_block_noalloc(dm_ctx* ctx, const long long* cols, long long ncols, int order,
+                                     double mu, double beta, double* P_out, double* m_out);
+
 /* From the accumulated moments (exact once every column 0..K-1 has been
  * processed once): tr_PS = Tr[P_N S] = sum_l a_l m_l (eq. Ne without the spin
  * factor) and e_band = g Tr[P_N F] = g sum_l a_l (Ebar m_l + dE (m_{l+1} +

@@ -37,7 +37,7 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
             "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal", "dm_density_on_grid",
             "dm_set_factored_options", "dm_solve_overlap", "dm_get_preconditioner", "dm_cg_stats",
-            "dm_cg_timing", "dm_cheb_order_rule", "dm_mlp_encode_targets"]
+            "dm_cg_timing", "dm_cheb_order_rule", "dm_mlp_encode_targets", "dm_chebyshev_block_noalloc"]
 
 
 class DMError(RuntimeError):
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
         "dm_get_operator": (_I, [_P, _I, _P]),
         "dm_chebyshev_block": (_I, [_P, _P, _LL, _I, _D, _D, _P]),
         "dm_chebyshev_block_multi": (_I, [_P, _P, _LL, _I, _I, _P, _P, _P]),
+        "dm_chebyshev_block_noalloc": (_I, [_P, _P, _LL, _I, _D, _D, _P, _P]),
         "dm_dos": (_I, [_P, _I, _I, _P, _D, _P]),
         "dm_set_operator_form": (_I, [_P, _I]),
         "dm_set_factored_options": (_I, [_P, _D, _I, _D, _I]),
@@ -288,6 +289,19 @@ class Context:
             raise ValueError("P_out too small")
         self._check(self._lib.dm_chebyshev_block(self.h, cp, n, int(order), float(mu), float(beta), pp))
         return P_out
+
+    def dm_chebyshev_block_noalloc(self, cols, order, mu, beta, P_out=None, m_out=None):
+        """Allocation-free pass (library-owned scratch); m_out receives the
+        order + 1 moments of these columns (not accumulated)."""
+        c, kc = _ptr(cols, np.int64)
+        p, kp = (None, None) if P_out is None else _ptr(P_out, np.float64)
+        m, km = (None, None) if m_out is None else _ptr(m_out, np.float64)
+        self._check(self._lib.dm_chebyshev_block_noalloc(self.h, c, _numel(cols), int(order), float(mu),
+                                                         float(beta), p, m))
+        if P_out is not None and kp is not P_out and not hasattr(P_out, "data_ptr"):
+            np.copyto(P_out, kp.reshape(np.shape(P_out)))
+        if m_out is not None and km is not m_out and not hasattr(m_out, "data_ptr"):
+            np.copyto(m_out, km.reshape(np.shape(m_out)))
 
     def dm_chebyshev_block_multi(self, cols, order, mus, betas, P_outs=None):
         """One pass accumulating len(mus) density-matrix blocks; P_outs: None or

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <array>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -34,6 +35,42 @@ struct DevBuf {
 
 long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
 
+}  // namespace
+
+// Device memory of dm_chebyshev_block_noalloc: one array per GPU, resident
+// from the moment the library's code object is loaded on that GPU until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy: the name is a host-side stand-in.  The device address is looked up
+// once per device, with that device current, by noalloc_register (called
+// from dm_init) and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) double dm_noalloc_scratch[kScratchBytes / 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Called with `device` current.  Returns the lookup's status; on failure the
+// device's pointer stays null and the allocation-free entry point refuses.
+hipError_t noalloc_register(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[device]) return g_scratch_ptr[device] ? hipSuccess : hipErrorInvalidSymbol;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(dm_noalloc_scratch));
+    g_scratch_done[device] = true;
+    g_scratch_ptr[device] = (e == hipSuccess) ? ptr : nullptr;
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+}
+
+void* noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 }  // namespace
 
 // One loaded operator: the overlap in CSR, S^-1, H^T = (S^-1 F)^T and H_N in
@@ -798,6 +835,9 @@ dm_status dm_init(dm_ctx** out, const dm_options* opt) try {
         g_init_error = "dm_init: device allocation failed";
         return DM_E_OOM;
     }
+    // the allocation-free entry point's device array (once per device; a
+    // failed lookup only disables that entry point)
+    (void)noalloc_register(o.device);
     *out = c;
     return DM_OK;
 } catch (...) {
@@ -1273,6 +1313,121 @@ dm_status dm_chebyshev_block_multi(dm_ctx* c, const long long* cols, long long n
     std::copy(mu, mu + n_sets, hmu.begin());
     std::copy(beta, beta + n_sets, hbeta.begin());
     return run_pass(c, cols, ncols, order, n_sets, hmu.data(), hbeta.data(), P_out);
+} catch (...) {
+    return host_exception(c);
+}
+
+dm_status dm_chebyshev_block_noalloc(dm_ctx* c, const long long* cols, long long ncols, int order, double mu,
+                                     double beta, double* P_out, double* m_out) try {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded");
+    const Op& op = c->op;
+    if (op.fact || op.form != DM_FORM_GENERAL)
+        return set_err(c, DM_E_STATE, "the allocation-free pass runs on the general (or orthonormal) operator only");
+    if (order < 2 || order > (1 << 20)) return set_err(c, DM_E_ARG, "order must be >= 2");
+    if (!std::isfinite(mu) || !std::isfinite(beta) || !(beta > 0)) return set_err(c, DM_E_ARG, "need finite mu and beta > 0");
+    if (ncols < 0 || ncols > op.K || (ncols > 0 && !cols)) return set_err(c, DM_E_ARG, "bad columns");
+    char* base = static_cast<char*>(noalloc_scratch(c->opt.device));
+    if (!base) return set_err(c, DM_E_STATE, "the allocation-free scratch array is not available on this device");
+    hipStream_t s = c->stream;
+    const long long K = op.K;
+    const int Kp = op.Kp;
+    const int prec = c->precision;
+    const size_t tsz = prec == DM_FP64 ? 8 : 4;
+    // the tile shape dm_chebyshev_block takes for one pass of ncols columns
+    const long long nc = std::max<long long>(ncols, 1);
+    int cfg = pick_cfg(Kp, (int)nc, prec);
+    if (c->opt.block_width == 0 && c->tuned_width > 0 &&
+        cheb_cfg_fits(c->tuned_cfg, prec, Kp, (int)round_up(nc, cheb_tile_cols(c->tuned_cfg))))
+        cfg = c->tuned_cfg;
+    const int BN = cheb_tile_cols(cfg);
+    const int Bp = (int)round_up(nc, std::max(BN, 16));
+    const size_t KB = (size_t)Kp * Bp;
+    const int ntl = cheb_num_tiles(Kp, Bp, cfg);
+    // regions of the scratch array, each 256-byte aligned
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_ua = take(KB * tsz), o_ub = take(KB * tsz), o_z = take(KB * 8), o_p = take(KB * 8);
+    const size_t o_work = take(cheb_work_bytes(Kp, Bp, cfg, prec));
+    const size_t o_steps = take((size_t)(order + 1) * ntl * 8);
+    const size_t o_start = take((size_t)(Kp / 64) * (Bp / 16) * 8);
+    const size_t o_coef = take((size_t)(order + 1) * 8), o_fk = take((size_t)4 * order * 8);
+    const size_t o_mom = take((size_t)(order + 1) * 8), o_cols = take((size_t)Bp * 8);
+    const size_t o_seen = take((size_t)K * 4), o_flag = take(16);
+    if (off > kScratchBytes)
+        return set_err(c, DM_E_ARG, "the allocation-free pass needs " + std::to_string(off) + " bytes of scratch for " +
+                                        std::to_string(ncols) + " columns, order " + std::to_string(order) +
+                                        " and K = " + std::to_string(K) + "; the array holds " +
+                                        std::to_string(kScratchBytes));
+    auto D = [&](size_t o) { return reinterpret_cast<double*>(base + o); };
+    int* flag = reinterpret_cast<int*>(base + o_flag);
+    long long* dcols = reinterpret_cast<long long*>(base + o_cols);
+    double* mom = D(o_mom);
+    int hflag = 0;
+    HIPTRY(c, fill_i32(flag, 0, 4, s));
+    HIPTRY(c, fill_f64(mom, 0.0, order + 1, s));
+    if (ncols > 0) {
+        // columns: copied in (host or device), checked on the device
+        HIPTRY(c, hipMemcpyAsync(dcols, cols, (size_t)ncols * 8, hipMemcpyDefault, s));
+        HIPTRY(c, fill_i32(reinterpret_cast<int*>(base + o_seen), 0, K, s));
+        HIPTRY(c, check_columns(dcols, ncols, K, reinterpret_cast<int*>(base + o_seen), flag, s));
+        HIPTRY(c, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPTRY(c, hipStreamSynchronize(s));
+        if (hflag & 2) return set_err(c, DM_E_ARG, "column index out of range");
+        if (hflag & 4) return set_err(c, DM_E_ARG, "repeated column index");
+        const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
+        const int M = 4 * order;
+        const long long pstride = (long long)KB;
+        HIPTRY(c, cheb_coefficients(order, M, ebar, de, mu, beta, D(o_fk), D(o_coef), s));
+        HIPTRY(c, fill_f64(D(o_z), 0.0, (long long)KB, s));
+        int nts = 0;
+        HIPTRY(c, cheb_start((int)K, Kp, Bp, (int)ncols, dcols, op.orth ? nullptr : op.Sinv.p, op.S_rowptr.p,
+                             op.S_col.p, op.S_val.p, prec, base + o_ua, D(o_z), D(o_p), D(o_coef), 1, pstride,
+                             order + 1, D(o_start), &nts, s));
+        HIPTRY(c, reduce_moments(0, nts, D(o_start), mom, flag, s));
+        void* ucur = base + o_ua;
+        void* uoth = base + o_ub;
+        ChebStepArgs a{};
+        a.Kp = Kp;
+        a.Bp = Bp;
+        a.HN = op.HNbuf.p;
+        a.coef = D(o_coef);
+        a.P = D(o_p);
+        a.Z = D(o_z);
+        a.partial = D(o_steps);
+        a.work = D(o_work);
+        a.nsets = 1;
+        a.cstride = order + 1;
+        a.pstride = pstride;
+        for (int l = 1; l <= order; ++l) {
+            a.Ucur = ucur;
+            a.Uprev = (l == 1) ? nullptr : uoth;
+            a.Unext = uoth;
+            a.alpha = (l == 1) ? 1.0 : 2.0;
+            a.has_prev = (l > 1);
+            a.l = l;
+            const hipError_t e = prec == DM_FP64 ? cheb_step_f64(a, cfg, s) : cheb_step_f32(a, cfg, s);
+            if (e != hipSuccess) return fail_hip(c, e, "cheb_step");
+            std::swap(ucur, uoth);
+        }
+        HIPTRY(c, reduce_moments(order - 1, ntl, D(o_steps) + ntl, mom + 1, flag, s));
+        HIPTRY(c, flag_large(mom, order + 1, 1e8 * (double)(ncols + 1), flag, s));
+        if (P_out)
+            HIPTRY(c, hipMemcpy2DAsync(P_out, (size_t)K * 8, D(o_p), (size_t)Kp * 8, (size_t)K * 8, (size_t)ncols,
+                                       hipMemcpyDefault, s));
+    }
+    if (m_out) HIPTRY(c, hipMemcpyAsync(m_out, mom, (size_t)(order + 1) * 8, hipMemcpyDefault, s));
+    HIPTRY(c, hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    if (hflag & 1)
+        return set_err(c, DM_E_BOUNDS, "Chebyshev recursion diverged: the spectral interval does not enclose the spectrum");
+    return DM_OK;
 } catch (...) {
     return host_exception(c);
 }

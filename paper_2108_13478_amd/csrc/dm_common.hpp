@@ -213,6 +213,12 @@ hipError_t density_on_grid(const GridArgs& a, hipStream_t s);
 hipError_t permute_rows(int K, long long ncols, const int* perm, const double* src, double* dst, hipStream_t s);
 
 // ----------------------------------------------------------------- setup
+// flag[0] |= 2 for a column outside [0, K), |= 4 for a repeated one; seen
+// holds K ints, zero on entry
+hipError_t check_columns(const long long* cols, long long ncols, long long K, int* seen, int* flag,
+                         hipStream_t s);
+// flag[0] |= 1 when some |x_i| > lim or x_i is not finite
+hipError_t flag_large(const double* x, long long n, double lim, int* flag, hipStream_t s);
 hipError_t fill_f64(double* x, double v, long long n, hipStream_t s);
 hipError_t fill_i32(int* x, int v, long long n, hipStream_t s);
 // D (Kp x Kp col-major, zero on entry) gets the CSR matrix; padded diagonal

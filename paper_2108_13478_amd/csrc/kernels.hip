@@ -40,6 +40,27 @@ __global__ void fill_i32_kernel(int* x, int v, long long n) {
         x[i] = v;
 }
 
+// flag[0] |= 2 for a column index outside [0, K), |= 4 for a repeated one
+// (seen: K zeroed ints)
+__global__ void check_columns_kernel(const long long* __restrict__ cols, long long ncols, long long K,
+                                     int* __restrict__ seen, int* flag) {
+    for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < ncols;
+         j += (long long)gridDim.x * blockDim.x) {
+        const long long x = cols[j];
+        if (x < 0 || x >= K)
+            atomicOr(flag, 2);
+        else if (atomicAdd(seen + x, 1) != 0)
+            atomicOr(flag, 4);
+    }
+}
+
+// flag[0] |= 1 when some |x_i| exceeds lim or is not finite
+__global__ void flag_large_kernel(const double* __restrict__ x, long long n, double lim, int* flag) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        if (!(fabs(x[i]) <= lim)) atomicOr(flag, 1);
+}
+
 inline dim3 grid_for(long long n, int bs) {
     long long g = (n + bs - 1) / bs;
     if (g > 65536) g = 65536;
@@ -557,6 +578,19 @@ hipError_t fill_f64(double* x, double v, long long n, hipStream_t s) {
 hipError_t fill_i32(int* x, int v, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32_kernel, grid_for(n, 256), dim3(256), 0, s, x, v, n);
+    return hipGetLastError();
+}
+
+hipError_t check_columns(const long long* cols, long long ncols, long long K, int* seen, int* flag,
+                         hipStream_t s) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(check_columns_kernel, grid_for(ncols, 256), dim3(256), 0, s, cols, ncols, K, seen, flag);
+    return hipGetLastError();
+}
+
+hipError_t flag_large(const double* x, long long n, double lim, int* flag, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(flag_large_kernel, grid_for(n, 256), dim3(256), 0, s, x, n, lim, flag);
     return hipGetLastError();
 }
 
