@@ -51,12 +51,18 @@ typedef enum {
     DM_E_NOCONV = -7   /* iteration did not reach its tolerance */
 } dm_status;
 
-enum { DM_FP64 = 0, DM_FP32 = 1 };
+/* Precision of H_N and the recursion vectors U_l.  DM_FP32_ACC64 is the
+ * refined FP32 path: H_N and U_l are stored in FP32 (half the bytes of
+ * FP64), every product and sum runs in FP64 (an FP32 x FP32 product is
+ * exact in FP64), and U_{l+1} is rounded to FP32 once, when stored.  It
+ * removes the FP32 accumulation error of DM_FP32; the rounding of H_N and
+ * U_l to FP32 remains.  Not for the batch or the factored form. */
+enum { DM_FP64 = 0, DM_FP32 = 1, DM_FP32_ACC64 = 2 };
 
 typedef struct {
     int device;              /* HIP device ordinal */
     void* stream;            /* hipStream_t to order work on; NULL = library-owned stream */
-    int precision;           /* DM_FP64 or DM_FP32: storage and arithmetic of H_N and U_l.
+    int precision;           /* DM_FP64, DM_FP32 or DM_FP32_ACC64: storage and arithmetic of H_N and U_l.
                                 P and the moments are always accumulated in FP64. */
     int block_width;         /* columns advanced together per pass; 0 = library choice */
     double spin;             /* g in N_e = g Tr[PS] (eq. Ne); the paper uses 2 */
@@ -205,7 +211,7 @@ dm_status dm_cg_stats(dm_ctx* ctx, long long* solves, long long* iterations, int
  * Errors: DM_E_STATE (no factored operator loaded). */
 dm_status dm_cg_timing(dm_ctx* ctx, int enable, long long* launches, double* ms);
 
-/* Switch the recursion precision (DM_FP64 / DM_FP32) of a loaded operator;
+/* Switch the recursion precision (DM_FP64 / DM_FP32 / DM_FP32_ACC64) of a loaded operator;
  * resets the accumulated moments and forgets a tuned or pinned pass shape.
  * A loaded batch keeps only its H_N and so the precision it was loaded in:
  * the batch calls return DM_E_STATE until dm_batch_set_focks is called
@@ -369,8 +375,10 @@ int dm_num_tile_shapes(void);
 dm_status dm_tile_shape(int cfg, int* rows, int* cols, int* split);
 
 /* ---------------------------------------------------------------- batch
- * Many independent clusters (the paper distributes unit vectors u_a over
- * processors, parallelisation section; here uneven clusters share one GPU). */
+ * Many independent clusters on one GPU.  Not in the paper, which splits the
+ * unit vectors u_a of one system over processors (parallelisation
+ * section); here each cluster is a separate problem with its own F, S and
+ * mu, and uneven clusters share one persistent launch. */
 typedef struct {
     long long K;
     const long long* F_rowptr;
@@ -399,6 +407,18 @@ enum { DM_BATCH_EAGER = 1, DM_BATCH_MOMENTS_ONLY = 2 };
  * m_out (host) receives n x n_mom values, cluster-major. */
 dm_status dm_batch_stoch_moments(dm_ctx* ctx, int n_mom, int n_vec, const double* const* xi,
                                  double* m_out);
+
+/* Precision of the moments pass of dm_batch_run (and so of each cluster's
+ * mu) for batches loaded afterwards: -1 (default) = the recursion
+ * precision; DM_FP64 under an FP32 recursion keeps an FP64 H_N of every
+ * cluster beside the FP32 one (three times the FP32 operator memory), runs
+ * the moments pass in FP64 and only the P pass in FP32.  The FP32 rounding
+ * of H_N shifts the trace Tr[P_N S] by far more than an electron-count
+ * tolerance of 1e-6 (hundredths of an electron at K ~ 4000 with spectra of
+ * +-1000 hartree), so a mu that must reproduce N_e to such a tolerance
+ * needs FP64 moments.  DM_FP32 under an FP64 recursion is the same as -1.
+ * Errors: DM_E_ARG (other value). */
+dm_status dm_set_moments_precision(dm_ctx* ctx, int precision);
 
 /* Full density matrices of every cluster: first a moments-only pass over all
  * columns of all clusters (one persistent launch: workgroups take

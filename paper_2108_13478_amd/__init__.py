@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdm.so")
 
 DM_OK, DM_E_ARG, DM_E_STATE, DM_E_HIP, DM_E_OOM, DM_E_NOTSPD, DM_E_BOUNDS, DM_E_NOCONV = (
     0, -1, -2, -3, -4, -5, -6, -7)
-DM_FP64, DM_FP32 = 0, 1
+DM_FP64, DM_FP32, DM_FP32_ACC64 = 0, 1, 2
 DM_OP_SINV, DM_OP_H, DM_OP_HSYM = 0, 1, 2
 DM_FORM_GENERAL, DM_FORM_SYMMETRIC, DM_FORM_FACTORED = 0, 1, 2
 DM_DOS_GAUSSIAN, DM_DOS_KPM = 0, 1
@@ -37,7 +37,8 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_set_pass_shape", "dm_num_tile_shapes", "dm_tile_shape", "dm_chebyshev_block_multi",
             "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal", "dm_density_on_grid",
             "dm_set_factored_options", "dm_solve_overlap", "dm_get_preconditioner", "dm_cg_stats",
-            "dm_cg_timing", "dm_cheb_order_rule", "dm_mlp_encode_targets", "dm_chebyshev_block_noalloc"]
+            "dm_cg_timing", "dm_cheb_order_rule", "dm_mlp_encode_targets",
+            "dm_set_moments_precision", "dm_chebyshev_block_noalloc"]
 
 
 class DMError(RuntimeError):
@@ -144,6 +145,7 @@ def load(path: str = LIB_PATH):
         "dm_mlp_features": (_I, [_P, _P, _I, _D, _D, _D, _D, _LL, _P]),
         "dm_mlp_predict": (_I, [_P, _P, _I, _D, _D, _I, _P, _P]),
         "dm_cheb_order_rule": (_I, [_D, _D, _D, _I, _I, _P]),
+        "dm_set_moments_precision": (_I, [_P, _I]),
         "dm_mlp_encode_targets": (_I, [_D, _D, _D, _I, _P]),
     }
     for name, (res, args) in sig.items():
@@ -450,6 +452,9 @@ class Context:
         self._check(self._lib.dm_set_pass_shape(self.h, int(width), int(cfg)))
 
     # ---------------------------------------------------------------- batch
+    def dm_set_moments_precision(self, precision):
+        self._check(self._lib.dm_set_moments_precision(self.h, int(precision)))
+
     def dm_batch_set_focks(self, clusters):
         """clusters: sequence of objects with K and F_/S_ rowptr, col, val."""
         keep = []

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdm.so")
-SOURCES = ["gemm.hip", "kernels.hip", "mlp.hip", "grid.hip", "factored.hip", "api.hip"]
+SOURCES = ["gemm.hip", "kernels.hip", "mlp.hip", "grid.hip", "factored.hip", "symform.hip", "api.hip"]
 ARCH = os.environ.get("DM_OFFLOAD_ARCH", "gfx950")
 
 

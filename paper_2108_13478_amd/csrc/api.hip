@@ -87,9 +87,16 @@ struct Op {
     DevBuf<double> Sinv;   // Kp x Kp, S^-1
     DevBuf<double> HT;     // Kp x Kp, (S^-1 F)^T column-major = H row-major
     DevBuf<double> HNbuf;  // Kp x Kp of the recursion precision (FP64 slots reused for FP32)
-    // symmetric form (DM_FORM_SYMMETRIC): S = U^T U, L = U^-T, Hsym = L F L^T
+    DevBuf<double> HN64;   // batch with FP64 moments under an FP32 recursion: H_N in FP64
+    // symmetric form (DM_FORM_SYMMETRIC): S = U^T U; only X = U^-1 (upper,
+    // FP64) is kept beside H~_N = (X^T F X - Ebar) / dE in HNbuf (F in CSR
+    // below, to rebuild H~_N for other bounds or another precision).
+    // sym_raw: HNbuf still holds H~ itself (between its panels and the
+    // Lanczos interval)
     int form = DM_FORM_GENERAL;
-    DevBuf<double> Lsym, Usym, Hsym;
+    DevBuf<double> Xs;
+    bool sym_raw = false;
+    int hn_precision_raw = -1;
     // orthonormal basis (dm_set_fock_orthonormal): S = I, H = F kept in CSR
     // (S_* then hold the identity), no dense S^-1 / H^T
     bool orth = false;
@@ -104,8 +111,9 @@ struct Op {
         if (fact) fact_destroy(fact);
         fact = nullptr;
         S_rowptr.release(); S_col.release(); S_val.release();
-        Sinv.release(); HT.release(); HNbuf.release();
-        Lsym.release(); Usym.release(); Hsym.release();
+        Sinv.release(); HT.release(); HNbuf.release(); HN64.release();
+        Xs.release();
+        sym_raw = false;
         F_rowptr.release(); F_col.release(); F_val.release();
         K = 0; Kp = 0; form = DM_FORM_GENERAL; orth = false;
     }
@@ -140,6 +148,9 @@ struct dm_ctx {
     int tuned_cfg = -1;
     // operator form used by the next dm_set_fock
     int form = DM_FORM_GENERAL;
+    // precision of the batch's moments pass for batches loaded afterwards
+    // (-1: the recursion precision)
+    int batch_mom_prec = -1;
     // factored form: solve tolerance and iteration limit, FSAI pattern
     double cg_tol = 1e-11;
     int cg_max_iter = 2000;
@@ -171,6 +182,13 @@ struct BatchState {
     int n_items = 0;
     int cfg = 0;
     int table_cfg = -1, table_order = -1, table_prec = -1;
+    // moments pass in FP64 under an FP32 recursion: its own tile shape,
+    // cluster table (H_N in FP64) and item list
+    int mom_prec = -1;  // precision of the moments pass (set at load)
+    int cfg_m = -1;
+    DevBuf<BatchCluster> d_clusters_m;
+    DevBuf<BatchItem> d_items_m;
+    int n_items_m = 0;
     // captured graph and the parameters it was captured with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -194,6 +212,8 @@ struct BatchState {
         for (auto& b : cl) b.cols.release();
         d_clusters.release();
         d_items.release();
+        d_clusters_m.release();
+        d_items_m.release();
         counter.release();
     }
 };
@@ -397,6 +417,13 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
     const long long* rp = op.S_rowptr.p;
     const int* ci = op.S_col.p;
     const double* sv = op.S_val.p;
+    // the symmetric form's H~ (in HNbuf, before normalisation) with the
+    // standard inner product; every other form H = S^-1 F with the S one
+    const bool ident = op.form == DM_FORM_SYMMETRIC;
+    auto apply_s = [&](const double* x, double* y) -> hipError_t {
+        if (ident) return hipMemcpyAsync(y, x, (size_t)K * 8, hipMemcpyDeviceToDevice, s);
+        return csr_spmv(K, rp, ci, sv, x, y, s);
+    };
 #define LZ(expr)                          \
     do {                                  \
         if ((e = (expr)) != hipSuccess) { \
@@ -405,13 +432,15 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
         }                                 \
     } while (0)
     LZ(random_vector(K, c->opt.seed, V.p, s));
-    LZ(csr_spmv(K, rp, ci, sv, V.p, Q.p, s));
+    LZ(apply_s(V.p, Q.p));
     LZ(dots_cols(K, 1, V.p, ld, Q.p, sc.p, s));
     LZ(lanczos_normalize_start(K, V.p, Q.p, sc.p, s));
     for (int j = 0; j < ksteps; ++j) {
         double* vj = V.p + (size_t)j * ld;
         double* qj = Q.p + (size_t)j * ld;
-        if (op.orth) {
+        if (ident) {
+            LZ(gemv_rows_t(K, c->precision, op.HNbuf.p, ld, vj, wv.p, s));
+        } else if (op.orth) {
             LZ(csr_spmv(K, op.F_rowptr.p, op.F_col.p, op.F_val.p, vj, wv.p, s));
         } else if (op.fact) {
             // solves to at most 1e-8: the eigenvalue error this leaves (~1e-8
@@ -431,7 +460,7 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
             LZ(dots_cols(K, j + 1, Q.p, ld, wv.p, cc.p, s));
             LZ(lanczos_reorth(K, j + 1, wv.p, V.p, ld, cc.p, s));
         }
-        LZ(csr_spmv(K, rp, ci, sv, wv.p, sw.p, s));
+        LZ(apply_s(wv.p, sw.p));
         LZ(dots_cols(K, 1, wv.p, ld, sw.p, sc.p + 1, s));
         LZ(lanczos_next(K, wv.p, sw.p, sc.p + 1, beta + j, V.p + (size_t)(j + 1) * ld,
                         Q.p + (size_t)(j + 1) * ld, s));
@@ -472,6 +501,8 @@ dm_status lanczos_bounds(dm_ctx* c, Op& op) {
     return DM_OK;
 }
 
+dm_status sym_panels(dm_ctx* c, Op& op, double ebar, double de, int precision, void* dst);
+
 dm_status normalize(dm_ctx* c, Op& op) {
     const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
     if (op.form == DM_FORM_FACTORED) {  // H_N is applied, never formed
@@ -486,8 +517,23 @@ dm_status normalize(dm_ctx* c, Op& op) {
         op.hn_precision = c->precision;
         return DM_OK;
     }
-    const double* H = op.form == DM_FORM_SYMMETRIC ? op.Hsym.p : op.HT.p;  // both row-major
-    HIPTRY(c, normalize_operator((int)op.K, op.Kp, H, ebar, de, c->precision, op.HNbuf.p, c->stream));
+    if (op.form == DM_FORM_SYMMETRIC) {
+        const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
+        if (op.sym_raw && op.hn_precision_raw == c->precision) {
+            // right after the panels: H~ -> H~_N in place
+            HIPTRY(c, normalize_inplace((int)op.K, op.Kp, c->precision, op.HNbuf.p, ebar, de, c->stream));
+        } else {
+            // new bounds or precision: H~_N again from X and F (exact, no
+            // second rounding of the stored H~_N)
+            HIPTRY(c, ensure(op.HNbuf, (size_t)op.Kp * op.Kp * tsz / 8));
+            dm_status st = sym_panels(c, op, ebar, de, c->precision, op.HNbuf.p);
+            if (st != DM_OK) return st;
+        }
+        op.sym_raw = false;
+        op.hn_precision = c->precision;
+        return DM_OK;
+    }
+    HIPTRY(c, normalize_operator((int)op.K, op.Kp, op.HT.p, ebar, de, c->precision, op.HNbuf.p, c->stream));
     op.hn_precision = c->precision;
     return DM_OK;
 }
@@ -517,11 +563,14 @@ dm_status reset_moments(dm_ctx* c) {
 int pick_cfg(int Kp, int ncols, int precision) {
     static const int kPrefF64[] = {12, 36, 33, 32, 1, 2, 3};
     static const int kPrefF32[] = {12, 31, 29, 30, 1, 2, 3};
+    static const int kPrefW32[] = {12, 0, 29, 30, 20, 7, 2, 3};
     static const int kSplit[] = {18, 14, 13};
     const int n = std::max(ncols, 1);
     const int n32 = (int)round_up(n, 32);
-    const int* pref = precision == DM_FP64 ? kPrefF64 : kPrefF32;
-    const int npref = precision == DM_FP64 ? (int)(sizeof(kPrefF64) / sizeof(int)) : (int)(sizeof(kPrefF32) / sizeof(int));
+    const int* pref = precision == DM_FP64 ? kPrefF64 : precision == DM_FP32 ? kPrefF32 : kPrefW32;
+    const int npref = precision == DM_FP64   ? (int)(sizeof(kPrefF64) / sizeof(int))
+                      : precision == DM_FP32 ? (int)(sizeof(kPrefF32) / sizeof(int))
+                                             : (int)(sizeof(kPrefW32) / sizeof(int));
     for (int i = 0; i < npref; ++i) {
         const int cfg = pref[i];
         const int Bp = (int)round_up(n, cheb_tile_cols(cfg));
@@ -599,19 +648,15 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
     HIPTRY(c, hipMemcpyAsync(op.S_val.p, sval.data(), sval.size() * 8, hipMemcpyHostToDevice, s));
     DevBuf<long long> Frp;
     DevBuf<int> Fci;
-    DevBuf<double> Fv, Vblk, tmp, G;
-    auto release_tmp = [&]() { Frp.release(); Fci.release(); Fv.release(); Vblk.release(); tmp.release(); G.release(); };
-    const bool sym = form == DM_FORM_SYMMETRIC;
+    DevBuf<double> Fv, Vblk, tmp;
+    auto release_tmp = [&]() { Frp.release(); Fci.release(); Fv.release(); Vblk.release(); tmp.release(); };
+    (void)form;
     op.form = DM_FORM_GENERAL;
     op.orth = false;
     op.F_rowptr.release();
     op.F_col.release();
     op.F_val.release();
-    if (!sym) {
-        op.Lsym.release();
-        op.Usym.release();
-        op.Hsym.release();
-    }
+    op.Xs.release();
     hipError_t e;
 #define ST(expr)                          \
     do {                                  \
@@ -661,10 +706,6 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
         return set_err(c, DM_E_NOTSPD, "overlap matrix is not positive definite (pivot " +
                                            std::to_string(info[0] - 1) + ")");
     }
-    if (sym) {
-        ST(ensure(op.Usym, KK));
-        ST(copy_upper(Kp, A, op.Usym.p, s));
-    }
     // ---- X = U^-T (lower) by block forward substitution
     ST(fill_f64(X, 0.0, (long long)KK, s));
     for (int k = 0; k < Kp; k += kNb) {
@@ -675,31 +716,140 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
         }
         ST(copy_transpose_block(Vk, kNb, X + k + (long)k * ld, ld, s));
     }
-    if (sym) {
-        ST(ensure(op.Lsym, KK));
-        ST(hipMemcpyAsync(op.Lsym.p, X, KK * 8, hipMemcpyDeviceToDevice, s));
-    }
     // ---- S^-1 = X^T X, then A := F and H^T = F S^-1
     ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, X, ld, X, ld, 0.0, op.Sinv.p, ld, false, s));
     ST(fill_f64(A, 0.0, (long long)KK, s));
     ST(csr_to_dense((int)K, Kp, Frp.p, Fci.p, Fv.p, 0.0, A, s));
     ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, A, ld, op.Sinv.p, ld, 0.0, X, ld, false, s));
-    if (sym) {
-        // W = L^T (column-major) in Hsym, G = F L^T, Hsym := W^T G = L F L^T
-        // (symmetric, so its column-major and row-major layouts coincide)
-        ST(ensure(op.Hsym, KK));
-        ST(ensure(G, KK));
-        ST(transpose_square(Kp, op.Lsym.p, op.Hsym.p, s));
-        ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, A, ld, op.Hsym.p, ld, 0.0, G.p, ld, false, s));
-        ST(gemm_tn_f64(Kp, Kp, Kp, 1.0, op.Hsym.p, ld, G.p, ld, 0.0, A, ld, false, s));
-        ST(hipMemcpyAsync(op.Hsym.p, A, KK * 8, hipMemcpyDeviceToDevice, s));
-    }
     ST(hipStreamSynchronize(s));
     release_tmp();
 #undef ST
     dm_status st = lanczos_bounds(c, op);
     if (st != DM_OK) return st;
-    op.form = sym ? DM_FORM_SYMMETRIC : DM_FORM_GENERAL;
+    op.form = DM_FORM_GENERAL;
+    return normalize(c, op);
+}
+
+// H~_N = (X^T F X - ebar I) / de (ebar = 0, de = 1: H~ itself) into dst in
+// `precision`, by column panels J of width w: P = X[:, J] transposed to a
+// row-major panel (X[:, J] is zero below row max J), Y = F P by the CSR
+// product, Y back to column-major, then X^T Y on the MFMA (X upper: row tile
+// r sums k <= r only) and the panel stored with the shift and scale.
+dm_status sym_panels(dm_ctx* c, Op& op, double ebar, double de, int precision, void* dst) {
+    hipStream_t s = c->stream;
+    const int Kp = op.Kp;
+    const long ld = Kp;
+    const int w = std::min(Kp, 1024);
+    DevBuf<double> pa, pb;
+    hipError_t e = ensure(pa, (size_t)Kp * w);
+    if (e == hipSuccess) e = ensure(pb, (size_t)Kp * w);
+    for (int j0 = 0; j0 < Kp && e == hipSuccess; j0 += w) {
+        const int kmax = j0 + w;
+        e = transpose_rect(kmax, w, op.Xs.p + (long)j0 * ld, ld, pa.p, w, s);
+        if (e == hipSuccess)
+            e = csr_spmm_rm((int)op.K, op.F_rowptr.p, op.F_col.p, op.F_val.p, w, pa.p, kmax, pb.p, s);
+        if (e == hipSuccess && Kp > op.K) e = fill_f64(pb.p + (size_t)op.K * w, 0.0, (long long)(Kp - op.K) * w, s);
+        if (e == hipSuccess) e = transpose_rect(w, Kp, pb.p, w, pa.p, Kp, s);
+        if (e == hipSuccess) e = gemm_tn_f64(Kp, w, Kp, 1.0, op.Xs.p, ld, pa.p, Kp, 0.0, pb.p, Kp, false, s, true);
+        if (e == hipSuccess) e = store_panel((int)op.K, Kp, w, j0, pb.p, ebar, 1.0 / de, precision, dst, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    pa.release();
+    pb.release();
+    if (e != hipSuccess) return fail_hip(c, e, "symmetric operator panels");
+    return DM_OK;
+}
+
+// Operator setup of the symmetric form, in place: S = U^T U is factored in
+// the one FP64 K x K array op.Xs, which then becomes X = U^-1 (blocked
+// left-looking inversion: with the leading block already inverted,
+// X12 = -X11 U12 U22^-1, the diagonal blocks' inverses coming from the
+// Cholesky).  H~ = X^T F X (= L F L^T with L = U^-T, the same spectrum as
+// S^-1 F) is formed by sym_panels straight into the recursion-precision
+// array HNbuf, the Lanczos interval comes from H~ with the standard inner
+// product, and H~ is normalised in place.  Device memory: K^2 (8 + p) bytes
+// (p = 8 or 4 for the recursion precision) plus panels and the CSR arrays.
+dm_status build_sym(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const HostCsr& Sh) {
+    hipStream_t s = c->stream;
+    op.release();
+    op.K = K;
+    op.Kp = (int)round_up(K, kRowPad);
+    const int Kp = op.Kp;
+    const size_t KK = (size_t)Kp * Kp;
+    const long ld = Kp;
+    const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
+    HIPTRY(c, ensure(op.S_rowptr, (size_t)K + 1));
+    HIPTRY(c, ensure(op.S_col, Sh.col.size()));
+    HIPTRY(c, ensure(op.S_val, Sh.val.size()));
+    HIPTRY(c, ensure(op.F_rowptr, (size_t)K + 1));
+    HIPTRY(c, ensure(op.F_col, Fh.col.size()));
+    HIPTRY(c, ensure(op.F_val, Fh.val.size()));
+    HIPTRY(c, hipMemcpyAsync(op.S_rowptr.p, Sh.rp.data(), Sh.rp.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.S_col.p, Sh.col.data(), Sh.col.size() * 4, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.S_val.p, Sh.val.data(), Sh.val.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.F_rowptr.p, Fh.rp.data(), Fh.rp.size() * 8, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.F_col.p, Fh.col.data(), Fh.col.size() * 4, hipMemcpyHostToDevice, s));
+    HIPTRY(c, hipMemcpyAsync(op.F_val.p, Fh.val.data(), Fh.val.size() * 8, hipMemcpyHostToDevice, s));
+    DevBuf<double> Vblk, tmp;
+    auto release_tmp = [&]() { Vblk.release(); tmp.release(); };
+    hipError_t e;
+#define ST(expr)                          \
+    do {                                  \
+        if ((e = (expr)) != hipSuccess) { \
+            release_tmp();                \
+            return fail_hip(c, e, #expr); \
+        }                                 \
+    } while (0)
+    ST(ensure(op.Xs, KK));
+    ST(ensure(op.HNbuf, KK * tsz / 8));
+    ST(ensure(Vblk, (size_t)Kp * kNb));
+    ST(ensure(tmp, (size_t)Kp * kNb));
+    double* A = op.Xs.p;
+    ST(fill_f64(A, 0.0, (long long)KK, s));
+    ST(csr_to_dense((int)K, Kp, op.S_rowptr.p, op.S_col.p, op.S_val.p, 1.0, A, s));
+    ST(fill_i32(c->flag.p, 0, 4, s));
+    // ---- blocked Cholesky S = U^T U (upper, right-looking), as in build_op
+    for (int k = 0; k < Kp; k += kNb) {
+        double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
+        ST(potrf_diag(A + k + (long)k * ld, ld, Vk, c->flag.p, k, s));
+        const int n2 = Kp - k - kNb;
+        if (n2 > 0) {
+            ST(gemm_tn_f64(kNb, n2, kNb, 1.0, Vk, kNb, A + k + (long)(k + kNb) * ld, ld, 0.0, tmp.p, kNb, false, s));
+            ST(hipMemcpy2DAsync(A + k + (long)(k + kNb) * ld, ld * 8, tmp.p, kNb * 8, kNb * 8, n2,
+                                hipMemcpyDeviceToDevice, s));
+            ST(gemm_tn_f64(n2, n2, kNb, -1.0, tmp.p, kNb, tmp.p, kNb, 1.0, A + (k + kNb) + (long)(k + kNb) * ld, ld,
+                           true, s));
+        }
+    }
+    int info[4] = {0, 0, 0, 0};
+    ST(hipMemcpyAsync(info, c->flag.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    if (info[0] != 0) {
+        release_tmp();
+        return set_err(c, DM_E_NOTSPD,
+                       "overlap matrix is not positive definite (pivot " + std::to_string(info[0] - 1) + ")");
+    }
+    // ---- X = U^-1 in place (the trailing updates left S below the diagonal)
+    ST(zero_strict_lower(Kp, A, s));
+    for (int k = 0; k < Kp; k += kNb) {
+        const double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
+        if (k > 0) {
+            // tmp = X11 U12, then X12 = -tmp U22^-1 (U22^-1 from the Cholesky)
+            ST(gemm_nn_f64(k, kNb, k, 1.0, A, ld, A + (long)k * ld, ld, 0.0, tmp.p, Kp, true, s));
+            ST(gemm_nn_f64(k, kNb, kNb, -1.0, tmp.p, Kp, Vk, kNb, 0.0, A + (long)k * ld, ld, false, s));
+        }
+        ST(set_upper_block(kNb, A + k + (long)k * ld, ld, Vk, s));
+    }
+    ST(hipStreamSynchronize(s));
+    release_tmp();
+#undef ST
+    op.form = DM_FORM_SYMMETRIC;
+    dm_status st = sym_panels(c, op, 0.0, 1.0, c->precision, op.HNbuf.p);
+    if (st != DM_OK) return st;
+    op.sym_raw = true;
+    op.hn_precision_raw = c->precision;
+    st = lanczos_bounds(c, op);
+    if (st != DM_OK) return st;
     return normalize(c, op);
 }
 
@@ -795,7 +945,7 @@ dm_status dm_init(dm_ctx** out, const dm_options* opt) try {
         o = *opt;
     else
         dm_default_options(&o);
-    if ((o.precision != DM_FP64 && o.precision != DM_FP32) || o.block_width < 0 ||
+    if ((o.precision != DM_FP64 && o.precision != DM_FP32 && o.precision != DM_FP32_ACC64) || o.block_width < 0 ||
         !(o.spin > 0) || o.lanczos_steps < 0 || o.device < 0) {
         g_init_error = "dm_init: invalid option";
         return DM_E_ARG;
@@ -885,7 +1035,9 @@ dm_status dm_set_fock(dm_ctx* c, long long K, const long long* F_rowptr, const i
     HostCsr Fh, Sh;
     st = load_csr_pair(c, K, F_rowptr, F_col, F_val, S_rowptr, S_col, S_val, Fh, Sh);
     if (st != DM_OK) return st;
-    st = c->form == DM_FORM_FACTORED ? build_fact(c, c->op, K, Fh, Sh) : build_op(c, c->op, K, Fh, Sh, c->form);
+    st = c->form == DM_FORM_FACTORED    ? build_fact(c, c->op, K, Fh, Sh)
+         : c->form == DM_FORM_SYMMETRIC ? build_sym(c, c->op, K, Fh, Sh)
+                                        : build_op(c, c->op, K, Fh, Sh, c->form);
     if (st != DM_OK) return st;
     c->have_fock = true;
     return DM_OK;
@@ -1051,9 +1203,39 @@ dm_status dm_get_operator(dm_ctx* c, int which, double* out) try {
     if (c->op.fact) return set_err(c, DM_E_STATE, "a factored operator keeps no dense setup products");
     const size_t K = (size_t)c->op.K, Kp = (size_t)c->op.Kp;
     hipStream_t s = c->stream;
+    if (c->op.form == DM_FORM_SYMMETRIC) {
+        // formed on request from X = U^-1 and F: S^-1 = X X^T, H = X X^T F,
+        // H~ = X^T F X (two K x K FP64 work arrays)
+        const Op& op = c->op;
+        const int kp = op.Kp;
+        DevBuf<double> W, T;
+        hipError_t e = ensure(W, Kp * Kp);
+        if (e == hipSuccess) e = ensure(T, Kp * Kp);
+        if (e == hipSuccess && which == DM_OP_SINV) {
+            e = transpose_square(kp, op.Xs.p, W.p, s);
+            if (e == hipSuccess) e = gemm_tn_f64(kp, kp, kp, 1.0, W.p, kp, W.p, kp, 0.0, T.p, kp, false, s);
+        } else if (e == hipSuccess) {
+            e = fill_f64(W.p, 0.0, (long long)(Kp * Kp), s);
+            if (e == hipSuccess) e = csr_to_dense((int)K, kp, op.F_rowptr.p, op.F_col.p, op.F_val.p, 0.0, W.p, s);
+            if (e == hipSuccess && which == DM_OP_H) {
+                e = gemm_tn_f64(kp, kp, kp, 1.0, op.Xs.p, kp, W.p, kp, 0.0, T.p, kp, false, s, true);
+                if (e == hipSuccess) e = gemm_nn_f64(kp, kp, kp, 1.0, op.Xs.p, kp, T.p, kp, 0.0, W.p, kp, true, s);
+                std::swap(W, T);
+            } else if (e == hipSuccess) {
+                e = gemm_nn_f64(kp, kp, kp, 1.0, W.p, kp, op.Xs.p, kp, 0.0, T.p, kp, false, s);
+                if (e == hipSuccess) e = gemm_tn_f64(kp, kp, kp, 1.0, op.Xs.p, kp, T.p, kp, 0.0, W.p, kp, false, s, true);
+                std::swap(W, T);
+            }
+        }
+        if (e == hipSuccess) e = hipMemcpy2DAsync(out, K * 8, T.p, Kp * 8, K * 8, K, hipMemcpyDefault, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        W.release();
+        T.release();
+        if (e != hipSuccess) return fail_hip(c, e, "symmetric-form operator on request");
+        return DM_OK;
+    }
     if (which == DM_OP_SINV || which == DM_OP_HSYM) {
-        const double* src = which == DM_OP_SINV ? c->op.Sinv.p : c->op.Hsym.p;
-        HIPTRY(c, hipMemcpy2DAsync(out, K * 8, src, Kp * 8, K * 8, K, hipMemcpyDefault, s));
+        HIPTRY(c, hipMemcpy2DAsync(out, K * 8, c->op.Sinv.p, Kp * 8, K * 8, K, hipMemcpyDefault, s));
     } else {
         // HT holds H^T column-major; transpose through a device scratch buffer
         DevBuf<double> t;
@@ -1078,7 +1260,8 @@ dm_status dm_set_precision(dm_ctx* c, int precision) try {
     if (!c) return DM_E_ARG;
     dm_status st = enter(c);
     if (st != DM_OK) return st;
-    if (precision != DM_FP64 && precision != DM_FP32) return set_err(c, DM_E_ARG, "bad precision");
+    if (precision != DM_FP64 && precision != DM_FP32 && precision != DM_FP32_ACC64)
+        return set_err(c, DM_E_ARG, "bad precision");
     c->precision = precision;
     c->tuned_width = 0;  // shapes were timed (or fit) for the other precision
     c->tuned_cfg = -1;
@@ -1087,6 +1270,27 @@ dm_status dm_set_precision(dm_ctx* c, int precision) try {
     return normalize(c, c->op);
 } catch (...) {
     return host_exception(c);
+}
+
+// Start block of the symmetric form for the ncols columns `cols` (device)
+// of a pass of width Bp (B64 = Bp rounded up to 64): the moment vectors
+// Z[:, j] = U u_a = X^T s_a (S's column a, scattered into vbuf, then one
+// MFMA product; X upper), V_0[:, j] = L u_a = X[a, :]^T into vbuf, then
+// U_0 = V_0 in the recursion precision, P_q = a_0(q) V_0 and the moment
+// partial sums of l = 0 as cheb_start does for the general form.  vbuf and
+// Z are Kp x B64 FP64.
+static hipError_t sym_start(const Op& op, int Bp, int B64, int ncols, const long long* cols, int precision,
+                            void* U0, double* Z, double* P, double* vbuf, const double* coef, int nsets,
+                            long long pstride, int cstride, double* partial, int* nts, hipStream_t s) {
+    const int Kp = op.Kp;
+    hipError_t e = fill_f64(vbuf, 0.0, (long long)Kp * B64, s);
+    if (e == hipSuccess) e = scatter_s_columns(Kp, ncols, cols, op.S_rowptr.p, op.S_col.p, op.S_val.p, vbuf, s);
+    if (e == hipSuccess) e = gemm_tn_f64(Kp, B64, Kp, 1.0, op.Xs.p, Kp, vbuf, Kp, 0.0, Z, Kp, false, s, true);
+    if (e == hipSuccess) e = gather_rows(Kp, ncols, cols, op.Xs.p, vbuf, s);
+    if (e == hipSuccess)
+        e = cheb_start((int)op.K, Kp, Bp, ncols, nullptr, vbuf, op.S_rowptr.p, op.S_col.p, op.S_val.p, precision, U0,
+                       Z, P, coef, nsets, pstride, cstride, partial, nts, s, Z);
+    return e;
 }
 
 // End of a pass: the moments accumulated so far must be finite and bounded.
@@ -1224,11 +1428,11 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
     if (wbytes) HIPTRY(c, ensure(c->work, (wbytes + 7) / 8));
     HIPTRY(c, ensure(c->Ua, (size_t)Kp * Bp_max * tsz / 8));
     HIPTRY(c, ensure(c->Ub, (size_t)Kp * Bp_max * tsz / 8));
-    HIPTRY(c, ensure(c->Z, (size_t)Kp * Bp_max));
     // symmetric form: the accumulated blocks are Q = p_N(H~) L u_a, and P = L^T Q
-    // is one FP64 product per pass, over columns padded to 64
+    // (L^T = X) is one FP64 product per pass, over columns padded to 64
     const bool sym = c->op.form == DM_FORM_SYMMETRIC;
     const int Bpad = sym ? (int)round_up(Bp_max, 64) : Bp_max;
+    HIPTRY(c, ensure(c->Z, (size_t)Kp * Bpad));
     const long long pstride = (long long)Kp * Bpad;
     HIPTRY(c, ensure(c->P, (size_t)pstride * nsets));
     if (sym) HIPTRY(c, ensure(c->Pfin, (size_t)pstride));
@@ -1241,12 +1445,17 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
         const int nc = (int)std::min<long long>(bw, ncols - off);
         const int Bp = (int)round_up(nc, std::max(BN, 16));
         HIPTRY(c, hipMemcpyAsync(c->cols.p, hc.data() + off, (size_t)nc * 8, hipMemcpyHostToDevice, s));
-        HIPTRY(c, fill_f64(c->Z.p, 0.0, (long long)Kp * Bp, s));
         int nts = 0;
-        const double* v0src = c->op.orth ? nullptr : (sym ? c->op.Lsym.p : c->op.Sinv.p);
-        HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, v0src, c->op.S_rowptr.p,
-                             c->op.S_col.p, c->op.S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p,
-                             nsets, pstride, cstride, c->part_start.p, &nts, s, sym ? c->op.Usym.p : nullptr));
+        if (sym) {
+            HIPTRY(c, sym_start(c->op, Bp, (int)round_up(Bp, 64), nc, c->cols.p, c->precision, c->Ua.p, c->Z.p,
+                                c->P.p, c->Pfin.p, c->coef.p, nsets, pstride, cstride, c->part_start.p, &nts, s));
+        } else {
+            HIPTRY(c, fill_f64(c->Z.p, 0.0, (long long)Kp * Bp, s));
+            const double* v0src = c->op.orth ? nullptr : c->op.Sinv.p;
+            HIPTRY(c, cheb_start((int)K, Kp, Bp, nc, c->cols.p, v0src, c->op.S_rowptr.p, c->op.S_col.p,
+                                 c->op.S_val.p, c->precision, c->Ua.p, c->Z.p, c->P.p, c->coef.p, nsets, pstride,
+                                 cstride, c->part_start.p, &nts, s));
+        }
         HIPTRY(c, reduce_moments(0, nts, c->part_start.p, c->mom.p, c->flag.p, s));
         void* ucur = c->Ua.p;
         void* uoth = c->Ub.p;
@@ -1270,7 +1479,7 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
             a.alpha = (l == 1) ? 1.0 : 2.0;
             a.has_prev = (l > 1);
             a.l = l;
-            hipError_t e = c->precision == DM_FP64 ? cheb_step_f64(a, cfg, s) : cheb_step_f32(a, cfg, s);
+            hipError_t e = cheb_step(a, cfg, c->precision, s);
             if (e != hipSuccess) return fail_hip(c, e, "cheb_step");
             std::swap(ucur, uoth);
         }
@@ -1282,7 +1491,7 @@ static dm_status run_pass(dm_ctx* c, const long long* cols, long long ncols, int
                 const int B64 = (int)round_up(Bp, 64);
                 double* Q = c->P.p + (size_t)q * pstride;
                 if (B64 > Bp) HIPTRY(c, fill_f64(Q + (size_t)Kp * Bp, 0.0, (long long)Kp * (B64 - Bp), s));
-                HIPTRY(c, gemm_tn_f64(Kp, B64, Kp, 1.0, c->op.Lsym.p, Kp, Q, Kp, 0.0, c->Pfin.p, Kp, false, s));
+                HIPTRY(c, gemm_nn_f64(Kp, B64, Kp, 1.0, c->op.Xs.p, Kp, Q, Kp, 0.0, c->Pfin.p, Kp, true, s));
                 src = c->Pfin.p;
             }
             HIPTRY(c, hipMemcpy2DAsync(P_outs[q] + off * K, (size_t)K * 8, src, (size_t)Kp * 8, (size_t)K * 8, nc,
@@ -1412,7 +1621,7 @@ dm_status dm_chebyshev_block_noalloc(dm_ctx* c, const long long* cols, long long
             a.alpha = (l == 1) ? 1.0 : 2.0;
             a.has_prev = (l > 1);
             a.l = l;
-            const hipError_t e = prec == DM_FP64 ? cheb_step_f64(a, cfg, s) : cheb_step_f32(a, cfg, s);
+            const hipError_t e = cheb_step(a, cfg, prec, s);
             if (e != hipSuccess) return fail_hip(c, e, "cheb_step");
             std::swap(ucur, uoth);
         }
@@ -1918,7 +2127,7 @@ dm_status dm_autotune(dm_ctx* c, long long ncols, int steps, double* table, int*
             a.alpha = (l == 1) ? 1.0 : 2.0;
             a.has_prev = l > 1;
             a.l = l;
-            AT(c->precision == DM_FP64 ? cheb_step_f64(a, cd.cfg, s) : cheb_step_f32(a, cd.cfg, s));
+            AT(cheb_step(a, cd.cfg, c->precision, s));
             std::swap(ucur, uoth);
         }
         AT(hipEventRecord(e1, s));
@@ -2072,7 +2281,7 @@ dm_status stoch_moments_op(dm_ctx* c, Op& op, int n_mom, int n_vec, const double
         a.alpha = (l == 1) ? 1.0 : 2.0;
         a.has_prev = (l > 1);
         a.l = l;
-        SM(c->precision == DM_FP64 ? cheb_step_f64(a, cfg, s) : cheb_step_f32(a, cfg, s));
+        SM(cheb_step(a, cfg, c->precision, s));
         std::swap(ucur, uoth);
     }
     if (n_mom > 1) SM(reduce_moments(n_mom - 2, ntl, pss.p + ntl, ms.p + 1, c->flag.p, s));
@@ -2092,40 +2301,37 @@ extern "C" {
 
 namespace {
 
-// (Re)builds the per-cluster buffers and the device tables of the batch
-// kernel for tile shape cfg and `order` steps.  Rebuilding invalidates any
-// captured graph (buffer addresses may change).
-dm_status batch_tables(dm_ctx* c, int cfg, int order) {
+// Tile shape of the FP64 moments pass that goes with the recursion shape
+// cfg: the FP64 batch shape with the same tile rows and columns, else the
+// first FP64 batch shape.
+int batch_mom_cfg(int cfg) {
+    int first = -1;
+    for (int i = 0; i < cheb_batch_num_cfgs(); ++i) {
+        const int m = cheb_batch_cfg(i, DM_FP64);
+        if (m < 0) continue;
+        if (first < 0) first = m;
+        if (cheb_tile_rows(m) == cheb_tile_rows(cfg) && cheb_tile_cols(m) == cheb_tile_cols(cfg)) return m;
+    }
+    return first;
+}
+
+// Cluster table and longest-first item list of one pass with tile shape
+// cfg, reading H_N from HN64 (FP64 moments pass) or HNbuf.
+dm_status batch_pass_table(dm_ctx* c, int cfg, bool fp64_copy, DevBuf<BatchCluster>& dcl,
+                           DevBuf<BatchItem>& ditems, int& n_items) {
     BatchState& bs = *c->bstate;
-    if (bs.table_cfg == cfg && bs.table_order == order && bs.table_prec == c->precision) return DM_OK;
-    bs.drop_graph();
-    const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
     const int BN = cheb_tile_cols(cfg);
     const int n = (int)c->batch.size();
-    const int M = 4 * order;
     std::vector<BatchCluster> hcl(n);
     std::vector<std::pair<long long, BatchItem>> items;
     for (int i = 0; i < n; ++i) {
         const Op& op = c->batch[i];
         BatchClusterBufs& b = bs.cl[i];
-        const size_t KB = (size_t)op.Kp * b.Bp;
-        HIPTRY(c, ensure(b.Ua, KB * tsz / 8));
-        HIPTRY(c, ensure(b.Ub, KB * tsz / 8));
-        HIPTRY(c, ensure(b.Z, KB));
-        HIPTRY(c, ensure(b.P, KB));
-        HIPTRY(c, ensure(b.coef, (size_t)order + 1));
-        HIPTRY(c, ensure(b.partial, (size_t)(order + 1) * (b.Bp / 32)));
-        HIPTRY(c, ensure(b.pstart, (size_t)(op.Kp / 64) * (b.Bp / 16)));
-        HIPTRY(c, ensure(b.mom, (size_t)order + 1));
-        HIPTRY(c, ensure(b.w, (size_t)M));
-        HIPTRY(c, ensure(b.v, (size_t)M));
-        HIPTRY(c, ensure(b.fk, (size_t)M));
-        HIPTRY(c, ensure(b.out, 8));
         BatchCluster& h = hcl[i];
         h.Kp = op.Kp;
         h.Bp = b.Bp;
         h.nblocks = b.Bp / BN;
-        h.HN = op.HNbuf.p;
+        h.HN = fp64_copy ? op.HN64.p : op.HNbuf.p;
         h.Ua = b.Ua.p;
         h.Ub = b.Ub.p;
         h.P = b.P.p;
@@ -2143,41 +2349,93 @@ dm_status batch_tables(dm_ctx* c, int cfg, int order) {
                      });
     std::vector<BatchItem> hitems(items.size());
     for (size_t k = 0; k < items.size(); ++k) hitems[k] = items[k].second;
-    HIPTRY(c, ensure(bs.d_clusters, (size_t)n));
-    HIPTRY(c, ensure(bs.d_items, hitems.size()));
+    HIPTRY(c, ensure(dcl, (size_t)n));
+    HIPTRY(c, ensure(ditems, hitems.size()));
+    HIPTRY(c, hipMemcpy(dcl.p, hcl.data(), n * sizeof(BatchCluster), hipMemcpyHostToDevice));
+    HIPTRY(c, hipMemcpy(ditems.p, hitems.data(), hitems.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+    n_items = (int)hitems.size();
+    return DM_OK;
+}
+
+// Precision of the batch's moments pass.
+int batch_mom_precision(const dm_ctx* c) {
+    return c->bstate && c->bstate->mom_prec >= 0 ? c->bstate->mom_prec : c->precision;
+}
+
+// (Re)builds the per-cluster buffers and the device tables of the batch
+// kernel for tile shape cfg and `order` steps.  Rebuilding invalidates any
+// captured graph (buffer addresses may change).
+dm_status batch_tables(dm_ctx* c, int cfg, int order) {
+    BatchState& bs = *c->bstate;
+    if (bs.table_cfg == cfg && bs.table_order == order && bs.table_prec == c->precision) return DM_OK;
+    bs.drop_graph();
+    const int mprec = batch_mom_precision(c);
+    const bool split_mom = mprec != c->precision;
+    const size_t tsz = (c->precision == DM_FP64 || mprec == DM_FP64) ? 8 : 4;
+    const int n = (int)c->batch.size();
+    const int M = 4 * order;
+    for (int i = 0; i < n; ++i) {
+        const Op& op = c->batch[i];
+        BatchClusterBufs& b = bs.cl[i];
+        const size_t KB = (size_t)op.Kp * b.Bp;
+        HIPTRY(c, ensure(b.Ua, KB * tsz / 8));
+        HIPTRY(c, ensure(b.Ub, KB * tsz / 8));
+        HIPTRY(c, ensure(b.Z, KB));
+        HIPTRY(c, ensure(b.P, KB));
+        HIPTRY(c, ensure(b.coef, (size_t)order + 1));
+        HIPTRY(c, ensure(b.partial, (size_t)(order + 1) * (b.Bp / 32)));
+        HIPTRY(c, ensure(b.pstart, (size_t)(op.Kp / 64) * (b.Bp / 16)));
+        HIPTRY(c, ensure(b.mom, (size_t)order + 1));
+        HIPTRY(c, ensure(b.w, (size_t)M));
+        HIPTRY(c, ensure(b.v, (size_t)M));
+        HIPTRY(c, ensure(b.fk, (size_t)M));
+        HIPTRY(c, ensure(b.out, 8));
+    }
+    dm_status st = batch_pass_table(c, cfg, false, bs.d_clusters, bs.d_items, bs.n_items);
+    if (st != DM_OK) return st;
+    if (split_mom) {
+        bs.cfg_m = batch_mom_cfg(cfg);
+        if (bs.cfg_m < 0) return set_err(c, DM_E_STATE, "no FP64 batch tile shape");
+        st = batch_pass_table(c, bs.cfg_m, true, bs.d_clusters_m, bs.d_items_m, bs.n_items_m);
+        if (st != DM_OK) return st;
+    }
     HIPTRY(c, ensure(bs.counter, 4));
-    HIPTRY(c, hipMemcpy(bs.d_clusters.p, hcl.data(), n * sizeof(BatchCluster), hipMemcpyHostToDevice));
-    HIPTRY(c, hipMemcpy(bs.d_items.p, hitems.data(), hitems.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
-    bs.n_items = (int)hitems.size();
     bs.table_cfg = cfg;
     bs.table_order = order;
     bs.table_prec = c->precision;
     return DM_OK;
 }
 
-int batch_grid(dm_ctx* c, int cfg) {
+int batch_grid(dm_ctx* c, int cfg, int precision, int n_items) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->opt.device) != hipSuccess || cus < 1)
         cus = 256;
-    const int occ = std::max(1, cheb_batch_occupancy(cfg, c->precision));
-    return std::max(1, std::min(c->bstate->n_items, cus * occ));
+    const int occ = std::max(1, cheb_batch_occupancy(cfg, precision));
+    return std::max(1, std::min(n_items, cus * occ));
 }
 
-// Start blocks of every cluster (U_0 = S^-1 columns into U_a, Z = S, P = a_0 U_0).
-hipError_t batch_start(dm_ctx* c, bool zero_moments) {
+// Start blocks of every cluster (U_0 = S^-1 columns into U_a in `precision`,
+// Z = S, P = a_0 U_0).
+hipError_t batch_start(dm_ctx* c, bool zero_moments, int precision) {
     BatchState& bs = *c->bstate;
     hipStream_t s = c->stream;
     hipError_t e;
     for (size_t i = 0; i < c->batch.size(); ++i) {
         const Op& op = c->batch[i];
         BatchClusterBufs& b = bs.cl[i];
-        if ((e = fill_f64(b.Z.p, 0.0, (long long)op.Kp * b.Bp, s)) != hipSuccess) return e;
         int nts = 0;
-        const bool sym = op.form == DM_FORM_SYMMETRIC;
-        if ((e = cheb_start((int)op.K, op.Kp, b.Bp, (int)op.K, b.cols.p, sym ? op.Lsym.p : op.Sinv.p,
-                            op.S_rowptr.p, op.S_col.p, op.S_val.p, c->precision, b.Ua.p, b.Z.p, b.P.p,
-                            b.coef.p, 1, 0, 0, b.pstart.p, &nts, s, sym ? op.Usym.p : nullptr)) != hipSuccess)
-            return e;
+        if (op.form == DM_FORM_SYMMETRIC) {
+            // V_0 staged in P (cheb_start reads and writes each element in one thread)
+            if ((e = sym_start(op, b.Bp, b.Bp, (int)op.K, b.cols.p, precision, b.Ua.p, b.Z.p, b.P.p, b.P.p,
+                               b.coef.p, 1, 0, 0, b.pstart.p, &nts, s)) != hipSuccess)
+                return e;
+        } else {
+            if ((e = fill_f64(b.Z.p, 0.0, (long long)op.Kp * b.Bp, s)) != hipSuccess) return e;
+            if ((e = cheb_start((int)op.K, op.Kp, b.Bp, (int)op.K, b.cols.p, op.Sinv.p, op.S_rowptr.p, op.S_col.p,
+                                op.S_val.p, precision, b.Ua.p, b.Z.p, b.P.p, b.coef.p, 1, 0, 0, b.pstart.p, &nts,
+                                s)) != hipSuccess)
+                return e;
+        }
         if (zero_moments) {
             if ((e = fill_f64(b.mom.p, 0.0, bs.table_order + 1, s)) != hipSuccess) return e;
             if ((e = reduce_moments(0, nts, b.pstart.p, b.mom.p, c->flag.p, s)) != hipSuccess) return e;
@@ -2187,13 +2445,17 @@ hipError_t batch_start(dm_ctx* c, bool zero_moments) {
 }
 
 // The whole batch sequence on c->stream (also recorded under graph capture).
+// grid1, grid2: workgroups of the moments and the P pass (batch_grid),
+// taken before a capture starts.
 hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<double>& ne, double tol,
-                         int grid, bool with_P) {
+                         int grid1, int grid2, bool with_P) {
     BatchState& bs = *c->bstate;
     hipStream_t s = c->stream;
     const int n = (int)c->batch.size();
     const int M = 4 * order;
     const double g = c->opt.spin;
+    const int mprec = batch_mom_precision(c);
+    const bool split_mom = mprec != c->precision;
     hipError_t e;
 #define BQ(x)                                 \
     do {                                      \
@@ -2202,11 +2464,15 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
     BQ(fill_i32(c->flag.p, 0, 4, s));
     BQ(fill_i32(bs.counter.p, 0, 4, s));
     for (int i = 0; i < n; ++i) BQ(fill_f64(bs.cl[i].coef.p, 0.0, order + 1, s));
-    // pass 1: moments of every column (coefficients zero: P is not touched)
-    BQ(batch_start(c, true));
-    BatchArgs a{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p, order, 0};
-    BQ(cheb_batch(a, bs.cfg, c->precision, grid, s));
-    const int BN = cheb_tile_cols(bs.cfg);
+    // pass 1: moments of every column (coefficients zero: P is not touched),
+    // in FP64 from the FP64 copy of H_N when the batch was loaded so
+    const int cfg1 = split_mom ? bs.cfg_m : bs.cfg;
+    const int nit1 = split_mom ? bs.n_items_m : bs.n_items;
+    BQ(batch_start(c, true, mprec));
+    BatchArgs a{split_mom ? bs.d_clusters_m.p : bs.d_clusters.p, split_mom ? bs.d_items_m.p : bs.d_items.p, nit1,
+                bs.counter.p, order, 0};
+    BQ(cheb_batch(a, cfg1, mprec, grid1, s));
+    const int BN = cheb_tile_cols(cfg1);
     for (int i = 0; i < n; ++i) {
         const Op& op = c->batch[i];
         BatchClusterBufs& b = bs.cl[i];
@@ -2221,15 +2487,15 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
     }
     if (!with_P) return hipSuccess;
     // pass 2: P at mu_c
-    BQ(batch_start(c, false));
+    BQ(batch_start(c, false, c->precision));
     BatchArgs a2{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p + 1, order, 1};
-    BQ(cheb_batch(a2, bs.cfg, c->precision, grid, s));
+    BQ(cheb_batch(a2, bs.cfg, c->precision, grid2, s));
     // symmetric form: P = L^T Q into the Z buffer (Z is not read after the pass)
     for (int i = 0; i < n; ++i) {
         const Op& op = c->batch[i];
         if (op.form != DM_FORM_SYMMETRIC) continue;
         BatchClusterBufs& b = bs.cl[i];
-        BQ(gemm_tn_f64(op.Kp, b.Bp, op.Kp, 1.0, op.Lsym.p, op.Kp, b.P.p, op.Kp, 0.0, b.Z.p, op.Kp, false, s));
+        BQ(gemm_nn_f64(op.Kp, b.Bp, op.Kp, 1.0, op.Xs.p, op.Kp, b.P.p, op.Kp, 0.0, b.Z.p, op.Kp, true, s));
     }
 #undef BQ
     return hipSuccess;
@@ -2244,6 +2510,8 @@ dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) try {
     dm_status st = enter(c);
     if (st != DM_OK) return st;
     if (n < 1 || !cl) return set_err(c, DM_E_ARG, "need n >= 1 clusters");
+    if (c->precision == DM_FP32_ACC64)
+        return set_err(c, DM_E_STATE, "the batch runs in DM_FP64 or DM_FP32");
     if (c->form == DM_FORM_FACTORED)
         return set_err(c, DM_E_STATE, "the batch runs in the general or symmetric form");
     delete c->bstate;
@@ -2255,21 +2523,42 @@ dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) try {
         HostCsr Fh, Sh;
         st = load_csr_pair(c, cl[i].K, cl[i].F_rowptr, cl[i].F_col, cl[i].F_val, cl[i].S_rowptr,
                            cl[i].S_col, cl[i].S_val, Fh, Sh);
-        if (st == DM_OK) st = build_op(c, c->batch[i], cl[i].K, Fh, Sh, c->form);
+        if (st == DM_OK)
+            st = c->form == DM_FORM_SYMMETRIC ? build_sym(c, c->batch[i], cl[i].K, Fh, Sh)
+                                              : build_op(c, c->batch[i], cl[i].K, Fh, Sh, c->form);
         if (st != DM_OK) {
             const std::string m = "cluster " + std::to_string(i) + ": " + c->err;
             for (auto& o : c->batch) o.release();
             c->batch.clear();
             return set_err(c, st, m);
         }
-        // H^T / H~ are only needed to renormalise, S^-1 only by the general
-        // form's start block; the batch keeps H_N
+        // FP64 moments under an FP32 recursion: an FP64 H_N beside the FP32 one
+        if (c->batch_mom_prec == DM_FP64 && c->precision == DM_FP32) {
+            Op& op = c->batch[i];
+            const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
+            hipError_t e = ensure(op.HN64, (size_t)op.Kp * op.Kp);
+            dm_status st2 = DM_OK;
+            if (e == hipSuccess && op.form == DM_FORM_SYMMETRIC)
+                st2 = sym_panels(c, op, ebar, de, DM_FP64, op.HN64.p);
+            else if (e == hipSuccess)
+                e = normalize_operator((int)op.K, op.Kp, op.HT.p, ebar, de, DM_FP64, op.HN64.p, c->stream);
+            if (e != hipSuccess || st2 != DM_OK) {
+                const std::string m = c->err;
+                for (auto& o : c->batch) o.release();
+                c->batch.clear();
+                return e != hipSuccess ? fail_hip(c, e, "FP64 copy of a batch operator") : set_err(c, st2, m);
+            }
+        }
+        // H^T is only needed to renormalise, F only to rebuild H~_N; the
+        // batch keeps H_N (and X or S^-1 for its start blocks)
         c->batch[i].HT.release();
-        c->batch[i].Hsym.release();
-        if (c->batch[i].form == DM_FORM_SYMMETRIC) c->batch[i].Sinv.release();
+        c->batch[i].F_rowptr.release();
+        c->batch[i].F_col.release();
+        c->batch[i].F_val.release();
     }
     c->bstate = new BatchState();
     c->bstate->cl.resize(n);
+    c->bstate->mom_prec = (c->batch_mom_prec == DM_FP64 && c->precision == DM_FP32) ? DM_FP64 : -1;
     for (int i = 0; i < n; ++i) {
         BatchClusterBufs& b = c->bstate->cl[i];
         const long long K = c->batch[i].K;
@@ -2279,6 +2568,18 @@ dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) try {
         HIPTRY(c, ensure(b.cols, (size_t)K));
         HIPTRY(c, hipMemcpy(b.cols.p, ar.data(), (size_t)K * 8, hipMemcpyHostToDevice));
     }
+    return DM_OK;
+} catch (...) {
+    return host_exception(c);
+}
+
+dm_status dm_set_moments_precision(dm_ctx* c, int precision) try {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (precision != DM_FP64 && precision != DM_FP32 && precision != -1)
+        return set_err(c, DM_E_ARG, "precision must be DM_FP64, DM_FP32 or -1");
+    c->batch_mom_prec = precision;
     return DM_OK;
 } catch (...) {
     return host_exception(c);
@@ -2300,11 +2601,15 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
         if (!std::isfinite(x)) return set_err(c, DM_E_ARG, "non-finite n_e");
     st = batch_tables(c, bs.cfg, order);
     if (st != DM_OK) return st;
-    const int grid = batch_grid(c, bs.cfg);
+    const int mprec = batch_mom_precision(c);
+    const bool split_mom = mprec != c->precision;
+    const int grid1 = split_mom ? batch_grid(c, bs.cfg_m, mprec, bs.n_items_m)
+                                : batch_grid(c, bs.cfg, c->precision, bs.n_items);
+    const int grid2 = batch_grid(c, bs.cfg, c->precision, bs.n_items);
     const bool with_P = !(flags & DM_BATCH_MOMENTS_ONLY);
     hipStream_t s = c->stream;
     if (flags & DM_BATCH_EAGER) {
-        HIPTRY(c, batch_enqueue(c, order, beta, ne, tol, grid, with_P));
+        HIPTRY(c, batch_enqueue(c, order, beta, ne, tol, grid1, grid2, with_P));
     } else {
         const bool same = bs.exec && bs.g_order == order && bs.g_beta == beta && bs.g_tol == tol &&
                           bs.g_prec == c->precision && bs.g_cfg == bs.cfg && bs.g_ne == ne &&
@@ -2312,7 +2617,7 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
         if (!same) {
             bs.drop_graph();
             HIPTRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            const hipError_t e1 = batch_enqueue(c, order, beta, ne, tol, grid, with_P);
+            const hipError_t e1 = batch_enqueue(c, order, beta, ne, tol, grid1, grid2, with_P);
             hipGraph_t g = nullptr;
             const hipError_t e2 = hipStreamEndCapture(s, &g);
             if (e1 != hipSuccess) {
@@ -2388,9 +2693,9 @@ dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, in
         st = batch_tables(c, cfg, steps);
         if (st != DM_OK) break;
         for (size_t i = 0; i < c->batch.size(); ++i) HIPTRY(c, fill_f64(bs.cl[i].coef.p, 0.0, steps + 1, s));
-        HIPTRY(c, batch_start(c, false));
+        HIPTRY(c, batch_start(c, false, c->precision));
         HIPTRY(c, fill_i32(bs.counter.p, 0, 4, s));
-        const int grid = batch_grid(c, cfg);
+        const int grid = batch_grid(c, cfg, c->precision, bs.n_items);
         BatchArgs a{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p, steps, 0};
         HIPTRY(c, hipEventRecord(e0, s));
         HIPTRY(c, cheb_batch(a, cfg, c->precision, grid, s));

@@ -21,13 +21,20 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // ----------------------------------------------------------------- launches
 // All launch wrappers return the hipError_t of the launch.
 
+// C = alpha A B + beta C, every matrix column-major (A: M x Kred, B: Kred x
+// N); a_upper: A is upper triangular (a row tile's sum starts at its first
+// row).  M, N multiples of 64, Kred of 32.
+hipError_t gemm_nn_f64(int M, int N, int Kred, double alpha, const double* A, long lda, const double* B,
+                       long ldb, double beta, double* C, long ldc, bool a_upper, hipStream_t s);
 // C[m + n*ldc] = alpha * sum_k A[m*lda + k] * B[n*ldb + k] + beta * C[...]
 // M, N multiples of 64, Kred multiple of 32, operands FP64.  With
 // upper_only, output tiles entirely below the diagonal (m0 >= n0 + tile) are
 // skipped (used where only the upper triangle of a symmetric result is read).
+// a_cols_upper: column m of A is zero below row m (A upper triangular), so
+// a row tile's sum stops after its last row.
 hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, long lda,
                        const double* B, long ldb, double beta, double* C, long ldc,
-                       bool upper_only, hipStream_t s);
+                       bool upper_only, hipStream_t s, bool a_cols_upper = false);
 
 // One step of the Chebyshev column recursion with the fused epilogue:
 //   Unext = alpha * (HN * Ucur) - (has_prev ? Uprev : 0)      (storage T)
@@ -69,6 +76,9 @@ int cheb_tile_cols(int cfg);
 int cheb_tile_rows(int cfg);
 hipError_t cheb_step_f64(const ChebStepArgs& a, int cfg, hipStream_t s);
 hipError_t cheb_step_f32(const ChebStepArgs& a, int cfg, hipStream_t s);
+// One recursion step in precision 0 (FP64), 1 (FP32) or 2 (FP32 storage,
+// FP64 arithmetic).
+hipError_t cheb_step(const ChebStepArgs& a, int cfg, int precision, hipStream_t s);
 int cheb_num_tiles(int Kp, int Bp, int cfg);
 
 // Persistent batch recursion.  Each workgroup repeatedly takes the next work
@@ -116,9 +126,11 @@ hipError_t cheb_coefficients_devmu(int N, int M, double ebar, double de, const d
 // (from its CSR rows; S is symmetric) or, with Zdense, Zdense[:, cols[j]],
 // P_s[:, j] = coef[s * cstride] * Sinv[:, cols[j]] for s < nsets (P_s = P +
 // s * pstride), partial[t] = per-tile sums of Z .* U0 for t < ntiles(start).
-// Columns j >= ncols are zero.  Z must be zero on entry.  (The symmetric form
-// passes L for Sinv and U for Zdense; an orthonormal basis passes no Sinv:
-// U0 and P start from the unit vectors.)
+// Columns j >= ncols are zero.  Z must be zero on entry.  With cols NULL
+// the source columns are Sinv's own columns 0 .. ncols - 1; with Zdense ==
+// Z the moment vectors are taken as already in Z.  (The symmetric form
+// passes its start block for Sinv and its moment vectors in Z; an
+// orthonormal basis passes no Sinv: U0 and P start from the unit vectors.)
 hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, const double* Sinv,
                       const long long* S_rowptr, const int* S_col, const double* S_val,
                       int precision, void* U0, double* Z, double* P, const double* coef,
@@ -219,6 +231,30 @@ hipError_t check_columns(const long long* cols, long long ncols, long long K, in
                          hipStream_t s);
 // flag[0] |= 1 when some |x_i| > lim or x_i is not finite
 hipError_t flag_large(const double* x, long long n, double lim, int* flag, hipStream_t s);
+// --- symmetric form built in place (symform.hip)
+// A[r + c Kp] = 0 below the diagonal of the Kp x Kp column-major A
+hipError_t zero_strict_lower(int Kp, double* A, hipStream_t s);
+// the nb x nb block at A (ld) := upper triangle of V (nb x nb), zero below
+hipError_t set_upper_block(int nb, double* A, long ld, const double* V, hipStream_t s);
+// dst[c + r ldd] = src[r + c lds], r < rows, c < cols
+hipError_t transpose_rect(long rows, long cols, const double* src, long lds, double* dst, long ldd, hipStream_t s);
+// V[:, j] = X[cols[j], :]^T (rows of the Kp x Kp column-major X), j < ncols
+hipError_t gather_rows(int Kp, int ncols, const long long* cols, const double* X, double* V, hipStream_t s);
+// Y = F X, X and Y row-major K x w panels (w <= 2048), F in CSR; rows of X
+// from kmax on are taken as zero
+hipError_t csr_spmm_rm(int K, const long long* rp, const int* col, const double* val, int w, const double* X,
+                       int kmax, double* Y, hipStream_t s);
+// columns col0 .. col0 + w - 1 of H (Kp x Kp, precision 0: FP64, else FP32)
+// := (C - ebar I) inv_de on the K x K block, zero padding; C is Kp x w FP64
+hipError_t store_panel(int K, int Kp, int w, int col0, const double* C, double ebar, double inv_de, int precision,
+                       void* H, hipStream_t s);
+// H := (H - ebar I) / de in place on the K x K block
+hipError_t normalize_inplace(int K, int Kp, int precision, void* H, double ebar, double de, hipStream_t s);
+// y = A x, A row-major in FP64 (precision 0) or FP32, x and y FP64
+hipError_t gemv_rows_t(int K, int precision, const void* A, long lda, const double* x, double* y, hipStream_t s);
+// Z[:, j] = column cols[j] of the symmetric CSR S (Z zero on entry), j < ncols
+hipError_t scatter_s_columns(int Kp, int ncols, const long long* cols, const long long* rowptr, const int* col,
+                             const double* val, double* Z, hipStream_t s);
 hipError_t fill_f64(double* x, double v, long long n, hipStream_t s);
 hipError_t fill_i32(int* x, int v, long long n, hipStream_t s);
 // D (Kp x Kp col-major, zero on entry) gets the CSR matrix; padded diagonal

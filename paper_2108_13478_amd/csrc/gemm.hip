@@ -45,6 +45,23 @@ struct Mfma<float> {
     __device__ static inline int a_row(int i) { return i; }
 };
 
+// Storage and arithmetic type of a recursion precision.  W32 is the
+// refined mode: H_N and U_l are stored in FP32 (half the bytes of FP64),
+// every product and sum runs in FP64 on the f64 MFMA (an FP32 x FP32
+// product is exact in FP64), and U_{l+1} is rounded to FP32 once, when it
+// is stored.
+struct W32 {};
+template <typename T>
+struct Prec {
+    typedef T store;
+    typedef T calc;
+};
+template <>
+struct Prec<W32> {
+    typedef float store;
+    typedef double calc;
+};
+
 // Tile placement.  Workgroups are dispatched round-robin over the 8 XCDs
 // (workgroup b lands on XCD b % 8); remapping b so that each XCD gets a
 // contiguous range of logical tiles, and ordering logical tiles in groups of
@@ -86,24 +103,34 @@ template <> struct VecOf<double, 8> { typedef double type __attribute__((ext_vec
 template <> struct VecOf<float, 8> { typedef float type __attribute__((ext_vector_type(8))); };
 template <> struct VecOf<float, 16> { typedef float type __attribute__((ext_vector_type(16))); };
 
-template <typename T, int TM, int TN, int KV, int DEPTH = 2, bool NT = false>
-__device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda,
-                                     const T* __restrict__ B, long ldb, int row0, int col0,
-                                     typename Mfma<T>::acc_t (&acc)[TM][TN]) {
-    typedef typename VecOf<T, KV>::type vec_t;
+// ACM: A is stored column-major (A[m + k lda], the plain product A B): a
+// lane then reads its KV values of k one by one, lda apart, and the 16 lanes
+// of a row group read 16 consecutive rows of one column together.
+template <typename T, int TM, int TN, int KV, int DEPTH = 2, bool NT = false, bool ACM = false>
+__device__ inline void gemm_mainloop(int Kred, const typename Prec<T>::store* __restrict__ A, long lda,
+                                     const typename Prec<T>::store* __restrict__ B, long ldb, int row0, int col0,
+                                     typename Mfma<typename Prec<T>::calc>::acc_t (&acc)[TM][TN]) {
+    typedef typename Prec<T>::store S;
+    typedef typename Prec<T>::calc C;
+    typedef typename VecOf<S, KV>::type vec_t;
     constexpr int SLAB = 4 * KV;
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
-    const T* pa[TM];
-    const T* pb[TN];
+    const S* pa[TM];
+    const S* pb[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) pa[i] = A + (long)(row0 + 16 * i + Mfma<T>::a_row(li)) * lda + KV * lq;
+    for (int i = 0; i < TM; ++i) {
+        if constexpr (ACM)
+            pa[i] = A + (long)(row0 + 16 * i + Mfma<C>::a_row(li)) + (long)(KV * lq) * lda;
+        else
+            pa[i] = A + (long)(row0 + 16 * i + Mfma<C>::a_row(li)) * lda + KV * lq;
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j) pb[j] = B + (long)(col0 + 16 * j + li) * ldb + KV * lq;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+        for (int j = 0; j < TN; ++j) acc[i][j] = typename Mfma<C>::acc_t{0, 0, 0, 0};
 
     vec_t a0[TM], b0[TN], a1[TM], b1[TN];
     // NT: the A operand is read once per launch, so its loads carry the
@@ -111,10 +138,14 @@ __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda
     auto load = [&](vec_t(&a)[TM], vec_t(&b)[TN], int k) {
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
-            if constexpr (NT)
+            if constexpr (ACM) {
+#pragma unroll
+                for (int s = 0; s < KV; ++s) a[i][s] = pa[i][(long)(k + s) * lda];
+            } else if constexpr (NT) {
                 a[i] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(pa[i] + k));
-            else
+            } else {
                 a[i] = *reinterpret_cast<const vec_t*>(pa[i] + k);
+            }
         }
 #pragma unroll
         for (int j = 0; j < TN; ++j) b[j] = *reinterpret_cast<const vec_t*>(pb[j] + k);
@@ -125,7 +156,8 @@ __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i][s], b[j][s], acc[i][j]);
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = Mfma<C>::mma(static_cast<C>(a[i][s]), static_cast<C>(b[j][s]), acc[i][j]);
     };
     if constexpr (DEPTH == 2) {
         // Kred is a multiple of 2 SLAB (checked by the launchers).  The steady
@@ -185,27 +217,29 @@ __device__ inline void gemm_mainloop(int Kred, const T* __restrict__ A, long lda
 // * 16 bytes with no bank conflicts.  The barrier waits only for LDS
 // traffic; the operator loads of later slabs stay in flight across it.
 template <typename T, int TM, int TN, int WM, int KV, int DEPTH>
-__device__ inline void gemm_mainloop_ldsb(int Kred, const T* __restrict__ A, long lda,
-                                          const T* __restrict__ B, long ldb, int row0, int col0,
-                                          typename Mfma<T>::acc_t (&acc)[TM][TN]) {
-    typedef typename VecOf<T, KV>::type vec_t;
+__device__ inline void gemm_mainloop_ldsb(int Kred, const typename Prec<T>::store* __restrict__ A, long lda,
+                                          const typename Prec<T>::store* __restrict__ B, long ldb, int row0,
+                                          int col0, typename Mfma<typename Prec<T>::calc>::acc_t (&acc)[TM][TN]) {
+    typedef typename Prec<T>::store S;
+    typedef typename Prec<T>::calc C;
+    typedef typename VecOf<S, KV>::type vec_t;
     typedef float piece_t __attribute__((ext_vector_type(4)));
     constexpr int SLAB = 4 * KV;
-    constexpr int H = KV * (int)sizeof(T) / 16;          // 16-byte parts per lane and column group
+    constexpr int H = KV * (int)sizeof(S) / 16;          // 16-byte parts per lane and column group
     constexpr int NPIECE = TN * H * 64;                   // pieces per slab
     constexpr int NT = 64 * WM;
     constexpr int R = NPIECE / NT;                        // pieces per thread and slab
-    constexpr int EPP = 16 / (int)sizeof(T);              // elements per piece
+    constexpr int EPP = 16 / (int)sizeof(S);              // elements per piece
     static_assert(NPIECE % NT == 0 && R >= 1, "every thread loads whole pieces");
     static_assert(DEPTH >= 2 && (DEPTH & (DEPTH - 1)) == 0, "ring depth is a power of two");
     __shared__ piece_t lds[2][NPIECE];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int li = lane & 15, lq = lane >> 4;
-    const T* pa[TM];
+    const S* pa[TM];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) pa[i] = A + (long)(row0 + 16 * i + Mfma<T>::a_row(li)) * lda + KV * lq;
-    const T* pp[R];
+    for (int i = 0; i < TM; ++i) pa[i] = A + (long)(row0 + 16 * i + Mfma<C>::a_row(li)) * lda + KV * lq;
+    const S* pp[R];
 #pragma unroll
     for (int e = 0; e < R; ++e) {
         const int c = (tid + e * NT) >> 6;  // chunk: column group c / H, part c % H
@@ -214,7 +248,7 @@ __device__ inline void gemm_mainloop_ldsb(int Kred, const T* __restrict__ A, lon
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+        for (int j = 0; j < TN; ++j) acc[i][j] = typename Mfma<C>::acc_t{0, 0, 0, 0};
 
     vec_t ra[DEPTH][TM];
     piece_t rs[DEPTH][R];
@@ -231,7 +265,7 @@ __device__ inline void gemm_mainloop_ldsb(int Kred, const T* __restrict__ A, lon
         vec_t b[TN];
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-            T* bj = reinterpret_cast<T*>(&b[j]);
+            S* bj = reinterpret_cast<S*>(&b[j]);
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 const piece_t v = lds[buf][(j * H + h) * 64 + lane];
@@ -243,7 +277,8 @@ __device__ inline void gemm_mainloop_ldsb(int Kred, const T* __restrict__ A, lon
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::mma(a[i][s], b[j][s], acc[i][j]);
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = Mfma<C>::mma(static_cast<C>(a[i][s]), static_cast<C>(b[j][s]), acc[i][j]);
     };
     // Slab n uses LDS buffer n & 1 (DEPTH is even, so that is d & 1 below).
     // A buffer is rewritten two slabs later, after every wave has passed the
@@ -270,15 +305,57 @@ template <int TM, int TN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_tn_store_kernel(int M, int N, int Kred, double alpha, const double* __restrict__ A, long lda,
                      const double* __restrict__ B, long ldb, double beta, double* __restrict__ C,
-                     long ldc, int upper_only) {
+                     long ldc, int upper_only, int k_to_row) {
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
     const TilePos tp = tile_position<8>(M / BM, N / BN);
     if (upper_only && tp.tile_m * BM >= (tp.tile_n + 1) * BN) return;
     const int wave = threadIdx.x >> 6;
     const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
     const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
+    // k_to_row: column m of A is zero below row m, so the tile's rows need
+    // k < its last row + 1 only (rounded up to the slab pair)
+    const int kend = k_to_row ? min(Kred, (tp.tile_m * BM + BM + 31) / 32 * 32) : Kred;
     double4_t acc[TM][TN];
-    gemm_mainloop<double, TM, TN, 4>(Kred, A, lda, B, ldb, row0, col0, acc);
+    gemm_mainloop<double, TM, TN, 4>(kend, A, lda, B, ldb, row0, col0, acc);
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const long idx = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * ldc;
+            double4_t* c = reinterpret_cast<double4_t*>(C + idx);
+            double4_t r = alpha * acc[i][j];
+            if (beta != 0.0) r += beta * (*c);
+            *c = r;
+        }
+}
+
+// C = alpha A B + beta C with A column-major (M x Kred, lda), B column-major
+// (Kred x N, ldb) and C column-major; k_from_row: A is upper triangular, so
+// a row tile starting at row r0 only needs k >= r0 (rounded down to the
+// slab pair).
+template <int TM, int TN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_nn_store_kernel(int M, int N, int Kred, double alpha, const double* __restrict__ A, long lda,
+                     const double* __restrict__ B, long ldb, double beta, double* __restrict__ C,
+                     long ldc, int k_from_row) {
+    constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    const TilePos tp = tile_position<8>(M / BM, N / BN);
+    const int wave = threadIdx.x >> 6;
+    const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
+    const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
+    const int k0 = k_from_row ? min(Kred, (tp.tile_m * BM) / 32 * 32) : 0;
+    double4_t acc[TM][TN];
+    if (k0 < Kred) {
+        gemm_mainloop<double, TM, TN, 4, 2, false, true>(Kred - k0, A + (long)k0 * lda, lda, B + k0, ldb, row0,
+                                                         col0, acc);
+    } else {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
+    }
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
@@ -297,40 +374,45 @@ gemm_tn_store_kernel(int M, int N, int Kred, double alpha, const double* __restr
 template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH, bool LDSB = false>
 __global__ void __launch_bounds__(64 * WM * WN)
 cheb_step_kernel(ChebStepArgs a) {
-    typedef typename Mfma<T>::vec_t vec_t;
+    typedef typename Prec<T>::store S;
+    typedef typename Prec<T>::calc C;
+    typedef typename Mfma<S>::vec_t svec_t;  // four stored values
+    typedef typename Mfma<C>::vec_t cvec_t;  // four values in the arithmetic type
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
     const int ntm = a.Kp / BM, ntn = a.Bp / BN;
     const TilePos tp = tile_position<8>(ntm, ntn);
     const int wave = threadIdx.x >> 6;
     const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
     const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
-    typename Mfma<T>::acc_t acc[TM][TN];
+    typename Mfma<C>::acc_t acc[TM][TN];
     if constexpr (LDSB) {
         static_assert(WN == 1, "the shared panel needs every wave on the same columns");
-        gemm_mainloop_ldsb<T, TM, TN, WM, KV, DEPTH>(a.Kp, static_cast<const T*>(a.HN), a.Kp,
-                                                     static_cast<const T*>(a.Ucur), a.Kp, row0, col0, acc);
+        gemm_mainloop_ldsb<T, TM, TN, WM, KV, DEPTH>(a.Kp, static_cast<const S*>(a.HN), a.Kp,
+                                                     static_cast<const S*>(a.Ucur), a.Kp, row0, col0, acc);
     } else {
-        gemm_mainloop<T, TM, TN, KV, DEPTH>(a.Kp, static_cast<const T*>(a.HN), a.Kp,
-                                            static_cast<const T*>(a.Ucur), a.Kp, row0, col0, acc);
+        gemm_mainloop<T, TM, TN, KV, DEPTH>(a.Kp, static_cast<const S*>(a.HN), a.Kp,
+                                            static_cast<const S*>(a.Ucur), a.Kp, row0, col0, acc);
     }
 
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
-    const T alpha = static_cast<T>(a.alpha);
+    const C alpha = static_cast<C>(a.alpha);
     const double c0 = a.coef[a.l];
-    const T* Uprev = static_cast<const T*>(a.Uprev);
-    T* Unext = static_cast<T*>(a.Unext);
+    const S* Uprev = static_cast<const S*>(a.Uprev);
+    S* Unext = static_cast<S*>(a.Unext);
     double msum = 0.0;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             const long idx = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * a.Kp;
-            vec_t out = alpha * acc[i][j];
-            if (a.has_prev) out -= *reinterpret_cast<const vec_t*>(Uprev + idx);
-            *reinterpret_cast<vec_t*>(Unext + idx) = out;
+            cvec_t out = alpha * acc[i][j];
+            if (a.has_prev)
+                out -= __builtin_convertvector(*reinterpret_cast<const svec_t*>(Uprev + idx), cvec_t);
+            const svec_t st = __builtin_convertvector(out, svec_t);
+            *reinterpret_cast<svec_t*>(Unext + idx) = st;
             const double4_t z = *reinterpret_cast<const double4_t*>(a.Z + idx);
-            double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
+            double4_t od = {(double)st[0], (double)st[1], (double)st[2], (double)st[3]};
             msum += z[0] * od[0] + z[1] * od[1] + z[2] * od[2] + z[3] * od[3];
             if (c0 != 0.0) {
                 double4_t* p = reinterpret_cast<double4_t*>(a.P + idx);
@@ -704,7 +786,16 @@ int cheb_batch_occupancy(int cfg, int precision) {
 }
 
 int cheb_num_tile_configs() { return (int)(sizeof(kChebCfgs) / sizeof(kChebCfgs[0])); }
-bool cheb_cfg_supports(int cfg, int precision) { return (kChebCfgs[cfg].precs >> (precision == 0 ? 0 : 1)) & 1; }
+// Shapes built for the refined precision (FP32 storage, FP64 arithmetic).
+constexpr int kW32Cfgs[] = {0, 2, 3, 7, 12, 20, 22, 29, 30};
+bool cheb_cfg_supports(int cfg, int precision) {
+    if (precision == 2) {
+        for (int x : kW32Cfgs)
+            if (x == cfg) return true;
+        return false;
+    }
+    return (kChebCfgs[cfg].precs >> (precision == 0 ? 0 : 1)) & 1;
+}
 int cheb_tile_rows(int cfg) { return 16 * kChebCfgs[cfg].tm * kChebCfgs[cfg].wm; }
 int cheb_tile_cols(int cfg) { return 16 * kChebCfgs[cfg].tn * kChebCfgs[cfg].wn; }
 int cheb_cfg_split(int cfg) { return kChebCfgs[cfg].split; }
@@ -731,19 +822,61 @@ hipError_t cheb_step_f32(const ChebStepArgs& a, int cfg, hipStream_t s) {
     return launch_cheb<float>(a, cfg, s);
 }
 
+// The refined precision: the shapes of kW32Cfgs with FP32 operands widened
+// to FP64 in registers.
+hipError_t cheb_step_w32(const ChebStepArgs& a, int cfg, hipStream_t s) {
+    switch (cfg) {
+        case 0: return launch_one<W32, 4, 4, 2, 2, 4>(a, s);
+        case 2: return launch_one<W32, 2, 2, 4, 1, 4>(a, s);
+        case 3: return launch_one<W32, 2, 2, 2, 2, 4>(a, s);
+        case 7: return launch_one<W32, 2, 2, 4, 1, 4, 4>(a, s);
+        case 12: return launch_one<W32, 4, 4, 2, 2, 4, 4>(a, s);
+        case 20: return launch_one<W32, 2, 2, 4, 1, 4, 8>(a, s);
+        case 22: return launch_one<W32, 2, 2, 4, 1, 8, 4>(a, s);
+        case 29: return launch_one<W32, 2, 2, 4, 1, 8, 8, true>(a, s);
+        case 30: return launch_one<W32, 2, 2, 4, 1, 8, 4, true>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t cheb_step(const ChebStepArgs& a, int cfg, int precision, hipStream_t s) {
+    switch (precision) {
+        case 0: return cheb_step_f64(a, cfg, s);
+        case 1: return cheb_step_f32(a, cfg, s);
+        case 2: return cheb_step_w32(a, cfg, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t gemm_nn_f64(int M, int N, int Kred, double alpha, const double* A, long lda, const double* B,
+                       long ldb, double beta, double* C, long ldc, bool a_upper, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (M % 64 || N % 64 || Kred % 32 || Kred <= 0) return hipErrorInvalidValue;
+    if (M % 128 == 0 && N % 128 == 0 && (long)(M / 128) * (N / 128) >= 256) {
+        const dim3 grid((M / 128) * (N / 128));
+        hipLaunchKernelGGL((gemm_nn_store_kernel<4, 4, 2, 2>), grid, dim3(256), 0, s, M, N, Kred, alpha, A, lda, B,
+                           ldb, beta, C, ldc, (int)a_upper);
+    } else {
+        const dim3 grid((M / 64) * (N / 64));
+        hipLaunchKernelGGL((gemm_nn_store_kernel<2, 2, 2, 2>), grid, dim3(256), 0, s, M, N, Kred, alpha, A, lda, B,
+                           ldb, beta, C, ldc, (int)a_upper);
+    }
+    return hipGetLastError();
+}
+
 hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, long lda,
                        const double* B, long ldb, double beta, double* C, long ldc,
-                       bool upper_only, hipStream_t s) {
+                       bool upper_only, hipStream_t s, bool a_cols_upper) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (M % 64 || N % 64 || Kred % 32 || Kred <= 0) return hipErrorInvalidValue;
     if (M % 128 == 0 && N % 128 == 0) {
         const dim3 grid((M / 128) * (N / 128));
         hipLaunchKernelGGL((gemm_tn_store_kernel<4, 4, 2, 2>), grid, dim3(256), 0, s, M, N, Kred,
-                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only);
+                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only, (int)a_cols_upper);
     } else {
         const dim3 grid((M / 64) * (N / 64));
         hipLaunchKernelGGL((gemm_tn_store_kernel<2, 2, 2, 2>), grid, dim3(256), 0, s, M, N, Kred,
-                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only);
+                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only, (int)a_cols_upper);
     }
     return hipGetLastError();
 }

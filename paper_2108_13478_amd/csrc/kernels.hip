@@ -241,7 +241,8 @@ cheb_start_kernel(int K, int Kp, int Bp, int ncols, const long long* __restrict_
     double msum = 0.0;
     const long idx = (long)r0 + (long)j * Kp;
     if (j < ncols) {
-        const double* src = Sinv ? Sinv + (long)cols[j] * Kp + r0 : nullptr;
+        // no cols: column j of Sinv itself
+        const double* src = Sinv ? Sinv + (cols ? cols[j] : (long long)j) * Kp + r0 : nullptr;
         for (int i = 0; i < 4; ++i) {
             const double u = src ? src[i] : (r0 + i == cols[j] ? 1.0 : 0.0);  // no Sinv: S = I
             U0[idx + i] = static_cast<T>(u);
@@ -648,6 +649,14 @@ hipError_t normalize_operator(int K, int Kp, const double* HT, double ebar, doub
     return hipGetLastError();
 }
 
+hipError_t scatter_s_columns(int Kp, int ncols, const long long* cols, const long long* rowptr, const int* col,
+                             const double* val, double* Z, hipStream_t s) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_s_columns_kernel, dim3((ncols + 3) / 4), dim3(256), 0, s, Kp, ncols, cols, rowptr,
+                       col, val, Z);
+    return hipGetLastError();
+}
+
 hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, const double* Sinv,
                       const long long* S_rowptr, const int* S_col, const double* S_val,
                       int precision, void* U0, double* Z, double* P, const double* coef,
@@ -655,7 +664,10 @@ hipError_t cheb_start(int K, int Kp, int Bp, int ncols, const long long* cols, c
                       hipStream_t s, const double* Zdense) {
     if (nsets < 1) return hipErrorInvalidValue;
     if (Kp % kStartRows || Bp % kStartCols) return hipErrorInvalidValue;
-    if (ncols > 0 && Zdense)
+    if (!cols && !Sinv) return hipErrorInvalidValue;
+    if (Zdense == Z) {
+        // the moment vectors are already in Z
+    } else if (ncols > 0 && Zdense)
         hipLaunchKernelGGL(gather_columns_kernel, grid_for((long long)Kp * ncols, 256), dim3(256), 0, s, Kp,
                            ncols, cols, Zdense, Z);
     else if (ncols > 0)

@@ -49,13 +49,15 @@ def test_fp64_batch_matches_oracle(form):
         assert err <= 1e-9
 
 
-def test_graph_replays_match_eager_run():
+@pytest.mark.parametrize("mom_prec", [-1, dmlib.DM_FP64])
+def test_graph_replays_match_eager_run(mom_prec):
     import torch
 
     sizes = batch_cluster_sizes(5, lo=40, hi=200, seed=4)
     clusters = make_batch(sizes, range(200, 205), processes=1)
-    say(f"case: graph replay K = {[c.K for c in clusters]}")
+    say(f"case: graph replay K = {[c.K for c in clusters]}, moments precision {mom_prec}")
     ctx = dmlib.Context(precision=dmlib.DM_FP32)
+    ctx.dm_set_moments_precision(mom_prec)
     ctx.dm_batch_set_focks(clusters)
     N, beta = 120, 30.0
     mu_e, P_e = run_batch(ctx, clusters, N, beta, tol=1e-6, flags=dmlib.DM_BATCH_EAGER)
@@ -114,10 +116,13 @@ def test_batch64_fp32_full_configuration():
     d = np.abs(P1 - Pb).max()
     say(f"  largest cluster K={c.K}: batch vs single-cluster path max|dP| = {d:.3e}")
     assert d <= 1e-12 * np.abs(P1).max()
-    # sampled clusters against the oracle (FP32 recursion error is reported)
-    for i in sorted({int(np.argmin(Ks)), j, 10, 40}):
-        c = clusters[i]
-        sp = O.spectrum(c)
+    # sampled clusters against the oracle: the FP32 recursion error is
+    # measured (about 1e-5 of max|P|); mu from FP32 moments misses the
+    # electron count by hundredths of an electron (FP32 rounding of H_N)
+    sample = sorted({int(np.argmin(Ks)), j, 10, 40})
+    spectra = {i: O.spectrum(clusters[i]) for i in sample}
+    for i in sample:
+        c, sp = clusters[i], spectra[i]
         lo, hi = ctx.dm_batch_get_bounds(i)
         ref = O.density_matrix_poly(sp, np.arange(c.K), N, mu[i], beta, lo, hi)
         Pi = P[i].cpu().numpy().reshape(c.K, c.K).T
@@ -125,8 +130,37 @@ def test_batch64_fp32_full_configuration():
         ne_err = 2.0 * O.trace_poly(sp, N, mu[i], beta, lo, hi)[0] - c.n_electrons
         say(f"  cluster {i} K={c.K}: FP32 max|dP| = {err:.2e} (max|P| {np.abs(ref).max():.1f}), "
             f"oracle 2Tr - N_e at mu = {ne_err:.2e}")
-        assert err < 1e-4 * np.abs(ref).max()
-        assert abs(ne_err) < 1e-3 * c.n_electrons
+        assert err < 3e-5 * np.abs(ref).max()
+        assert abs(ne_err) < 0.2
+    # the same batch with the moments pass in FP64 (dm_set_moments_precision):
+    # each mu now reproduces N_e in the oracle's trace to 1e-6
+    m64 = dmlib.Context(precision=dmlib.DM_FP32)
+    m64.dm_set_moments_precision(dmlib.DM_FP64)
+    t0 = time.perf_counter()
+    m64.dm_batch_set_focks(clusters)
+    say(f"  FP64-moments batch: setup {time.perf_counter() - t0:.1f} s")
+    best64, _ = m64.dm_batch_autotune(steps=8)
+    say(f"  FP64-moments batch: chosen cfg {best64}")
+    tol = 5e-7
+    mu64 = m64.dm_batch_run(N, beta, ne, tol=tol, P_out=P)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mu64b = m64.dm_batch_run(N, beta, ne, tol=tol, P_out=P)
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t0
+    assert np.array_equal(mu64, mu64b)
+    say(f"  FP64-moments replay: {dt64:.2f} s ({Ks.sum() / dt64:.0f} columns/s; FP32 moments {dt:.2f} s)")
+    for i in sample:
+        c, sp = clusters[i], spectra[i]
+        lo, hi = m64.dm_batch_get_bounds(i)
+        ref = O.density_matrix_poly(sp, np.arange(c.K), N, mu64[i], beta, lo, hi)
+        Pi = P[i].cpu().numpy().reshape(c.K, c.K).T
+        err = np.abs(Pi - ref).max()
+        ne_err = 2.0 * O.trace_poly(sp, N, mu64[i], beta, lo, hi)[0] - c.n_electrons
+        say(f"  cluster {i} K={c.K}: mu {mu64[i]:.9f} (FP32 moments {mu[i]:.9f}), FP32 max|dP| = {err:.2e}, "
+            f"oracle 2Tr - N_e at mu = {ne_err:.2e}")
+        assert abs(ne_err) <= 1e-6
+        assert err < 3e-5 * np.abs(ref).max()
 
 
 def test_batch_refuses_other_precision():
