@@ -4,6 +4,9 @@
 // vectors runs in the HIP kernels of gemm.hip and kernels.hip; the host only
 // orders launches and evaluates the k x k Lanczos tridiagonal.
 #include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstdarg>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,6 +37,24 @@ struct DevBuf {
 };
 
 long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+// Progress of long operator setups on stderr when the environment variable
+// DM_LOG is set (minutes at K ~ 10^5): phase, elapsed seconds.
+struct SetupLog {
+    bool on = std::getenv("DM_LOG") != nullptr;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    void operator()(const char* fmt, ...) const {
+        if (!on) return;
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr, "[dm setup %7.1f s] ", dt);
+        va_list ap;
+        va_start(ap, fmt);
+        std::vfprintf(stderr, fmt, ap);
+        va_end(ap);
+        std::fputc('\n', stderr);
+        std::fflush(stderr);
+    }
+};
 
 }  // namespace
 
@@ -95,8 +116,13 @@ struct Op {
     // Lanczos interval)
     int form = DM_FORM_GENERAL;
     DevBuf<double> Xs;
+    // F in groups of four rows (sym_panels' sparse products)
+    DevBuf<long long> Fg_ptr;
+    DevBuf<int> Fg_col;
+    DevBuf<double> Fg_val;
     bool sym_raw = false;
     int hn_precision_raw = -1;
+    double hn_lo = 0, hn_hi = 0;  // interval HNbuf was last normalised with
     // orthonormal basis (dm_set_fock_orthonormal): S = I, H = F kept in CSR
     // (S_* then hold the identity), no dense S^-1 / H^T
     bool orth = false;
@@ -113,6 +139,7 @@ struct Op {
         S_rowptr.release(); S_col.release(); S_val.release();
         Sinv.release(); HT.release(); HNbuf.release(); HN64.release();
         Xs.release();
+        Fg_ptr.release(); Fg_col.release(); Fg_val.release();
         sym_raw = false;
         F_rowptr.release(); F_col.release(); F_val.release();
         K = 0; Kp = 0; form = DM_FORM_GENERAL; orth = false;
@@ -519,7 +546,10 @@ dm_status normalize(dm_ctx* c, Op& op) {
     }
     if (op.form == DM_FORM_SYMMETRIC) {
         const size_t tsz = c->precision == DM_FP64 ? 8 : 4;
-        if (op.sym_raw && op.hn_precision_raw == c->precision) {
+        const bool same_storage = (op.hn_precision == DM_FP64) == (c->precision == DM_FP64);
+        if (!op.sym_raw && op.hn_precision >= 0 && same_storage && op.hn_lo == op.emin && op.hn_hi == op.emax) {
+            // FP32 <-> refined FP32: the stored H~_N is the same array
+        } else if (op.sym_raw && op.hn_precision_raw == c->precision) {
             // right after the panels: H~ -> H~_N in place
             HIPTRY(c, normalize_inplace((int)op.K, op.Kp, c->precision, op.HNbuf.p, ebar, de, c->stream));
         } else {
@@ -531,6 +561,8 @@ dm_status normalize(dm_ctx* c, Op& op) {
         }
         op.sym_raw = false;
         op.hn_precision = c->precision;
+        op.hn_lo = op.emin;
+        op.hn_hi = op.emax;
         return DM_OK;
     }
     HIPTRY(c, normalize_operator((int)op.K, op.Kp, op.HT.p, ebar, de, c->precision, op.HNbuf.p, c->stream));
@@ -624,6 +656,43 @@ dm_status load_csr_pair(dm_ctx* c, long long K, const long long* F_rowptr, const
     return DM_OK;
 }
 
+// Blocked right-looking Cholesky S = U^T U in place on the Kp x Kp
+// column-major A (upper triangle; below it the entries are left stale).
+// Block rows of kChol = 256: inside one, 64-wide steps factor the diagonal
+// block (one workgroup, which also writes its inverse U_kk^-1 to V), solve
+// the step's rows U12 = U_kk^-T A12 and update the remaining rows of the
+// block row; the rows below then get one rank-256 update, which moves a
+// quarter of the trailing-matrix bytes of rank-64 updates.
+// V: Kp/64 blocks of 64 x 64; tmp: 64 x Kp.  Errors in flag (pivot + 1).
+constexpr int kChol = 256;
+hipError_t chol_upper(double* A, int Kp, double* V, double* tmp, int* flag, hipStream_t s) {
+    const long ld = Kp;
+    hipError_t e = hipSuccess;
+    for (int K0 = 0; K0 < Kp && e == hipSuccess; K0 += kChol) {
+        for (int k = K0; k < K0 + kChol && e == hipSuccess; k += kNb) {
+            double* Vk = V + (size_t)(k / kNb) * kNb * kNb;
+            e = potrf_diag(A + k + (long)k * ld, ld, Vk, flag, k, s);
+            const int n2 = Kp - k - kNb;
+            if (e != hipSuccess || n2 <= 0) continue;
+            e = gemm_tn_f64(kNb, n2, kNb, 1.0, Vk, kNb, A + k + (long)(k + kNb) * ld, ld, 0.0, tmp, kNb, false, s);
+            if (e == hipSuccess)
+                e = hipMemcpy2DAsync(A + k + (long)(k + kNb) * ld, ld * 8, tmp, kNb * 8, kNb * 8, n2,
+                                     hipMemcpyDeviceToDevice, s);
+            const int r = K0 + kChol - k - kNb;  // rows of the block row still to update
+            if (e == hipSuccess && r > 0)
+                e = gemm_tn_f64(r, n2, kNb, -1.0, tmp, kNb, tmp, kNb, 1.0, A + (k + kNb) + (long)(k + kNb) * ld, ld,
+                                true, s);
+        }
+        const int n3 = Kp - K0 - kChol;
+        if (e == hipSuccess && n3 > 0) {
+            const double* Ub = A + K0 + (long)(K0 + kChol) * ld;  // U[K0 : K0 + 256, K0 + 256 :]
+            e = gemm_tn_f64(n3, n3, kChol, -1.0, Ub, ld, Ub, ld, 1.0, A + (K0 + kChol) + (long)(K0 + kChol) * ld, ld,
+                            true, s);
+        }
+    }
+    return e;
+}
+
 // Operator setup for one (F, S): S = U^T U, S^-1, H^T, Lanczos interval, H_N.
 dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const HostCsr& Sh, int form) {
     const std::vector<long long>& frp = Fh.rp;
@@ -683,21 +752,8 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
     ST(fill_f64(A, 0.0, (long long)KK, s));
     ST(csr_to_dense((int)K, Kp, op.S_rowptr.p, op.S_col.p, op.S_val.p, 1.0, A, s));
     ST(fill_i32(c->flag.p, 0, 4, s));
-    // ---- blocked Cholesky S = U^T U (upper, right-looking)
-    for (int k = 0; k < Kp; k += kNb) {
-        double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
-        ST(potrf_diag(A + k + (long)k * ld, ld, Vk, c->flag.p, k, s));
-        const int n2 = Kp - k - kNb;
-        if (n2 > 0) {
-            // U12 = U_kk^-T A12, then A22 -= U12^T U12 (upper tiles only)
-            ST(gemm_tn_f64(kNb, n2, kNb, 1.0, Vk, kNb, A + k + (long)(k + kNb) * ld, ld, 0.0, tmp.p,
-                           kNb, false, s));
-            ST(hipMemcpy2DAsync(A + k + (long)(k + kNb) * ld, ld * 8, tmp.p, kNb * 8, kNb * 8, n2,
-                                hipMemcpyDeviceToDevice, s));
-            ST(gemm_tn_f64(n2, n2, kNb, -1.0, tmp.p, kNb, tmp.p, kNb, 1.0,
-                           A + (k + kNb) + (long)(k + kNb) * ld, ld, true, s));
-        }
-    }
+    // ---- blocked Cholesky S = U^T U (upper)
+    ST(chol_upper(A, Kp, Vblk.p, tmp.p, c->flag.p, s));
     int info[4] = {0, 0, 0, 0};
     ST(hipMemcpyAsync(info, c->flag.p, sizeof(info), hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
@@ -732,9 +788,11 @@ dm_status build_op(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Host
 
 // H~_N = (X^T F X - ebar I) / de (ebar = 0, de = 1: H~ itself) into dst in
 // `precision`, by column panels J of width w: P = X[:, J] transposed to a
-// row-major panel (X[:, J] is zero below row max J), Y = F P by the CSR
-// product, Y back to column-major, then X^T Y on the MFMA (X upper: row tile
-// r sums k <= r only) and the panel stored with the shift and scale.
+// row-major panel (X[:, J] is zero below row max J), Y = F P by the sparse
+// product over groups of four rows, Y back to column-major, then the rows
+// from j0 on of X^T Y on the MFMA (X upper: row tile r sums k <= r only) and
+// the panel stored with the shift and scale; the upper triangle is then the
+// mirror image of the lower one.
 dm_status sym_panels(dm_ctx* c, Op& op, double ebar, double de, int precision, void* dst) {
     hipStream_t s = c->stream;
     const int Kp = op.Kp;
@@ -743,16 +801,27 @@ dm_status sym_panels(dm_ctx* c, Op& op, double ebar, double de, int precision, v
     DevBuf<double> pa, pb;
     hipError_t e = ensure(pa, (size_t)Kp * w);
     if (e == hipSuccess) e = ensure(pb, (size_t)Kp * w);
+    const SetupLog log;
     for (int j0 = 0; j0 < Kp && e == hipSuccess; j0 += w) {
+        if (log.on && j0 > 0 && j0 % (16 * w) == 0) {
+            e = hipStreamSynchronize(s);
+            log("panel columns %d of %d", j0, Kp);
+            if (e != hipSuccess) break;
+        }
         const int kmax = j0 + w;
         e = transpose_rect(kmax, w, op.Xs.p + (long)j0 * ld, ld, pa.p, w, s);
         if (e == hipSuccess)
-            e = csr_spmm_rm((int)op.K, op.F_rowptr.p, op.F_col.p, op.F_val.p, w, pa.p, kmax, pb.p, s);
+            e = rg4_spmm_rm((int)op.K, op.Fg_ptr.p, op.Fg_col.p, op.Fg_val.p, w, pa.p, kmax, pb.p, s);
         if (e == hipSuccess && Kp > op.K) e = fill_f64(pb.p + (size_t)op.K * w, 0.0, (long long)(Kp - op.K) * w, s);
         if (e == hipSuccess) e = transpose_rect(w, Kp, pb.p, w, pa.p, Kp, s);
-        if (e == hipSuccess) e = gemm_tn_f64(Kp, w, Kp, 1.0, op.Xs.p, ld, pa.p, Kp, 0.0, pb.p, Kp, false, s, true);
-        if (e == hipSuccess) e = store_panel((int)op.K, Kp, w, j0, pb.p, ebar, 1.0 / de, precision, dst, s);
+        // rows j0 .. Kp of the panel only (H~ is symmetric; the rows above
+        // come from earlier panels' columns, mirrored below)
+        if (e == hipSuccess)
+            e = gemm_tn_f64(Kp - j0, w, Kp, 1.0, op.Xs.p + (long)j0 * ld, ld, pa.p, Kp, 0.0, pb.p + j0, Kp, false, s,
+                            j0);
+        if (e == hipSuccess) e = store_panel((int)op.K, Kp, w, j0, j0, pb.p, ebar, 1.0 / de, precision, dst, s);
     }
+    if (e == hipSuccess) e = mirror_lower(Kp, precision, dst, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     pa.release();
     pb.release();
@@ -771,6 +840,8 @@ dm_status sym_panels(dm_ctx* c, Op& op, double ebar, double de, int precision, v
 // (p = 8 or 4 for the recursion precision) plus panels and the CSR arrays.
 dm_status build_sym(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const HostCsr& Sh) {
     hipStream_t s = c->stream;
+    const SetupLog log;
+    log("symmetric form, K = %lld: start", K);
     op.release();
     op.K = K;
     op.Kp = (int)round_up(K, kRowPad);
@@ -790,6 +861,40 @@ dm_status build_sym(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Hos
     HIPTRY(c, hipMemcpyAsync(op.F_rowptr.p, Fh.rp.data(), Fh.rp.size() * 8, hipMemcpyHostToDevice, s));
     HIPTRY(c, hipMemcpyAsync(op.F_col.p, Fh.col.data(), Fh.col.size() * 4, hipMemcpyHostToDevice, s));
     HIPTRY(c, hipMemcpyAsync(op.F_val.p, Fh.val.data(), Fh.val.size() * 8, hipMemcpyHostToDevice, s));
+    {
+        // F in groups of four rows: per group the sorted union of the rows'
+        // columns, four values per column (zero where a row has none)
+        const long long ng = (K + 3) / 4;
+        std::vector<long long> gp((size_t)ng + 1, 0);
+        std::vector<int> gc;
+        std::vector<double> gv;
+        gc.reserve(Fh.col.size() / 3);
+        gv.reserve(Fh.col.size() * 4 / 3);
+        for (long long g = 0; g < ng; ++g) {
+            long long pos[4], end[4];
+            for (int r = 0; r < 4; ++r) {
+                const long long row = 4 * g + r;
+                pos[r] = row < K ? Fh.rp[row] : 0;
+                end[r] = row < K ? Fh.rp[row + 1] : 0;
+            }
+            for (;;) {
+                int next = INT32_MAX;
+                for (int r = 0; r < 4; ++r)
+                    if (pos[r] < end[r]) next = std::min(next, Fh.col[pos[r]]);
+                if (next == INT32_MAX) break;
+                gc.push_back(next);
+                for (int r = 0; r < 4; ++r)
+                    gv.push_back(pos[r] < end[r] && Fh.col[pos[r]] == next ? Fh.val[pos[r]++] : 0.0);
+            }
+            gp[g + 1] = (long long)gc.size();
+        }
+        HIPTRY(c, ensure(op.Fg_ptr, gp.size()));
+        HIPTRY(c, ensure(op.Fg_col, std::max<size_t>(gc.size(), 1)));
+        HIPTRY(c, ensure(op.Fg_val, std::max<size_t>(gv.size(), 1)));
+        HIPTRY(c, hipMemcpy(op.Fg_ptr.p, gp.data(), gp.size() * 8, hipMemcpyHostToDevice));
+        if (!gc.empty()) HIPTRY(c, hipMemcpy(op.Fg_col.p, gc.data(), gc.size() * 4, hipMemcpyHostToDevice));
+        if (!gv.empty()) HIPTRY(c, hipMemcpy(op.Fg_val.p, gv.data(), gv.size() * 8, hipMemcpyHostToDevice));
+    }
     DevBuf<double> Vblk, tmp;
     auto release_tmp = [&]() { Vblk.release(); tmp.release(); };
     hipError_t e;
@@ -808,49 +913,57 @@ dm_status build_sym(dm_ctx* c, Op& op, long long K, const HostCsr& Fh, const Hos
     ST(fill_f64(A, 0.0, (long long)KK, s));
     ST(csr_to_dense((int)K, Kp, op.S_rowptr.p, op.S_col.p, op.S_val.p, 1.0, A, s));
     ST(fill_i32(c->flag.p, 0, 4, s));
-    // ---- blocked Cholesky S = U^T U (upper, right-looking), as in build_op
-    for (int k = 0; k < Kp; k += kNb) {
-        double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
-        ST(potrf_diag(A + k + (long)k * ld, ld, Vk, c->flag.p, k, s));
-        const int n2 = Kp - k - kNb;
-        if (n2 > 0) {
-            ST(gemm_tn_f64(kNb, n2, kNb, 1.0, Vk, kNb, A + k + (long)(k + kNb) * ld, ld, 0.0, tmp.p, kNb, false, s));
-            ST(hipMemcpy2DAsync(A + k + (long)(k + kNb) * ld, ld * 8, tmp.p, kNb * 8, kNb * 8, n2,
-                                hipMemcpyDeviceToDevice, s));
-            ST(gemm_tn_f64(n2, n2, kNb, -1.0, tmp.p, kNb, tmp.p, kNb, 1.0, A + (k + kNb) + (long)(k + kNb) * ld, ld,
-                           true, s));
-        }
-    }
+    // ---- blocked Cholesky S = U^T U (upper), as in build_op
+    log("dense S built");
+    ST(chol_upper(A, Kp, Vblk.p, tmp.p, c->flag.p, s));
     int info[4] = {0, 0, 0, 0};
     ST(hipMemcpyAsync(info, c->flag.p, sizeof(info), hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
+    log("Cholesky done");
     if (info[0] != 0) {
         release_tmp();
         return set_err(c, DM_E_NOTSPD,
                        "overlap matrix is not positive definite (pivot " + std::to_string(info[0] - 1) + ")");
     }
-    // ---- X = U^-1 in place (the trailing updates left S below the diagonal)
+    // ---- X = U^-1 in place (the trailing updates left S below the diagonal),
+    // by block columns of 256: the diagonal block D is inverted in place by
+    // 64-wide steps (D12 := -D11^-1 D12 D22^-1 with the Cholesky's inverses
+    // of the 64 x 64 blocks), then the block column above it becomes
+    // X12 = -X11 U12 D^-1, two MFMA products 256 columns wide
     ST(zero_strict_lower(Kp, A, s));
-    for (int k = 0; k < Kp; k += kNb) {
-        const double* Vk = Vblk.p + (size_t)(k / kNb) * kNb * kNb;
-        if (k > 0) {
-            // tmp = X11 U12, then X12 = -tmp U22^-1 (U22^-1 from the Cholesky)
-            ST(gemm_nn_f64(k, kNb, k, 1.0, A, ld, A + (long)k * ld, ld, 0.0, tmp.p, Kp, true, s));
-            ST(gemm_nn_f64(k, kNb, kNb, -1.0, tmp.p, Kp, Vk, kNb, 0.0, A + (long)k * ld, ld, false, s));
+    tmp.release();
+    ST(ensure(tmp, (size_t)Kp * kChol));
+    for (int K0 = 0; K0 < Kp; K0 += kChol) {
+        double* D = A + K0 + (long)K0 * ld;
+        for (int k = 0; k < kChol; k += kNb) {
+            const double* Vk = Vblk.p + (size_t)((K0 + k) / kNb) * kNb * kNb;
+            if (k > 0) {
+                ST(gemm_nn_f64(k, kNb, k, 1.0, D, ld, D + (long)k * ld, ld, 0.0, tmp.p, Kp, true, s));
+                ST(gemm_nn_f64(k, kNb, kNb, -1.0, tmp.p, Kp, Vk, kNb, 0.0, D + (long)k * ld, ld, false, s));
+            }
+            ST(set_upper_block(kNb, D + k + (long)k * ld, ld, Vk, s));
         }
-        ST(set_upper_block(kNb, A + k + (long)k * ld, ld, Vk, s));
+        if (K0 > 0) {
+            ST(gemm_nn_f64(K0, kChol, K0, 1.0, A, ld, A + (long)K0 * ld, ld, 0.0, tmp.p, Kp, true, s));
+            ST(gemm_nn_f64(K0, kChol, kChol, -1.0, tmp.p, Kp, D, ld, 0.0, A + (long)K0 * ld, ld, false, s));
+        }
     }
     ST(hipStreamSynchronize(s));
     release_tmp();
 #undef ST
+    log("X = U^-1 done");
     op.form = DM_FORM_SYMMETRIC;
     dm_status st = sym_panels(c, op, 0.0, 1.0, c->precision, op.HNbuf.p);
     if (st != DM_OK) return st;
+    log("H~ = X^T F X done");
     op.sym_raw = true;
     op.hn_precision_raw = c->precision;
     st = lanczos_bounds(c, op);
     if (st != DM_OK) return st;
-    return normalize(c, op);
+    log("Lanczos interval [%.4f, %.4f]", op.emin, op.emax);
+    st = normalize(c, op);
+    log("normalised");
+    return st;
 }
 
 // Operator setup in an orthonormal basis (S = I): F in CSR on the device,
@@ -1218,12 +1331,12 @@ dm_status dm_get_operator(dm_ctx* c, int which, double* out) try {
             e = fill_f64(W.p, 0.0, (long long)(Kp * Kp), s);
             if (e == hipSuccess) e = csr_to_dense((int)K, kp, op.F_rowptr.p, op.F_col.p, op.F_val.p, 0.0, W.p, s);
             if (e == hipSuccess && which == DM_OP_H) {
-                e = gemm_tn_f64(kp, kp, kp, 1.0, op.Xs.p, kp, W.p, kp, 0.0, T.p, kp, false, s, true);
+                e = gemm_tn_f64(kp, kp, kp, 1.0, op.Xs.p, kp, W.p, kp, 0.0, T.p, kp, false, s, 0);
                 if (e == hipSuccess) e = gemm_nn_f64(kp, kp, kp, 1.0, op.Xs.p, kp, T.p, kp, 0.0, W.p, kp, true, s);
                 std::swap(W, T);
             } else if (e == hipSuccess) {
                 e = gemm_nn_f64(kp, kp, kp, 1.0, W.p, kp, op.Xs.p, kp, 0.0, T.p, kp, false, s);
-                if (e == hipSuccess) e = gemm_tn_f64(kp, kp, kp, 1.0, op.Xs.p, kp, T.p, kp, 0.0, W.p, kp, false, s, true);
+                if (e == hipSuccess) e = gemm_tn_f64(kp, kp, kp, 1.0, op.Xs.p, kp, T.p, kp, 0.0, W.p, kp, false, s, 0);
                 std::swap(W, T);
             }
         }
@@ -1285,7 +1398,7 @@ static hipError_t sym_start(const Op& op, int Bp, int B64, int ncols, const long
     const int Kp = op.Kp;
     hipError_t e = fill_f64(vbuf, 0.0, (long long)Kp * B64, s);
     if (e == hipSuccess) e = scatter_s_columns(Kp, ncols, cols, op.S_rowptr.p, op.S_col.p, op.S_val.p, vbuf, s);
-    if (e == hipSuccess) e = gemm_tn_f64(Kp, B64, Kp, 1.0, op.Xs.p, Kp, vbuf, Kp, 0.0, Z, Kp, false, s, true);
+    if (e == hipSuccess) e = gemm_tn_f64(Kp, B64, Kp, 1.0, op.Xs.p, Kp, vbuf, Kp, 0.0, Z, Kp, false, s, 0);
     if (e == hipSuccess) e = gather_rows(Kp, ncols, cols, op.Xs.p, vbuf, s);
     if (e == hipSuccess)
         e = cheb_start((int)op.K, Kp, Bp, ncols, nullptr, vbuf, op.S_rowptr.p, op.S_col.p, op.S_val.p, precision, U0,
@@ -2555,6 +2668,9 @@ dm_status dm_batch_set_focks(dm_ctx* c, int n, const dm_csr_pair* cl) try {
         c->batch[i].F_rowptr.release();
         c->batch[i].F_col.release();
         c->batch[i].F_val.release();
+        c->batch[i].Fg_ptr.release();
+        c->batch[i].Fg_col.release();
+        c->batch[i].Fg_val.release();
     }
     c->bstate = new BatchState();
     c->bstate->cl.resize(n);

@@ -30,11 +30,12 @@ hipError_t gemm_nn_f64(int M, int N, int Kred, double alpha, const double* A, lo
 // M, N multiples of 64, Kred multiple of 32, operands FP64.  With
 // upper_only, output tiles entirely below the diagonal (m0 >= n0 + tile) are
 // skipped (used where only the upper triangle of a symmetric result is read).
-// a_cols_upper: column m of A is zero below row m (A upper triangular), so
-// a row tile's sum stops after its last row.
+// a_upper_row0 >= 0: column m of A is zero below row a_upper_row0 + m (an
+// upper triangular matrix whose columns from a_upper_row0 on are C's rows),
+// so a row tile's sum stops after its last row; -1: no such structure.
 hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, long lda,
                        const double* B, long ldb, double beta, double* C, long ldc,
-                       bool upper_only, hipStream_t s, bool a_cols_upper = false);
+                       bool upper_only, hipStream_t s, int a_upper_row0 = -1);
 
 // One step of the Chebyshev column recursion with the fused epilogue:
 //   Unext = alpha * (HN * Ucur) - (has_prev ? Uprev : 0)      (storage T)
@@ -244,10 +245,18 @@ hipError_t gather_rows(int Kp, int ncols, const long long* cols, const double* X
 // from kmax on are taken as zero
 hipError_t csr_spmm_rm(int K, const long long* rp, const int* col, const double* val, int w, const double* X,
                        int kmax, double* Y, hipStream_t s);
-// columns col0 .. col0 + w - 1 of H (Kp x Kp, precision 0: FP64, else FP32)
-// := (C - ebar I) inv_de on the K x K block, zero padding; C is Kp x w FP64
-hipError_t store_panel(int K, int Kp, int w, int col0, const double* C, double ebar, double inv_de, int precision,
-                       void* H, hipStream_t s);
+// the same with F in groups of four rows: gp (ceil(K/4) + 1 offsets), gc
+// (sorted union of a group's columns), gv (four values per listed column)
+hipError_t rg4_spmm_rm(int K, const long long* gp, const int* gc, const double* gv, int w, const double* X, int kmax,
+                       double* Y, hipStream_t s);
+// rows row0 .. Kp - 1 of columns col0 .. col0 + w - 1 of H (Kp x Kp,
+// precision 0: FP64, else FP32) := (C - ebar I) inv_de on the K x K block,
+// zero padding; C is Kp x w FP64
+hipError_t store_panel(int K, int Kp, int w, int col0, int row0, const double* C, double ebar, double inv_de,
+                       int precision, void* H, hipStream_t s);
+// upper triangle of H (Kp x Kp) := transpose of its lower triangle (the
+// 32 x 32 diagonal tiles are kept)
+hipError_t mirror_lower(int Kp, int precision, void* H, hipStream_t s);
 // H := (H - ebar I) / de in place on the K x K block
 hipError_t normalize_inplace(int K, int Kp, int precision, void* H, double ebar, double de, hipStream_t s);
 // y = A x, A row-major in FP64 (precision 0) or FP32, x and y FP64

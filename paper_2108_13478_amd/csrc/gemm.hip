@@ -305,18 +305,25 @@ template <int TM, int TN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_tn_store_kernel(int M, int N, int Kred, double alpha, const double* __restrict__ A, long lda,
                      const double* __restrict__ B, long ldb, double beta, double* __restrict__ C,
-                     long ldc, int upper_only, int k_to_row) {
+                     long ldc, int upper_only, int k_row0) {
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
-    const TilePos tp = tile_position<8>(M / BM, N / BN);
+    TilePos tp = tile_position<8>(M / BM, N / BN);
+    // with a reduction limit the tiles of the last rows carry the longest
+    // sums: they go first, so the launch does not end on them
+    if (k_row0 >= 0) tp.tile_m = M / BM - 1 - tp.tile_m;
     if (upper_only && tp.tile_m * BM >= (tp.tile_n + 1) * BN) return;
     const int wave = threadIdx.x >> 6;
     const int row0 = tp.tile_m * BM + (wave % WM) * TM * 16;
     const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
-    // k_to_row: column m of A is zero below row m, so the tile's rows need
-    // k < its last row + 1 only (rounded up to the slab pair)
-    const int kend = k_to_row ? min(Kred, (tp.tile_m * BM + BM + 31) / 32 * 32) : Kred;
+    // k_row0 >= 0: column m of A is zero below row k_row0 + m (A upper
+    // triangular, C's first row being row k_row0 of it), so the tile's rows
+    // need k < k_row0 + its last row + 1 only (rounded up to the slab pair)
+    const int kend = k_row0 >= 0 ? min(Kred, (k_row0 + tp.tile_m * BM + BM + 31) / 32 * 32) : Kred;
     double4_t acc[TM][TN];
-    gemm_mainloop<double, TM, TN, 4>(kend, A, lda, B, ldb, row0, col0, acc);
+    if (kend % 64 == 0)  // three slabs in flight (same k order as two buffers)
+        gemm_mainloop<double, TM, TN, 4, 4>(kend, A, lda, B, ldb, row0, col0, acc);
+    else
+        gemm_mainloop<double, TM, TN, 4>(kend, A, lda, B, ldb, row0, col0, acc);
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
@@ -347,7 +354,10 @@ gemm_nn_store_kernel(int M, int N, int Kred, double alpha, const double* __restr
     const int col0 = tp.tile_n * BN + (wave / WM) * TN * 16;
     const int k0 = k_from_row ? min(Kred, (tp.tile_m * BM) / 32 * 32) : 0;
     double4_t acc[TM][TN];
-    if (k0 < Kred) {
+    if (k0 < Kred && (Kred - k0) % 64 == 0) {
+        gemm_mainloop<double, TM, TN, 4, 4, false, true>(Kred - k0, A + (long)k0 * lda, lda, B + k0, ldb, row0,
+                                                         col0, acc);
+    } else if (k0 < Kred) {
         gemm_mainloop<double, TM, TN, 4, 2, false, true>(Kred - k0, A + (long)k0 * lda, lda, B + k0, ldb, row0,
                                                          col0, acc);
     } else {
@@ -866,17 +876,17 @@ hipError_t gemm_nn_f64(int M, int N, int Kred, double alpha, const double* A, lo
 
 hipError_t gemm_tn_f64(int M, int N, int Kred, double alpha, const double* A, long lda,
                        const double* B, long ldb, double beta, double* C, long ldc,
-                       bool upper_only, hipStream_t s, bool a_cols_upper) {
+                       bool upper_only, hipStream_t s, int a_upper_row0) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (M % 64 || N % 64 || Kred % 32 || Kred <= 0) return hipErrorInvalidValue;
     if (M % 128 == 0 && N % 128 == 0) {
         const dim3 grid((M / 128) * (N / 128));
         hipLaunchKernelGGL((gemm_tn_store_kernel<4, 4, 2, 2>), grid, dim3(256), 0, s, M, N, Kred,
-                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only, (int)a_cols_upper);
+                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only, a_upper_row0);
     } else {
         const dim3 grid((M / 64) * (N / 64));
         hipLaunchKernelGGL((gemm_tn_store_kernel<2, 2, 2, 2>), grid, dim3(256), 0, s, M, N, Kred,
-                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only, (int)a_cols_upper);
+                           alpha, A, lda, B, ldb, beta, C, ldc, (int)upper_only, a_upper_row0);
     }
     return hipGetLastError();
 }

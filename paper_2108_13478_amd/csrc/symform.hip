@@ -75,53 +75,96 @@ __global__ void __launch_bounds__(256) gather_rows_kernel(int Kp, int ncols, con
     }
 }
 
-// Y = F X for a row-major panel X (K x w, row k at X + k w) and CSR F:
-// one 256-thread workgroup per row, threads over the w columns (w <= 256 *
-// kSpmmCols), row entries in column order; entries with column >= kmax are
-// skipped (X is zero there) and end the row, columns being sorted.
-constexpr int kSpmmCols = 8;
-__global__ void __launch_bounds__(256) csr_spmm_rm_kernel(int K, const long long* __restrict__ rp,
-                                                          const int* __restrict__ col, const double* __restrict__ val,
-                                                          int w, const double* __restrict__ X, int kmax,
-                                                          double* __restrict__ Y) {
-    const int row = blockIdx.x;
-    if (row >= K) return;
-    double acc[kSpmmCols];
-#pragma unroll
-    for (int q = 0; q < kSpmmCols; ++q) acc[q] = 0.0;
+// Y = F X for a row-major panel X (K x w, row k at X + k w) and CSR F, in
+// column chunks of kSpmmChunk: workgroup b takes row b % K of chunk b / K,
+// so the workgroups in flight share one chunk of the panel (K x 128 FP64,
+// 134 MB at K = 131072, within the Infinity Cache) while they gather its
+// rows; a thread owns one column.  Row entries come in column order;
+// entries with column >= kmax are skipped (X is zero there) and end the
+// row.
+constexpr int kSpmmChunk = 128;
+__global__ void __launch_bounds__(kSpmmChunk) csr_spmm_rm_kernel(int K, const long long* __restrict__ rp,
+                                                                 const int* __restrict__ col,
+                                                                 const double* __restrict__ val, int w,
+                                                                 const double* __restrict__ X, int kmax,
+                                                                 double* __restrict__ Y) {
+    const long long b = blockIdx.x;
+    const int row = (int)(b % K);
+    const int j = (int)(b / K) * kSpmmChunk + threadIdx.x;
+    double acc = 0.0;
     for (long long p = rp[row]; p < rp[row + 1]; ++p) {
         const int k = col[p];
         if (k >= kmax) break;
-        const double v = val[p];
-        const double* x = X + (long)k * w;
-#pragma unroll
-        for (int q = 0; q < kSpmmCols; ++q) {
-            const int j = threadIdx.x + 256 * q;
-            if (j < w) acc[q] += v * x[j];
-        }
+        if (j < w) acc += val[p] * X[(long)k * w + j];
     }
-    double* y = Y + (long)row * w;
-#pragma unroll
-    for (int q = 0; q < kSpmmCols; ++q) {
-        const int j = threadIdx.x + 256 * q;
-        if (j < w) y[j] = acc[q];
-    }
+    if (j < w) Y[(long)row * w + j] = acc;
 }
 
-// Columns col0 .. col0 + w - 1 of the Kp x Kp matrix H (column-major, type
-// T) := (C - ebar I) inv_de (C: Kp x w column-major, FP64), zero outside the
-// K x K block.
+// The same product with F in groups of four rows (one atom of the
+// four-function basis): per group the sorted union of its rows' columns,
+// each with four values (zero where a row has no entry).  Every gathered
+// row of the panel then serves four rows of Y: a quarter of the gather
+// traffic of the CSR form.  Workgroup b: group b % ng, chunk b / ng.
+__global__ void __launch_bounds__(kSpmmChunk) rg4_spmm_rm_kernel(int K, int ng, const long long* __restrict__ gp,
+                                                                 const int* __restrict__ gc,
+                                                                 const double* __restrict__ gv, int w,
+                                                                 const double* __restrict__ X, int kmax,
+                                                                 double* __restrict__ Y) {
+    const long long b = blockIdx.x;
+    const int g = (int)(b % ng);
+    const int j = (int)(b / ng) * kSpmmChunk + threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (long long p = gp[g]; p < gp[g + 1]; ++p) {
+        const int k = gc[p];
+        if (k >= kmax) break;
+        if (j < w) {
+            const double x = X[(long)k * w + j];
+            const double* v = gv + 4 * p;
+            a0 += v[0] * x;
+            a1 += v[1] * x;
+            a2 += v[2] * x;
+            a3 += v[3] * x;
+        }
+    }
+    if (j >= w) return;
+    const int r0 = 4 * g;
+    if (r0 < K) Y[(long)r0 * w + j] = a0;
+    if (r0 + 1 < K) Y[(long)(r0 + 1) * w + j] = a1;
+    if (r0 + 2 < K) Y[(long)(r0 + 2) * w + j] = a2;
+    if (r0 + 3 < K) Y[(long)(r0 + 3) * w + j] = a3;
+}
+
+// Rows row0 .. Kp - 1 of columns col0 .. col0 + w - 1 of the Kp x Kp
+// matrix H (column-major, type T) := (C - ebar I) inv_de (C: Kp x w
+// column-major, FP64), zero outside the K x K block.
 template <typename T>
-__global__ void store_panel_kernel(int K, int Kp, int w, int col0, const double* __restrict__ C, double ebar,
-                                   double inv_de, T* __restrict__ H) {
+__global__ void store_panel_kernel(int K, int Kp, int w, int col0, int row0, const double* __restrict__ C,
+                                   double ebar, double inv_de, T* __restrict__ H) {
     const long long n = (long long)Kp * w;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const long long r = i % Kp, j = i / Kp, c = col0 + j;
+        if (r < row0) continue;
         double v = 0.0;
         if (r < K && c < K) v = (C[i] - (r == c ? ebar : 0.0)) * inv_de;
         H[r + c * Kp] = static_cast<T>(v);
     }
+}
+
+// Upper triangle of the Kp x Kp matrix H := mirror image of its lower one,
+// 32 x 32 tiles through LDS: block (bx, by), bx < by, reads tile (by, bx)
+// below the diagonal and writes its transpose to tile (bx, by); diagonal
+// tiles are left as they are.
+template <typename T>
+__global__ void __launch_bounds__(256) mirror_lower_kernel(int Kp, T* __restrict__ H) {
+    const int bx = blockIdx.x, by = blockIdx.y;
+    if (bx >= by) return;
+    __shared__ T tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const long r0 = (long)by * 32, c0 = (long)bx * 32;  // source tile rows by, columns bx
+    for (int j = ty; j < 32; j += 8) tile[j][tx] = H[(r0 + tx) + (c0 + j) * Kp];
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) H[(c0 + tx) + (r0 + j) * Kp] = tile[tx][j];
 }
 
 // H := (H - ebar I) inv_de in place on the K x K block, zero padding.
@@ -181,20 +224,44 @@ hipError_t gather_rows(int Kp, int ncols, const long long* cols, const double* X
 
 hipError_t csr_spmm_rm(int K, const long long* rp, const int* col, const double* val, int w, const double* X,
                        int kmax, double* Y, hipStream_t s) {
-    if (w < 1 || w > 256 * kSpmmCols) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(csr_spmm_rm_kernel, dim3(K), dim3(256), 0, s, K, rp, col, val, w, X, kmax, Y);
+    if (w < 1 || K < 1) return hipErrorInvalidValue;
+    const long long nb = (long long)K * ((w + kSpmmChunk - 1) / kSpmmChunk);
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(csr_spmm_rm_kernel, dim3((unsigned)nb), dim3(kSpmmChunk), 0, s, K, rp, col, val, w, X, kmax,
+                       Y);
     return hipGetLastError();
 }
 
-hipError_t store_panel(int K, int Kp, int w, int col0, const double* C, double ebar, double inv_de, int precision,
-                       void* H, hipStream_t s) {
+hipError_t rg4_spmm_rm(int K, const long long* gp, const int* gc, const double* gv, int w, const double* X, int kmax,
+                       double* Y, hipStream_t s) {
+    if (w < 1 || K < 1) return hipErrorInvalidValue;
+    const int ng = (K + 3) / 4;
+    const long long nb = (long long)ng * ((w + kSpmmChunk - 1) / kSpmmChunk);
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rg4_spmm_rm_kernel, dim3((unsigned)nb), dim3(kSpmmChunk), 0, s, K, ng, gp, gc, gv, w, X, kmax,
+                       Y);
+    return hipGetLastError();
+}
+
+hipError_t store_panel(int K, int Kp, int w, int col0, int row0, const double* C, double ebar, double inv_de,
+                       int precision, void* H, hipStream_t s) {
     const dim3 g = grid_1d((long long)Kp * w, 256);
     if (precision == 0)
-        hipLaunchKernelGGL(store_panel_kernel<double>, g, dim3(256), 0, s, K, Kp, w, col0, C, ebar, inv_de,
+        hipLaunchKernelGGL(store_panel_kernel<double>, g, dim3(256), 0, s, K, Kp, w, col0, row0, C, ebar, inv_de,
                            static_cast<double*>(H));
     else
-        hipLaunchKernelGGL(store_panel_kernel<float>, g, dim3(256), 0, s, K, Kp, w, col0, C, ebar, inv_de,
+        hipLaunchKernelGGL(store_panel_kernel<float>, g, dim3(256), 0, s, K, Kp, w, col0, row0, C, ebar, inv_de,
                            static_cast<float*>(H));
+    return hipGetLastError();
+}
+
+hipError_t mirror_lower(int Kp, int precision, void* H, hipStream_t s) {
+    if (Kp % 32 || Kp / 32 > 65535) return hipErrorInvalidValue;
+    const dim3 g(Kp / 32, Kp / 32);
+    if (precision == 0)
+        hipLaunchKernelGGL(mirror_lower_kernel<double>, g, dim3(256), 0, s, Kp, static_cast<double*>(H));
+    else
+        hipLaunchKernelGGL(mirror_lower_kernel<float>, g, dim3(256), 0, s, Kp, static_cast<float*>(H));
     return hipGetLastError();
 }
 
