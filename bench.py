@@ -15,8 +15,9 @@ first warm-up step solves it from a pass at mu = 0) and checks the electron
 count of its own moments.
 
 Besides the headline line's own roofline (the FP64 recursion kernel), the
-JSON carries two more measured points: hbm_point (the FP32 recursion of the
-K = 32768 cluster against a 32-column block, HBM-bound) and factored_point
+JSON carries more measured points: hbm_point (the FP32 recursion of the
+K = 32768 cluster against a 32-column block, HBM-bound), hbm_point_refined
+(the same pass with FP32 storage and FP64 sums) and factored_point
 (the paper's factored application of S^-1 F on the benchmark cluster: a
 sparse product with F and a preconditioned CG solve with S per step, with
 the roofline of its S products).
@@ -132,11 +133,13 @@ def cpu_baseline(cluster, order, beta, n_e, budget_s=30.0):
     return out
 
 
-def hbm_point(stream):
+def hbm_point(stream, refined=False):
     """The memory-bound point of the recursion: the FP32 operator of the
     K = 32768 workload streamed against a 32-column block (arithmetic
     intensity 16 flop/B, below the FP32 ridge of 19.7), timed live with HIP
-    events on the library's stream."""
+    events on the library's stream.  refined: the same pass in the refined
+    precision (FP32 storage, FP64 MFMA sums: 16 flop per FP32 byte against
+    the FP64 ridge of 9.8, so bound by the f64 matrix cores)."""
     import numpy as np
     import torch
 
@@ -147,7 +150,8 @@ def hbm_point(stream):
     print(f"[bench] building inputs {HBM_WORKLOAD}", file=sys.stderr, flush=True)
     c = workload(HBM_WORKLOAD)
     K = c.K
-    ctx = dmlib.Context(device=0, stream=stream.cuda_stream, precision=dmlib.DM_FP32)
+    prec = dmlib.DM_FP32_ACC64 if refined else dmlib.DM_FP32
+    ctx = dmlib.Context(device=0, stream=stream.cuda_stream, precision=prec)
     ctx.set_cluster(c)
     cols = torch.arange(HBM_COLUMNS, dtype=torch.int64, device="cuda:0")
     ctx.dm_chebyshev_block(cols, 20, 0.0, w["beta"], None)  # warm-up pass
@@ -165,6 +169,13 @@ def hbm_point(stream):
     alg_bytes = 4.0 * K * K + K * HBM_COLUMNS * (3 * 4 + 8 + 16)
     flops = 2.0 * K * K * HBM_COLUMNS
     gbs = alg_bytes / (launch_ms * 1e-3) / 1e9
+    if refined:
+        tf = flops / (launch_ms * 1e-3) / 1e12
+        return {"workload": HBM_WORKLOAD, "K": K, "columns": HBM_COLUMNS, "steps_timed": HBM_ORDER,
+                "precision": "fp32 storage, fp64 sums", "bound": "mfma", "kernel": "cheb_step_kernel<W32,2,2,4,1,8,8,true>",
+                "launch_ms": launch_ms, "algorithmic_bytes": alg_bytes, "achieved": tf, "unit": "TFLOP/s",
+                "peak": PEAK_FP64_TFLOPS, "frac": tf / PEAK_FP64_TFLOPS, "algorithmic_GBps": gbs,
+                "hbm_frac": gbs / PEAK_HBM_GBS, "traffic": None}
     traffic = None
     if kernel_source_hash() == COUNTERS_HBM["kernel_source_sha256_16"]:
         traffic = 1024.0 * (COUNTERS_HBM["fetch_kib"] * COUNTERS_HBM["fetch_scale"]
@@ -383,6 +394,7 @@ def main():
     ctx.close()
     if not args.no_hbm_point:
         out["hbm_point"] = hbm_point(stream)
+        out["hbm_point_refined"] = hbm_point(stream, refined=True)
     if not args.no_factored_point:
         out["factored_point"] = factored_point(stream, state["mu"])
     if not args.no_cpu_baseline:

@@ -808,18 +808,22 @@ dm_status sym_panels(dm_ctx* c, Op& op, double ebar, double de, int precision, v
             log("panel columns %d of %d", j0, Kp);
             if (e != hipSuccess) break;
         }
-        const int kmax = j0 + w;
-        e = transpose_rect(kmax, w, op.Xs.p + (long)j0 * ld, ld, pa.p, w, s);
+        // the last panel is narrower when Kp is not a multiple of w (Kp and
+        // w are multiples of 256, so wj is too)
+        const int wj = std::min(w, Kp - j0);
+        const int kmax = j0 + wj;
+        e = transpose_rect(kmax, wj, op.Xs.p + (long)j0 * ld, ld, pa.p, wj, s);
         if (e == hipSuccess)
-            e = rg4_spmm_rm((int)op.K, op.Fg_ptr.p, op.Fg_col.p, op.Fg_val.p, w, pa.p, kmax, pb.p, s);
-        if (e == hipSuccess && Kp > op.K) e = fill_f64(pb.p + (size_t)op.K * w, 0.0, (long long)(Kp - op.K) * w, s);
-        if (e == hipSuccess) e = transpose_rect(w, Kp, pb.p, w, pa.p, Kp, s);
+            e = rg4_spmm_rm((int)op.K, op.Fg_ptr.p, op.Fg_col.p, op.Fg_val.p, wj, pa.p, kmax, pb.p, s);
+        if (e == hipSuccess && Kp > op.K)
+            e = fill_f64(pb.p + (size_t)op.K * wj, 0.0, (long long)(Kp - op.K) * wj, s);
+        if (e == hipSuccess) e = transpose_rect(wj, Kp, pb.p, wj, pa.p, Kp, s);
         // rows j0 .. Kp of the panel only (H~ is symmetric; the rows above
         // come from earlier panels' columns, mirrored below)
         if (e == hipSuccess)
-            e = gemm_tn_f64(Kp - j0, w, Kp, 1.0, op.Xs.p + (long)j0 * ld, ld, pa.p, Kp, 0.0, pb.p + j0, Kp, false, s,
-                            j0);
-        if (e == hipSuccess) e = store_panel((int)op.K, Kp, w, j0, j0, pb.p, ebar, 1.0 / de, precision, dst, s);
+            e = gemm_tn_f64(Kp - j0, wj, Kp, 1.0, op.Xs.p + (long)j0 * ld, ld, pa.p, Kp, 0.0, pb.p + j0, Kp, false,
+                            s, j0);
+        if (e == hipSuccess) e = store_panel((int)op.K, Kp, wj, j0, j0, pb.p, ebar, 1.0 / de, precision, dst, s);
     }
     if (e == hipSuccess) e = mirror_lower(Kp, precision, dst, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

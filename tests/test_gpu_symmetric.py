@@ -122,3 +122,34 @@ def test_symmetric_stochastic_moments(c1):
     ref = O.stochastic_moments_symmetric(sp, xi, 48, emin, emax)
     say(f"case: symmetric stochastic moments: max|dm~| = {np.abs(got - ref).max():.2e}")
     assert np.abs(got - ref).max() < 1e-9 * max(1.0, np.abs(ref).max())
+
+
+def test_symmetric_setup_with_a_narrow_last_panel():
+    """K = 1280: H~ = X^T F X is formed in column panels of 1024, so the
+    last panel is 256 wide; the operator against dense algebra and P
+    against the oracle on sampled columns."""
+    c = make_cluster(320, seed=8, geometry="sphere", onsite="scaled")
+    sp = O.spectrum(c)
+    w = sp.e[-1] - sp.e[0]
+    emin, emax = sp.e[0] - 0.01 * w, sp.e[-1] + 0.01 * w
+    say(f"case: symmetric form K={c.K} (panels 1024 + 256)")
+    ctx = sym_ctx(c, dmlib.DM_FP64, (emin, emax))
+    Hs = ctx.dm_get_operator(dmlib.DM_OP_HSYM)
+    U = scipy.linalg.cholesky(c.S_dense(), lower=False)
+    L = np.linalg.inv(U).T
+    ref = L @ c.F_dense() @ L.T
+    e1 = np.abs(Hs - ref).max() / np.abs(ref).max()
+    cols = np.random.default_rng(5).permutation(c.K)[:48].astype(np.int64)
+    mu, N, beta = 0.5 * (sp.e[c.K // 4 - 1] + sp.e[c.K // 4]), 300, 20.0
+    P = np.zeros((len(cols), c.K))
+    ctx.dm_chebyshev_block(cols, N, mu, beta, P)
+    err = np.abs(P.T - O.density_matrix_poly(sp, cols, N, mu, beta, emin, emax)).max()
+    say(f"  H~ rel err {e1:.2e}; 48 columns N={N}: max|dP| = {err:.3e}")
+    assert e1 < 1e-10 and err <= TOL_FP64
+    # FP32 storage, Lanczos interval from the stored H~
+    f32 = dmlib.Context(precision=dmlib.DM_FP32)
+    f32.dm_set_operator_form(dmlib.DM_FORM_SYMMETRIC)
+    f32.set_cluster(c)
+    a, b = f32.dm_get_bounds()
+    say(f"  FP32 Lanczos interval [{a:.4f}, {b:.4f}], exact [{sp.e[0]:.4f}, {sp.e[-1]:.4f}]")
+    assert a <= sp.e[0] and b >= sp.e[-1]
