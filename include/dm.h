@@ -262,6 +262,25 @@ dm_status dm_chebyshev_block(dm_ctx* ctx, const long long* cols, long long ncols
 dm_status dm_chebyshev_block_noalloc(dm_ctx* ctx, const long long* cols, long long ncols, int order,
                                      double mu, double beta, double* P_out, double* m_out);
 
+/* Blocks of one multi-set pass combined at another chemical potential: the
+ * expansion coefficients a_l(T, mu) are smooth in mu (supplement "Chebyshev
+ * expansion") while the recursion vectors do not depend on it, so blocks
+ * P_q accumulated by dm_chebyshev_block_multi at nodes mu_q (same order and
+ * beta) give P at mu as P_out = sum_q w_q P_q, w_q the Lagrange weights of
+ * the nodes at mu.  *bound (host, may be NULL) receives
+ * sum_{l<order} |a_l(mu) - sum_q w_q a_l(mu_q)|, the largest error of the
+ * combined polynomial against p_N(.; mu, beta) on the loaded operator's
+ * interval (in the symmetric form P's error is at most bound x
+ * max_a (S^-1)_aa).  Used with a predicted mu: one pass with nodes around
+ * the prediction, mu from the pass's exact moments, then this call instead
+ * of a second pass.  P_in: host array of n_sets pointers (host or device,
+ * n FP64 each); P_out: host or device, n FP64; with n = 0 only *bound is
+ * computed and P_in, P_out may be NULL (to choose nodes before a pass).
+ * Errors: DM_E_STATE (no operator loaded), DM_E_ARG (n_sets outside
+ * [1, DM_MAX_SETS], repeated or non-finite nodes, order < 2, beta <= 0). */
+dm_status dm_combine_sets(dm_ctx* ctx, int n_sets, const double* mus, double beta, int order, double mu,
+                          long long n, const double* const* P_in, double* P_out, double* bound);
+
 /* From the accumulated moments (exact once every column 0..K-1 has been
  * processed once): tr_PS = Tr[P_N S] = sum_l a_l m_l (eq. Ne without the spin
  * factor) and e_band = g Tr[P_N F] = g sum_l a_l (Ebar m_l + dE (m_{l+1} +

@@ -38,7 +38,7 @@ EXPORTED = ["dm_default_options", "dm_init", "dm_destroy", "dm_last_error", "dm_
             "dm_dos", "dm_set_operator_form", "dm_set_fock_orthonormal", "dm_density_on_grid",
             "dm_set_factored_options", "dm_solve_overlap", "dm_get_preconditioner", "dm_cg_stats",
             "dm_cg_timing", "dm_cheb_order_rule", "dm_mlp_encode_targets",
-            "dm_set_moments_precision", "dm_chebyshev_block_noalloc"]
+            "dm_set_moments_precision", "dm_combine_sets", "dm_chebyshev_block_noalloc"]
 
 
 class DMError(RuntimeError):
@@ -146,6 +146,7 @@ def load(path: str = LIB_PATH):
         "dm_mlp_predict": (_I, [_P, _P, _I, _D, _D, _I, _P, _P]),
         "dm_cheb_order_rule": (_I, [_D, _D, _D, _I, _I, _P]),
         "dm_set_moments_precision": (_I, [_P, _I]),
+        "dm_combine_sets": (_I, [_P, _I, _P, _D, _I, _D, _LL, _P, _P, _P]),
         "dm_mlp_encode_targets": (_I, [_D, _D, _D, _I, _P]),
     }
     for name, (res, args) in sig.items():
@@ -304,6 +305,23 @@ class Context:
             np.copyto(P_out, kp.reshape(np.shape(P_out)))
         if m_out is not None and km is not m_out and not hasattr(m_out, "data_ptr"):
             np.copyto(m_out, km.reshape(np.shape(m_out)))
+
+    def dm_combine_sets(self, mus, beta, order, mu, P_ins, P_out):
+        """P_out = sum_q w_q(mu) P_ins[q] (Lagrange weights of the nodes mus);
+        returns the coefficient-space error bound.  P_out None: the bound only."""
+        m = np.ascontiguousarray(mus, dtype=np.float64)
+        if P_out is not None and len(P_ins) != len(m):
+            raise ValueError("one block per node")
+        keep = [_ptr(p, np.float64) for p in P_ins] if P_out is not None else []
+        arr = (ctypes.c_void_p * max(len(keep), 1))(*[k[0].value for k in keep])
+        op, ok = _ptr(P_out, np.float64)
+        n = _numel(P_out) if P_out is not None else 0
+        bound = ctypes.c_double()
+        self._check(self._lib.dm_combine_sets(self.h, len(m), ctypes.c_void_p(m.ctypes.data), float(beta), int(order),
+                                              float(mu), n, arr if keep else None, op, ctypes.byref(bound)))
+        if P_out is not None and ok is not P_out and not hasattr(P_out, "data_ptr"):
+            np.copyto(P_out, ok.reshape(np.shape(P_out)))
+        return bound.value
 
     def dm_chebyshev_block_multi(self, cols, order, mus, betas, P_outs=None):
         """One pass accumulating len(mus) density-matrix blocks; P_outs: None or

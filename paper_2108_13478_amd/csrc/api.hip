@@ -38,6 +38,17 @@ struct DevBuf {
 
 long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
 
+// True for device memory (hipMalloc'ed, e.g. a torch tensor on the GPU);
+// host memory, registered or not, is false.
+bool is_device_ptr(const void* p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
 // Progress of long operator setups on stderr when the environment variable
 // DM_LOG is set (minutes at K ~ 10^5): phase, elapsed seconds.
 struct SetupLog {
@@ -1753,6 +1764,73 @@ dm_status dm_chebyshev_block_noalloc(dm_ctx* c, const long long* cols, long long
     HIPTRY(c, hipStreamSynchronize(s));
     if (hflag & 1)
         return set_err(c, DM_E_BOUNDS, "Chebyshev recursion diverged: the spectral interval does not enclose the spectrum");
+    return DM_OK;
+} catch (...) {
+    return host_exception(c);
+}
+
+dm_status dm_combine_sets(dm_ctx* c, int n_sets, const double* mus, double beta, int order, double mu, long long n,
+                          const double* const* P_in, double* P_out, double* bound) try {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (!c->have_fock) return set_err(c, DM_E_STATE, "no Fock matrix loaded (its interval sets the coefficients)");
+    if (n_sets < 1 || n_sets > DM_MAX_SETS || !mus || order < 2 || order > (1 << 20) || !(beta > 0) ||
+        !std::isfinite(beta) || !std::isfinite(mu) || n < 0 || (n > 0 && (!P_in || !P_out)))
+        return set_err(c, DM_E_ARG, "bad set-combination arguments");
+    for (int q = 0; q < n_sets; ++q) {
+        if (!std::isfinite(mus[q])) return set_err(c, DM_E_ARG, "non-finite node");
+        for (int r = 0; r < q; ++r)
+            if (mus[r] == mus[q]) return set_err(c, DM_E_ARG, "repeated node");
+    }
+    // Lagrange weights of the nodes at mu
+    CombineSets cs{};
+    for (int q = 0; q < n_sets; ++q) {
+        double wq = 1.0;
+        for (int r = 0; r < n_sets; ++r)
+            if (r != q) wq *= (mu - mus[r]) / (mus[q] - mus[r]);
+        cs.w[q] = wq;
+    }
+    hipStream_t s = c->stream;
+    const double ebar = 0.5 * (c->op.emax + c->op.emin), de = 0.5 * (c->op.emax - c->op.emin);
+    const int M = 4 * order, stride = order + 1;
+    DevBuf<double> A, fk, out;
+    hipError_t e = ensure(A, (size_t)stride * (n_sets + 1));
+    if (e == hipSuccess) e = ensure(fk, (size_t)M);
+    if (e == hipSuccess) e = ensure(out, 1);
+    for (int q = 0; q <= n_sets && e == hipSuccess; ++q)
+        e = cheb_coefficients(order, M, ebar, de, q < n_sets ? mus[q] : mu, beta, fk.p, A.p + (size_t)q * stride, s);
+    if (e == hipSuccess) e = interp_bound(order, n_sets, A.p, stride, cs, out.p, s);
+    double hb = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, out.p, 8, hipMemcpyDeviceToHost, s);
+    // blocks in host memory go through device copies
+    DevBuf<double> stage;
+    if (e == hipSuccess && n > 0) {
+        int nhost = 0;
+        for (int q = 0; q < n_sets; ++q) nhost += !is_device_ptr(P_in[q]);
+        const bool out_dev = is_device_ptr(P_out);
+        e = ensure(stage, (size_t)n * (nhost + (out_dev ? 0 : 1)));
+        int k = 0;
+        for (int q = 0; q < n_sets && e == hipSuccess; ++q) {
+            if (is_device_ptr(P_in[q])) {
+                cs.p[q] = P_in[q];
+            } else {
+                double* d = stage.p + (size_t)n * k++;
+                e = hipMemcpyAsync(d, P_in[q], (size_t)n * 8, hipMemcpyHostToDevice, s);
+                cs.p[q] = d;
+            }
+        }
+        double* dst = out_dev ? P_out : stage.p + (size_t)n * k;
+        if (e == hipSuccess) e = combine_sets(n, n_sets, cs, dst, s);
+        if (e == hipSuccess && !out_dev) e = hipMemcpyAsync(P_out, dst, (size_t)n * 8, hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    A.release();
+    fk.release();
+    out.release();
+    stage.release();
+    if (e != hipSuccess) return fail_hip(c, e, "set combination");
+    if (bound) *bound = hb;
     return DM_OK;
 } catch (...) {
     return host_exception(c);

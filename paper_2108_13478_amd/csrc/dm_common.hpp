@@ -230,6 +230,18 @@ hipError_t permute_rows(int K, long long ncols, const int* perm, const double* s
 // holds K ints, zero on entry
 hipError_t check_columns(const long long* cols, long long ncols, long long K, int* seen, int* flag,
                          hipStream_t s);
+// Weights and (device) blocks of a combination of coefficient sets.
+constexpr int kMaxCombine = 16;
+struct CombineSets {
+    const double* p[kMaxCombine];
+    double w[kMaxCombine];
+};
+// out[i] = sum_q w_q p_q[i], i < n
+hipError_t combine_sets(long long n, int nsets, const CombineSets& cs, double* out, hipStream_t s);
+// out[0] = sum_{l < N} |A_nsets[l] - sum_q w_q A_q[l]| (A: nsets + 1 rows of
+// `stride` coefficients)
+hipError_t interp_bound(int N, int nsets, const double* A, int stride, const CombineSets& cs, double* out,
+                        hipStream_t s);
 // flag[0] |= 1 when some |x_i| > lim or x_i is not finite
 hipError_t flag_large(const double* x, long long n, double lim, int* flag, hipStream_t s);
 // --- symmetric form built in place (symform.hip)

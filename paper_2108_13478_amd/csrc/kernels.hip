@@ -54,6 +54,31 @@ __global__ void check_columns_kernel(const long long* __restrict__ cols, long lo
     }
 }
 
+// out[i] = sum_q w_q P_q[i] (the blocks of one multi-set pass combined)
+__global__ void combine_sets_kernel(long long n, int nsets, CombineSets cs, double* __restrict__ out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int q = 0; q < nsets; ++q) acc += cs.w[q] * cs.p[q][i];
+        out[i] = acc;
+    }
+}
+
+// out[0] = sum_{l <= N - 1} |a_l - sum_q w_q A_q[l]|, a = A_nsets (one
+// workgroup, fixed order)
+__global__ void __launch_bounds__(256) interp_bound_kernel(int N, int nsets, const double* __restrict__ A, int stride,
+                                                           CombineSets cs, double* out) {
+    double s = 0.0;
+    for (int l = threadIdx.x; l < N; l += 256) {
+        double v = A[(long)nsets * stride + l];
+        for (int q = 0; q < nsets; ++q) v -= cs.w[q] * A[(long)q * stride + l];
+        s += fabs(v);
+    }
+    __shared__ double red[4];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
 // flag[0] |= 1 when some |x_i| exceeds lim or is not finite
 __global__ void flag_large_kernel(const double* __restrict__ x, long long n, double lim, int* flag) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -586,6 +611,20 @@ hipError_t check_columns(const long long* cols, long long ncols, long long K, in
                          hipStream_t s) {
     if (ncols <= 0) return hipSuccess;
     hipLaunchKernelGGL(check_columns_kernel, grid_for(ncols, 256), dim3(256), 0, s, cols, ncols, K, seen, flag);
+    return hipGetLastError();
+}
+
+hipError_t combine_sets(long long n, int nsets, const CombineSets& cs, double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (nsets < 1 || nsets > kMaxCombine) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(combine_sets_kernel, grid_for(n, 256), dim3(256), 0, s, n, nsets, cs, out);
+    return hipGetLastError();
+}
+
+hipError_t interp_bound(int N, int nsets, const double* A, int stride, const CombineSets& cs, double* out,
+                        hipStream_t s) {
+    if (nsets < 1 || nsets > kMaxCombine) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(interp_bound_kernel, dim3(1), dim3(256), 0, s, N, nsets, A, stride, cs, out);
     return hipGetLastError();
 }
 
