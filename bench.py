@@ -42,8 +42,10 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE averages per recursion launch of this
 # workload (KiB), and the scale factors from a plain 1 GiB copy (FETCH_SIZE
 # counts half of the bytes a copy reads on this part, WRITE_SIZE all of them).
-# Valid only for the kernel source they were taken with.
-COUNTERS = {"kernel_source_sha256_16": "b20b5ef62b97a939", "fetch_kib": 1000503.5,
+# Valid only for the recursion-step code they were taken with: the text of
+# gemm.hip before the persistent-batch section (GEMM_STEP_END).
+GEMM_STEP_END = b"// ------------------------------------------------------------ persistent batch"
+COUNTERS = {"kernel_source_sha256_16": "6cb75a077bfe8e07", "fetch_kib": 998038.2,
             "write_kib": 262022.3, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -51,7 +53,7 @@ HBM_WORKLOAD = "K32768_sphere8192_fp32"
 HBM_COLUMNS = 32
 HBM_ORDER = 200
 # the same counters for the recursion launch of the HBM point (FP32, 32 columns)
-COUNTERS_HBM = {"kernel_source_sha256_16": "b20b5ef62b97a939", "fetch_kib": 2124170.1, "write_kib": 12279.9,
+COUNTERS_HBM = {"kernel_source_sha256_16": "6cb75a077bfe8e07", "fetch_kib": 2124299.0, "write_kib": 12295.0,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -69,6 +71,8 @@ COUNTERS_FACT = {"kernel_source_sha256_16": "418518f5b6973c24", "fetch_kib": 319
 
 # the device-code part of factored.hip ends at this line (host code follows)
 FACT_DEVICE_END = b"// --------------------------------------------------------------- host side"
+# the part of each source that a counter or profile is valid for ends here
+SOURCE_MARKERS = {"factored.hip": FACT_DEVICE_END, "gemm.hip": GEMM_STEP_END}
 
 
 def kernel_source_hash(name="gemm.hip", upto=None):
@@ -177,7 +181,7 @@ def hbm_point(stream, refined=False):
                 "peak": PEAK_FP64_TFLOPS, "frac": tf / PEAK_FP64_TFLOPS, "algorithmic_GBps": gbs,
                 "hbm_frac": gbs / PEAK_HBM_GBS, "traffic": None}
     traffic = None
-    if kernel_source_hash() == COUNTERS_HBM["kernel_source_sha256_16"]:
+    if kernel_source_hash("gemm.hip", GEMM_STEP_END) == COUNTERS_HBM["kernel_source_sha256_16"]:
         traffic = 1024.0 * (COUNTERS_HBM["fetch_kib"] * COUNTERS_HBM["fetch_scale"]
                             + COUNTERS_HBM["write_kib"] * COUNTERS_HBM["write_scale"])
     return {"workload": HBM_WORKLOAD, "K": K, "columns": HBM_COLUMNS, "steps_timed": HBM_ORDER,
@@ -358,7 +362,7 @@ def main():
     flops = 2.0 * K * K * K
     achieved = flops / (launch_ms * 1e-3) / 1e12
     traffic = None
-    if kernel_source_hash() == COUNTERS["kernel_source_sha256_16"]:
+    if kernel_source_hash("gemm.hip", GEMM_STEP_END) == COUNTERS["kernel_source_sha256_16"]:
         traffic = 1024.0 * (COUNTERS["fetch_kib"] * COUNTERS["fetch_scale"]
                             + COUNTERS["write_kib"] * COUNTERS["write_scale"])
     # algorithmic bytes per launch: operator K^2, reads of U_l, U_{l-1}, Z, P and

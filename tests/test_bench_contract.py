@@ -26,8 +26,8 @@ def test_more_than_one_gpu_is_refused():
 def test_counters_match_current_kernel_sources():
     # bench.py reports traffic only while these hold; a kernel change must
     # come with counters taken again
-    assert bench.kernel_source_hash("gemm.hip") == bench.COUNTERS["kernel_source_sha256_16"]
-    assert bench.kernel_source_hash("gemm.hip") == bench.COUNTERS_HBM["kernel_source_sha256_16"]
+    assert bench.kernel_source_hash("gemm.hip", bench.GEMM_STEP_END) == bench.COUNTERS["kernel_source_sha256_16"]
+    assert bench.kernel_source_hash("gemm.hip", bench.GEMM_STEP_END) == bench.COUNTERS_HBM["kernel_source_sha256_16"]
     assert (bench.kernel_source_hash("factored.hip", bench.FACT_DEVICE_END)
             == bench.COUNTERS_FACT["kernel_source_sha256_16"])
 
@@ -48,11 +48,11 @@ def test_profiles_name_their_source_and_a_committed_command():
                 if arg.endswith(".py") or arg.startswith("tests/"):
                     assert os.path.exists(os.path.join(ROOT, arg.split("::")[0])), f"{name}: {arg}"
         # a stated kernel-source hash is that of the source as committed (the
-        # device part, before the host-side marker, where the profile says so)
-        for m in re.finditer(r"(Device code[^`]*)?sha256\[:16\] of\s+`([^`]+)`:\s+`([0-9a-f]{16})`", text):
+        # part before the file's marker, where the profile says "(text before")
+        for m in re.finditer(r"(\(text before[^`]*)?sha256\[:16\] of\s+`([^`]+)`:\s+`([0-9a-f]{16})`", text):
             data = open(os.path.join(ROOT, m.group(2)), "rb").read()
             if m.group(1):
-                data = data[:data.index(bench.FACT_DEVICE_END)]
+                data = data[:data.index(bench.SOURCE_MARKERS[os.path.basename(m.group(2))])]
             assert hashlib.sha256(data).hexdigest()[:16] == m.group(3), f"{name}: {m.group(2)} changed"
         if name.startswith("density_kernel"):
             assert "csrc/grid.hip`: `" in text, f"{name}: grid.hip hash not stated"
