@@ -440,9 +440,12 @@ dm_status dm_batch_stoch_moments(dm_ctx* ctx, int n_mom, int n_vec, const double
 dm_status dm_set_moments_precision(dm_ctx* ctx, int precision);
 
 /* Full density matrices of every cluster: first a moments-only pass over all
- * columns of all clusters (one persistent launch: workgroups take
- * (cluster, column block) items longest first and run all order steps of
- * their block), then per cluster mu_c by bisection with g Tr[P_c S_c] =
+ * columns of all clusters (one persistent launch of exactly the resident
+ * workgroups, in gangs of four: a gang runs all order steps of one
+ * (cluster, column block) item of a large cluster with its members
+ * splitting the row tiles and meeting after each step, or four items of
+ * small clusters side by side; items dealt to gangs longest first), then
+ * per cluster mu_c by bisection with g Tr[P_c S_c] =
  * n_e[c] (tolerance tol) from those moments, the coefficients at mu_c, and a
  * second persistent launch that accumulates P_c.  The whole sequence is
  * captured once in a hipGraph and replayed while (order, beta, n_e, tol,
@@ -450,8 +453,10 @@ dm_status dm_set_moments_precision(dm_ctx* ctx, int precision);
  * without the graph.  n_e: host, n values.  mu_out: host, n values or NULL.
  * P_out: NULL or host array of n pointers (each host or device memory, K_c x
  * K_c column-major FP64, or NULL to skip that cluster).
- * Errors: DM_E_STATE (no batch), DM_E_ARG, DM_E_BOUNDS, DM_E_NOCONV (a
- * bisection stopped at rounding level before tol; mu_out still filled). */
+ * Errors: DM_E_STATE (no batch; or a gang member was not resident, so a
+ * step barrier gave up and the results are void), DM_E_ARG, DM_E_BOUNDS,
+ * DM_E_NOCONV (a bisection stopped at rounding level before tol; mu_out
+ * still filled). */
 dm_status dm_batch_run(dm_ctx* ctx, int order, double beta, const double* n_e, double tol,
                        double* mu_out, double* const* P_out, int flags);
 

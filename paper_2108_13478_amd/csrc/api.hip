@@ -212,12 +212,23 @@ struct BatchClusterBufs {
     int Bp = 0;
 };
 
+// Rounds of one batch launch (see BatchRound) and the gang layout they were
+// dealt to.
+struct BatchTable {
+    DevBuf<BatchRound> rounds;
+    DevBuf<int> gang_start;
+    int grid = 0, gmap = 1, ngangs = 0;
+    void release() {
+        rounds.release();
+        gang_start.release();
+    }
+};
+
 struct BatchState {
     std::vector<BatchClusterBufs> cl;
     DevBuf<BatchCluster> d_clusters;
-    DevBuf<BatchItem> d_items;
-    DevBuf<int> counter;
-    int n_items = 0;
+    BatchTable tab;
+    DevBuf<int> counter;  // barrier counters: one per gang and pass
     int cfg = 0;
     int table_cfg = -1, table_order = -1, table_prec = -1;
     // moments pass in FP64 under an FP32 recursion: its own tile shape,
@@ -225,8 +236,7 @@ struct BatchState {
     int mom_prec = -1;  // precision of the moments pass (set at load)
     int cfg_m = -1;
     DevBuf<BatchCluster> d_clusters_m;
-    DevBuf<BatchItem> d_items_m;
-    int n_items_m = 0;
+    BatchTable tab_m;
     // captured graph and the parameters it was captured with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -249,9 +259,9 @@ struct BatchState {
                 x->release();
         for (auto& b : cl) b.cols.release();
         d_clusters.release();
-        d_items.release();
+        tab.release();
         d_clusters_m.release();
-        d_items_m.release();
+        tab_m.release();
         counter.release();
     }
 };
@@ -2510,15 +2520,41 @@ int batch_mom_cfg(int cfg) {
     return first;
 }
 
-// Cluster table and longest-first item list of one pass with tile shape
-// cfg, reading H_N from HN64 (FP64 moments pass) or HNbuf.
-dm_status batch_pass_table(dm_ctx* c, int cfg, bool fp64_copy, DevBuf<BatchCluster>& dcl,
-                           DevBuf<BatchItem>& ditems, int& n_items) {
+// Items of at least this many operator rows are shared by a gang (its
+// members split the row tiles and meet after every step); smaller ones run
+// on one workgroup each, kGang of similar size to a round.
+constexpr int kGangSplitRows = 2048;
+
+// Workgroups of the batch kernel for tile shape cfg: every CU filled, in
+// whole gangs; gmap = 8 when the grid deals whole gangs to each of the 8
+// XCDs, else 1 (members then need not share an XCD).
+void batch_launch_shape(dm_ctx* c, int cfg, int precision, BatchTable& t) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->opt.device) != hipSuccess || cus < 1)
+        cus = 256;
+    const int resident = cus * std::max(1, cheb_batch_occupancy(cfg, precision));
+    if (resident >= 8 * kGang) {
+        t.gmap = 8;
+        t.ngangs = resident / (8 * kGang) * 8;
+    } else {
+        t.gmap = 1;
+        t.ngangs = std::max(1, resident / kGang);
+    }
+    t.grid = t.ngangs * kGang;
+}
+
+// Cluster table and the gangs' round lists of one pass with tile shape cfg,
+// reading H_N from HN64 (FP64 moments pass) or HNbuf.  Rounds are dealt
+// longest first to the gang with the least work so far (work of a round:
+// Kp^2 x its columns, divided among the members of a shared item).
+dm_status batch_pass_table(dm_ctx* c, int cfg, bool fp64_copy, int precision, DevBuf<BatchCluster>& dcl,
+                           BatchTable& tab) {
     BatchState& bs = *c->bstate;
     const int BN = cheb_tile_cols(cfg);
     const int n = (int)c->batch.size();
     std::vector<BatchCluster> hcl(n);
-    std::vector<std::pair<long long, BatchItem>> items;
+    std::vector<std::pair<double, BatchRound>> rounds;
+    std::vector<std::pair<int, BatchItem>> solo;  // (Kp, item)
     for (int i = 0; i < n; ++i) {
         const Op& op = c->batch[i];
         BatchClusterBufs& b = bs.cl[i];
@@ -2533,22 +2569,60 @@ dm_status batch_pass_table(dm_ctx* c, int cfg, bool fp64_copy, DevBuf<BatchClust
         h.Z = b.Z.p;
         h.coef = b.coef.p;
         h.partial = b.partial.p;
-        for (int blk = 0; blk < h.nblocks; ++blk)
-            items.push_back({(long long)op.Kp * op.Kp, BatchItem{i, blk}});
+        for (int blk = 0; blk < h.nblocks; ++blk) {
+            if (op.Kp >= kGangSplitRows) {
+                BatchRound r{};
+                r.split = 1;
+                r.n = 1;
+                r.item[0] = BatchItem{i, blk};
+                rounds.push_back({(double)op.Kp * op.Kp / kGang, r});
+            } else {
+                solo.push_back({op.Kp, BatchItem{i, blk}});
+            }
+        }
     }
-    // longest items first: a workgroup that takes a short item late cannot
-    // hold up the end of the launch by much
-    std::stable_sort(items.begin(), items.end(),
-                     [](const std::pair<long long, BatchItem>& x, const std::pair<long long, BatchItem>& y) {
+    std::stable_sort(solo.begin(), solo.end(),
+                     [](const std::pair<int, BatchItem>& x, const std::pair<int, BatchItem>& y) {
                          return x.first > y.first;
                      });
-    std::vector<BatchItem> hitems(items.size());
-    for (size_t k = 0; k < items.size(); ++k) hitems[k] = items[k].second;
+    for (size_t k = 0; k < solo.size(); k += kGang) {
+        BatchRound r{};
+        r.split = 0;
+        r.n = (int)std::min<size_t>(kGang, solo.size() - k);
+        for (int m = 0; m < r.n; ++m) r.item[m] = solo[k + m].second;
+        rounds.push_back({(double)solo[k].first * solo[k].first, r});
+    }
+    std::stable_sort(rounds.begin(), rounds.end(),
+                     [](const std::pair<double, BatchRound>& x, const std::pair<double, BatchRound>& y) {
+                         return x.first > y.first;
+                     });
+    batch_launch_shape(c, cfg, precision, tab);
+    const int G = tab.ngangs;
+    std::vector<double> load(G, 0.0);
+    std::vector<std::vector<BatchRound>> per(G);
+    for (const auto& r : rounds) {
+        const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[g] += r.first;
+        per[g].push_back(r.second);
+    }
+    // in each gang the shared rounds first: its members then start every
+    // shared round together, and wait at a barrier at most about one row
+    // tile for each other
+    std::vector<BatchRound> hr;
+    std::vector<int> gstart(G + 1, 0);
+    for (int g = 0; g < G; ++g) {
+        gstart[g] = (int)hr.size();
+        std::stable_partition(per[g].begin(), per[g].end(), [](const BatchRound& r) { return r.split != 0; });
+        hr.insert(hr.end(), per[g].begin(), per[g].end());
+    }
+    gstart[G] = (int)hr.size();
     HIPTRY(c, ensure(dcl, (size_t)n));
-    HIPTRY(c, ensure(ditems, hitems.size()));
+    HIPTRY(c, ensure(tab.rounds, std::max<size_t>(hr.size(), 1)));
+    HIPTRY(c, ensure(tab.gang_start, gstart.size()));
     HIPTRY(c, hipMemcpy(dcl.p, hcl.data(), n * sizeof(BatchCluster), hipMemcpyHostToDevice));
-    HIPTRY(c, hipMemcpy(ditems.p, hitems.data(), hitems.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
-    n_items = (int)hitems.size();
+    if (!hr.empty())
+        HIPTRY(c, hipMemcpy(tab.rounds.p, hr.data(), hr.size() * sizeof(BatchRound), hipMemcpyHostToDevice));
+    HIPTRY(c, hipMemcpy(tab.gang_start.p, gstart.data(), gstart.size() * sizeof(int), hipMemcpyHostToDevice));
     return DM_OK;
 }
 
@@ -2578,7 +2652,7 @@ dm_status batch_tables(dm_ctx* c, int cfg, int order) {
         HIPTRY(c, ensure(b.Z, KB));
         HIPTRY(c, ensure(b.P, KB));
         HIPTRY(c, ensure(b.coef, (size_t)order + 1));
-        HIPTRY(c, ensure(b.partial, (size_t)(order + 1) * (b.Bp / 32)));
+        HIPTRY(c, ensure(b.partial, (size_t)(order + 1) * (b.Bp / 32) * kGang));
         HIPTRY(c, ensure(b.pstart, (size_t)(op.Kp / 64) * (b.Bp / 16)));
         HIPTRY(c, ensure(b.mom, (size_t)order + 1));
         HIPTRY(c, ensure(b.w, (size_t)M));
@@ -2586,28 +2660,23 @@ dm_status batch_tables(dm_ctx* c, int cfg, int order) {
         HIPTRY(c, ensure(b.fk, (size_t)M));
         HIPTRY(c, ensure(b.out, 8));
     }
-    dm_status st = batch_pass_table(c, cfg, false, bs.d_clusters, bs.d_items, bs.n_items);
+    dm_status st = batch_pass_table(c, cfg, false, c->precision, bs.d_clusters, bs.tab);
     if (st != DM_OK) return st;
+    int ng = bs.tab.ngangs;
     if (split_mom) {
         bs.cfg_m = batch_mom_cfg(cfg);
         if (bs.cfg_m < 0) return set_err(c, DM_E_STATE, "no FP64 batch tile shape");
-        st = batch_pass_table(c, bs.cfg_m, true, bs.d_clusters_m, bs.d_items_m, bs.n_items_m);
+        st = batch_pass_table(c, bs.cfg_m, true, mprec, bs.d_clusters_m, bs.tab_m);
         if (st != DM_OK) return st;
+        ng = std::max(ng, bs.tab_m.ngangs);
     }
-    HIPTRY(c, ensure(bs.counter, 4));
+    HIPTRY(c, ensure(bs.counter, (size_t)2 * ng));
     bs.table_cfg = cfg;
     bs.table_order = order;
     bs.table_prec = c->precision;
     return DM_OK;
 }
 
-int batch_grid(dm_ctx* c, int cfg, int precision, int n_items) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->opt.device) != hipSuccess || cus < 1)
-        cus = 256;
-    const int occ = std::max(1, cheb_batch_occupancy(cfg, precision));
-    return std::max(1, std::min(n_items, cus * occ));
-}
 
 // Start blocks of every cluster (U_0 = S^-1 columns into U_a in `precision`,
 // Z = S, P = a_0 U_0).
@@ -2643,7 +2712,7 @@ hipError_t batch_start(dm_ctx* c, bool zero_moments, int precision) {
 // grid1, grid2: workgroups of the moments and the P pass (batch_grid),
 // taken before a capture starts.
 hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<double>& ne, double tol,
-                         int grid1, int grid2, bool with_P) {
+                         bool with_P) {
     BatchState& bs = *c->bstate;
     hipStream_t s = c->stream;
     const int n = (int)c->batch.size();
@@ -2657,22 +2726,23 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
         if ((e = (x)) != hipSuccess) return e; \
     } while (0)
     BQ(fill_i32(c->flag.p, 0, 4, s));
-    BQ(fill_i32(bs.counter.p, 0, 4, s));
+    const int ngm = split_mom ? bs.tab_m.ngangs : bs.tab.ngangs;
+    BQ(fill_i32(bs.counter.p, 0, ngm + bs.tab.ngangs, s));
     for (int i = 0; i < n; ++i) BQ(fill_f64(bs.cl[i].coef.p, 0.0, order + 1, s));
     // pass 1: moments of every column (coefficients zero: P is not touched),
     // in FP64 from the FP64 copy of H_N when the batch was loaded so
     const int cfg1 = split_mom ? bs.cfg_m : bs.cfg;
-    const int nit1 = split_mom ? bs.n_items_m : bs.n_items;
+    const BatchTable& t1 = split_mom ? bs.tab_m : bs.tab;
     BQ(batch_start(c, true, mprec));
-    BatchArgs a{split_mom ? bs.d_clusters_m.p : bs.d_clusters.p, split_mom ? bs.d_items_m.p : bs.d_items.p, nit1,
-                bs.counter.p, order, 0};
-    BQ(cheb_batch(a, cfg1, mprec, grid1, s));
+    BatchArgs a{split_mom ? bs.d_clusters_m.p : bs.d_clusters.p, t1.rounds.p, t1.gang_start.p, bs.counter.p,
+                c->flag.p, order, 0, t1.gmap};
+    BQ(cheb_batch(a, cfg1, mprec, t1.grid, s));
     const int BN = cheb_tile_cols(cfg1);
     for (int i = 0; i < n; ++i) {
         const Op& op = c->batch[i];
         BatchClusterBufs& b = bs.cl[i];
         const int nb = b.Bp / BN;
-        BQ(reduce_moments(order - 1, nb, b.partial.p + nb, b.mom.p + 1, c->flag.p, s));
+        BQ(reduce_moments(order - 1, nb * kGang, b.partial.p + (size_t)nb * kGang, b.mom.p + 1, c->flag.p, s));
         const double ebar = 0.5 * (op.emax + op.emin), de = 0.5 * (op.emax - op.emin);
         // mu_c from the exact moments, then the coefficients at mu_c
         BQ(trace_weights(order, M, ebar, de, b.mom.p, b.w.p, b.v.p, s));
@@ -2683,8 +2753,9 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
     if (!with_P) return hipSuccess;
     // pass 2: P at mu_c
     BQ(batch_start(c, false, c->precision));
-    BatchArgs a2{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p + 1, order, 1};
-    BQ(cheb_batch(a2, bs.cfg, c->precision, grid2, s));
+    BatchArgs a2{bs.d_clusters.p, bs.tab.rounds.p, bs.tab.gang_start.p, bs.counter.p + ngm, c->flag.p, order, 1,
+                 bs.tab.gmap};
+    BQ(cheb_batch(a2, bs.cfg, c->precision, bs.tab.grid, s));
     // symmetric form: P = L^T Q into the Z buffer (Z is not read after the pass)
     for (int i = 0; i < n; ++i) {
         const Op& op = c->batch[i];
@@ -2801,13 +2872,10 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
     if (st != DM_OK) return st;
     const int mprec = batch_mom_precision(c);
     const bool split_mom = mprec != c->precision;
-    const int grid1 = split_mom ? batch_grid(c, bs.cfg_m, mprec, bs.n_items_m)
-                                : batch_grid(c, bs.cfg, c->precision, bs.n_items);
-    const int grid2 = batch_grid(c, bs.cfg, c->precision, bs.n_items);
     const bool with_P = !(flags & DM_BATCH_MOMENTS_ONLY);
     hipStream_t s = c->stream;
     if (flags & DM_BATCH_EAGER) {
-        HIPTRY(c, batch_enqueue(c, order, beta, ne, tol, grid1, grid2, with_P));
+        HIPTRY(c, batch_enqueue(c, order, beta, ne, tol, with_P));
     } else {
         const bool same = bs.exec && bs.g_order == order && bs.g_beta == beta && bs.g_tol == tol &&
                           bs.g_prec == c->precision && bs.g_cfg == bs.cfg && bs.g_ne == ne &&
@@ -2815,7 +2883,7 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
         if (!same) {
             bs.drop_graph();
             HIPTRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            const hipError_t e1 = batch_enqueue(c, order, beta, ne, tol, grid1, grid2, with_P);
+            const hipError_t e1 = batch_enqueue(c, order, beta, ne, tol, with_P);
             hipGraph_t g = nullptr;
             const hipError_t e2 = hipStreamEndCapture(s, &g);
             if (e1 != hipSuccess) {
@@ -2853,6 +2921,7 @@ dm_status dm_batch_run(dm_ctx* c, int order, double beta, const double* n_e, dou
         if (mu_out) mu_out[i] = outs[8 * i];
         if (outs[8 * i + 3] == 0.0) conv = false;
     }
+    if (flag & 8) return set_err(c, DM_E_STATE, "a batch workgroup waited too long for its gang (too few resident)");
     if (flag) return set_err(c, DM_E_BOUNDS, "batch recursion diverged");
     if (!conv) return set_err(c, DM_E_NOCONV, "a cluster's mu bisection stopped before the tolerance");
     return DM_OK;
@@ -2892,11 +2961,12 @@ dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, in
         if (st != DM_OK) break;
         for (size_t i = 0; i < c->batch.size(); ++i) HIPTRY(c, fill_f64(bs.cl[i].coef.p, 0.0, steps + 1, s));
         HIPTRY(c, batch_start(c, false, c->precision));
-        HIPTRY(c, fill_i32(bs.counter.p, 0, 4, s));
-        const int grid = batch_grid(c, cfg, c->precision, bs.n_items);
-        BatchArgs a{bs.d_clusters.p, bs.d_items.p, bs.n_items, bs.counter.p, steps, 0};
+        HIPTRY(c, fill_i32(bs.counter.p, 0, bs.tab.ngangs, s));
+        HIPTRY(c, fill_i32(c->flag.p, 0, 4, s));
+        BatchArgs a{bs.d_clusters.p, bs.tab.rounds.p, bs.tab.gang_start.p, bs.counter.p, c->flag.p, steps, 0,
+                    bs.tab.gmap};
         HIPTRY(c, hipEventRecord(e0, s));
-        HIPTRY(c, cheb_batch(a, cfg, c->precision, grid, s));
+        HIPTRY(c, cheb_batch(a, cfg, c->precision, bs.tab.grid, s));
         HIPTRY(c, hipEventRecord(e1, s));
         HIPTRY(c, hipEventSynchronize(e1));
         float ms = 0;

@@ -102,13 +102,26 @@ struct BatchCluster {
 struct BatchItem {
     int cluster, block;
 };
+// Workgroups of the batch kernel form gangs of kGang.  A gang works through
+// its list of rounds; a round is either one item whose row tiles the gang
+// shares (split = 1: member m takes row tiles m, m + kGang, ..., and the
+// gang meets at a barrier after every step), or up to kGang items of which
+// member m takes item m alone.
+constexpr int kGang = 4;
+struct BatchRound {
+    int split;
+    int n;  // items in the round (1 when split)
+    BatchItem item[kGang];
+};
 struct BatchArgs {
     const BatchCluster* clusters;
-    const BatchItem* items;
-    int n_items;
-    int* counter;
+    const BatchRound* rounds;
+    const int* gang_start;  // rounds of gang g: [gang_start[g], gang_start[g + 1])
+    int* bar;               // one barrier counter per gang, zero at launch
+    int* flag;              // |= 8 when a barrier wait ran out of patience
     int order;
     int with_P;
+    int gmap;               // 8: gang g's members share XCD g % 8; 1: gangs of consecutive workgroups
 };
 hipError_t cheb_batch(const BatchArgs& a, int cfg, int precision, int grid, hipStream_t s);
 // Workgroups of tile shape cfg that fit on one CU at once.

@@ -520,22 +520,52 @@ __global__ void __launch_bounds__(256) cheb_combine_kernel(ChebStepArgs a) {
 }
 
 // ------------------------------------------------------------ persistent batch
+// Waits until the gang's barrier counter reaches `target` (every member has
+// arrived); the release / acquire pair at agent scope orders this
+// workgroup's U stores before the other members' loads of them.  Members
+// arrive within about one row tile of each other, so a wait of 2^20 polls
+// means a member is not running: the waiter sets flag bit 8 and goes on, and
+// once that bit is set no barrier waits any more, so the launch drains (the
+// results are then void and the host reports it).
+__device__ inline void gang_barrier(int* bar, int target, int* flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int polls = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > (1 << 20)) {
+                atomicOr(flag, 8);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// With gmap = 8 workgroup b belongs to gang (b / 8 / kGang) * 8 + b % 8 as
+// member (b / 8) % kGang: workgroups are dealt to the 8 XCDs round robin, so
+// a gang's members share one XCD and its L2, where the U panel that all of
+// them read for a shared item stays while they walk their row tiles.  The
+// grid is exactly the resident workgroups, so every member of a gang runs
+// at once.
 template <typename T, int TM, int TN, int WM, int WN, int KV, int DEPTH>
 __global__ void __launch_bounds__(64 * WM * WN)
 cheb_batch_kernel(BatchArgs a) {
     typedef typename Mfma<T>::vec_t vec_t;
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
-    __shared__ int item_s;
     __shared__ double red[WM * WN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lq = lane >> 4;
-    for (;;) {
-        if (threadIdx.x == 0) item_s = atomicAdd(a.counter, 1);
-        __syncthreads();
-        const int it = item_s;
-        __syncthreads();
-        if (it >= a.n_items) break;  // every wave of the workgroup leaves together
-        const BatchItem item = a.items[it];
+    const int slot = blockIdx.x / a.gmap;
+    const int gang = (slot / kGang) * a.gmap + blockIdx.x % a.gmap, member = slot % kGang;
+    int nbar = 0;  // barriers this gang has passed
+    for (int r = a.gang_start[gang]; r < a.gang_start[gang + 1]; ++r) {
+        const BatchRound rd = a.rounds[r];
+        if (!rd.split && member >= rd.n) continue;
+        const BatchItem item = rd.item[rd.split ? 0 : member];
+        const int row_first = rd.split ? member : 0, row_step = rd.split ? kGang : 1;
         const BatchCluster cl = a.clusters[item.cluster];
         const int Kp = cl.Kp;
         const T* HN = static_cast<const T*>(cl.HN);
@@ -549,7 +579,7 @@ cheb_batch_kernel(BatchArgs a) {
             const double c = a.with_P ? cl.coef[l] : 0.0;
             const T alpha = static_cast<T>(l == 1 ? 1.0 : 2.0);
             double msum = 0.0;
-            for (int r0 = 0; r0 < Kp; r0 += BM) {
+            for (int r0 = row_first * BM; r0 < Kp; r0 += row_step * BM) {
                 const int row0 = r0 + (wave % WM) * TM * 16;
                 typename Mfma<T>::acc_t acc[TM][TN];
                 gemm_mainloop<T, TM, TN, KV, DEPTH>(Kp, HN, Kp, ucur, Kp, row0, col0, acc);
@@ -573,15 +603,24 @@ cheb_batch_kernel(BatchArgs a) {
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) msum += __shfl_xor(msum, off, 64);
             if (lane == 0) red[wave] = msum;
-            // also orders this step's U writes before the next step's reads
             __syncthreads();
-            if (threadIdx.x == 0) {
+            if (threadIdx.x < kGang) {
+                // one partial per (step, block, member); a member working
+                // alone writes its sum into slot 0 and zeros elsewhere
                 double s = 0.0;
+                if (threadIdx.x == (rd.split ? member : 0)) {
 #pragma unroll
-                for (int w = 0; w < WM * WN; ++w) s += red[w];
-                cl.partial[(long)l * cl.nblocks + item.block] = s;
+                    for (int w = 0; w < WM * WN; ++w) s += red[w];
+                }
+                if (rd.split ? threadIdx.x == member : true)
+                    cl.partial[((long)l * cl.nblocks + item.block) * kGang + threadIdx.x] = s;
             }
-            __syncthreads();
+            // the barrier (or, alone, the workgroup barrier) also orders this
+            // step's U writes before the next step's reads
+            if (rd.split)
+                gang_barrier(a.bar + gang, kGang * ++nbar, a.flag);
+            else
+                __syncthreads();
         }
     }
 }
