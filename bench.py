@@ -52,6 +52,9 @@ COUNTERS = {"kernel_source_sha256_16": "6cb75a077bfe8e07", "fetch_kib": 998038.2
 HBM_WORKLOAD = "K32768_sphere8192_fp32"
 HBM_COLUMNS = 32
 HBM_ORDER = 200
+# the K = 32768 workload's whole configuration (every column): pass width and
+# tile shape, and the steps timed
+FULL_WIDTH, FULL_CFG, FULL_STEPS = 16384, 27, 4
 # the same counters for the recursion launch of the HBM point (FP32, 32 columns)
 COUNTERS_HBM = {"kernel_source_sha256_16": "6cb75a077bfe8e07", "fetch_kib": 2124299.0, "write_kib": 12295.0,
                 "fetch_scale": 2.0, "write_scale": 1.0}
@@ -167,6 +170,27 @@ def hbm_point(stream, refined=False):
     e1.record(stream)
     torch.cuda.synchronize()
     launch_ms = e0.elapsed_time(e1) / HBM_ORDER
+    full = None
+    if not refined:
+        # the same operator's whole configuration: every column, advanced in
+        # passes of 16384 columns on the 128 x 128 tile (the autotuned choice
+        # at this size); per-step time from two passes that differ by
+        # FULL_STEPS steps, so start and end of a pass cancel
+        allc = torch.arange(K, dtype=torch.int64, device="cuda:0")
+        ctx.dm_set_pass_shape(FULL_WIDTH, FULL_CFG)
+        ms = []
+        for n in (2, 2 + FULL_STEPS):
+            f0 = torch.cuda.Event(enable_timing=True)
+            f1 = torch.cuda.Event(enable_timing=True)
+            f0.record(stream)
+            ctx.dm_chebyshev_block(allc, n, 0.0, w["beta"], None)
+            f1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(f0.elapsed_time(f1))
+        step_ms = (ms[1] - ms[0]) / FULL_STEPS
+        full = {"columns": K, "pass_width": FULL_WIDTH, "tile": "128x128 (8 k per lane, three slabs)",
+                "step_ms": step_ms, "tflops": 2.0 * K ** 3 / (step_ms * 1e-3) / 1e12,
+                "order": w["order"], "columns_per_s_at_order": K / ((w["order"] + 1) * step_ms * 1e-3)}
     ctx.close()
     # per launch: the FP32 operator once, U_l, U_{l-1} read and U_{l+1} written
     # (FP32), Z read (FP64), P read and written (FP64)
@@ -189,7 +213,7 @@ def hbm_point(stream, refined=False):
             "launch_ms": launch_ms, "algorithmic_bytes": alg_bytes, "achieved": gbs, "unit": "GB/s",
             "peak": PEAK_HBM_GBS, "frac": gbs / PEAK_HBM_GBS, "traffic": traffic,
             "counter_GBps": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,
-            "tflops": flops / (launch_ms * 1e-3) / 1e12}
+            "tflops": flops / (launch_ms * 1e-3) / 1e12, "all_columns": full}
 
 
 def factored_point(stream, mu):
