@@ -201,6 +201,9 @@ struct dm_ctx {
     DevBuf<double> work;  // partial products of the split-reduction shapes (byte size via double slots)
     DevBuf<double> Pfin;  // symmetric form: P = L^T Q of one pass
     DevBuf<double> coef, coef_zero, fk, w, v, out;
+    // dm_combine_sets: coefficient rows, cosine-sum nodes, the bound, and
+    // device copies of blocks given in host memory (kept between calls)
+    DevBuf<double> cs_coef, cs_fk, cs_out, cs_stage;
     DevBuf<int> flag;
     DevBuf<long long> cols;
 };
@@ -277,9 +280,11 @@ struct MlpState {
     DevBuf<float> acts;  // H_0 (input) .. H_{L-1}, then Y: B x sizes[j] each
     std::vector<long> act_off;
     DevBuf<float> T, G0, G1, partial, loss;
+    DevBuf<double> mom_in;  // dm_mlp_predict: device copy of the stochastic moments
     int cap_B = 0;
     ~MlpState() {
         for (auto* b : {&params, &grads, &m, &v, &acts, &T, &G0, &G1, &partial, &loss}) b->release();
+        mom_in.release();
     }
 };
 
@@ -1139,7 +1144,7 @@ void dm_destroy(dm_ctx* c) {
     if (c->stream && !c->poisoned) (void)hipStreamSynchronize(c->stream);
     for (auto* b : {&c->op.Sinv, &c->op.HT, &c->op.HNbuf, &c->op.S_val, &c->mom, &c->Ua, &c->Ub, &c->Z, &c->P,
                     &c->part_start, &c->part_steps, &c->work, &c->Pfin, &c->coef, &c->coef_zero, &c->fk,
-                    &c->w, &c->v, &c->out})
+                    &c->w, &c->v, &c->out, &c->cs_coef, &c->cs_fk, &c->cs_out, &c->cs_stage})
         b->release();
     c->op.release();
     for (auto& o : c->batch) o.release();
@@ -1804,17 +1809,18 @@ dm_status dm_combine_sets(dm_ctx* c, int n_sets, const double* mus, double beta,
     hipStream_t s = c->stream;
     const double ebar = 0.5 * (c->op.emax + c->op.emin), de = 0.5 * (c->op.emax - c->op.emin);
     const int M = 4 * order, stride = order + 1;
-    DevBuf<double> A, fk, out;
+    DevBuf<double>& A = c->cs_coef;
     hipError_t e = ensure(A, (size_t)stride * (n_sets + 1));
-    if (e == hipSuccess) e = ensure(fk, (size_t)M);
-    if (e == hipSuccess) e = ensure(out, 1);
+    if (e == hipSuccess) e = ensure(c->cs_fk, (size_t)M);
+    if (e == hipSuccess) e = ensure(c->cs_out, 1);
     for (int q = 0; q <= n_sets && e == hipSuccess; ++q)
-        e = cheb_coefficients(order, M, ebar, de, q < n_sets ? mus[q] : mu, beta, fk.p, A.p + (size_t)q * stride, s);
-    if (e == hipSuccess) e = interp_bound(order, n_sets, A.p, stride, cs, out.p, s);
+        e = cheb_coefficients(order, M, ebar, de, q < n_sets ? mus[q] : mu, beta, c->cs_fk.p, A.p + (size_t)q * stride,
+                              s);
+    if (e == hipSuccess) e = interp_bound(order, n_sets, A.p, stride, cs, c->cs_out.p, s);
     double hb = 0.0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&hb, out.p, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, c->cs_out.p, 8, hipMemcpyDeviceToHost, s);
     // blocks in host memory go through device copies
-    DevBuf<double> stage;
+    DevBuf<double>& stage = c->cs_stage;
     if (e == hipSuccess && n > 0) {
         int nhost = 0;
         for (int q = 0; q < n_sets; ++q) nhost += !is_device_ptr(P_in[q]);
@@ -1835,10 +1841,6 @@ dm_status dm_combine_sets(dm_ctx* c, int n_sets, const double* mus, double beta,
         if (e == hipSuccess && !out_dev) e = hipMemcpyAsync(P_out, dst, (size_t)n * 8, hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    A.release();
-    fk.release();
-    out.release();
-    stage.release();
     if (e != hipSuccess) return fail_hip(c, e, "set combination");
     if (bound) *bound = hb;
     return DM_OK;
@@ -3280,16 +3282,12 @@ dm_status dm_mlp_predict(dm_ctx* c, const double* m_stoch, int n_mom, double bet
         max_order < 16)
         return set_err(c, DM_E_ARG, "network shape does not match n_mom + 4 -> 2, or bad arguments");
     if ((st = mlp_reserve(c, 1)) != DM_OK) return st;
-    DevBuf<double> md;
-    HIPTRY(c, ensure(md, (size_t)n_mom));
-    hipError_t e = hipMemcpyAsync(md.p, m_stoch, (size_t)n_mom * 8, hipMemcpyDefault, c->stream);
+    HIPTRY(c, ensure(M.mom_in, (size_t)n_mom));
+    hipError_t e = hipMemcpyAsync(M.mom_in.p, m_stoch, (size_t)n_mom * 8, hipMemcpyDefault, c->stream);
     if (e == hipSuccess)
-        e = mlp_features(n_mom, md.p, c->op.emin, c->op.emax, beta, n_e, c->opt.spin, (double)c->op.K,
+        e = mlp_features(n_mom, M.mom_in.p, c->op.emin, c->op.emax, beta, n_e, c->opt.spin, (double)c->op.K,
                          M.acts.p, c->stream);
-    if (e != hipSuccess) {
-        md.release();
-        return fail_hip(c, e, "predict features");
-    }
+    if (e != hipSuccess) return fail_hip(c, e, "predict features");
     const int L = (int)M.sizes.size() - 1;
     for (int j = 0; j < L && e == hipSuccess; ++j)
         e = mlp_linear_fwd(1, M.sizes[j], M.sizes[j + 1], M.acts.p + M.act_off[j], M.params.p + M.w_off[j],
@@ -3297,7 +3295,6 @@ dm_status dm_mlp_predict(dm_ctx* c, const double* m_stoch, int n_mom, double bet
     float y[2] = {0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(y, M.acts.p + M.act_off[L], 2 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    md.release();
     if (e != hipSuccess) return fail_hip(c, e, "predict");
     const double ebar = 0.5 * (c->op.emax + c->op.emin), de = 0.5 * (c->op.emax - c->op.emin);
     *mu = ebar + de * (double)y[0] / 10.0;

@@ -138,31 +138,98 @@ def _lagrange(nodes, x):
     return w
 
 
+def _network_path(ctx, c, beta, cols, P, Ps, params, sizes, sigma, xi, tol_order, b_target, m_max, N_plain):
+    """The network-assisted density matrix on a loaded context (timed by the
+    caller): stochastic moments -> mu^; the window mu^ +- 2.5 sigma with the
+    fewest nodes m <= m_max whose interpolation bound over the window is
+    <= b_target; one multi-set pass; mu_d from the interpolated electron
+    count; the Lagrange combination, or (mu_d outside the window, bound
+    missed) mu by bisection and a P pass; no window: the plain two passes."""
+    g = 2.0
+    lo, hi = ctx.dm_get_bounds()
+    ctx.dm_reset_moments()
+    ctx.dm_mlp_init(sizes)
+    ctx.dm_mlp_set_params(params)
+    ms = ctx.dm_stoch_moments(learn.N_MOM, xi)
+    mu_hat, N_hat = ctx.dm_mlp_predict(ms, beta, c.n_electrons, max_order=16384)
+    half = 2.5 * sigma
+    probe = np.linspace(mu_hat - half, mu_hat + half, 9)
+    N = max(ctx.dm_cheb_order(lo, hi, x, beta, tol_order, 16384) for x in probe)
+    m = None
+    for mm in range(3, m_max + 1):
+        nodes = _nodes(mu_hat, half, mm)
+        if max(ctx.dm_combine_sets(nodes, beta, N, x, [], None) for x in probe) <= b_target:
+            m = mm
+            break
+    out = dict(mu_hat=mu_hat, N_hat=N_hat, m=m, accepted=False, how="plain (no window meets the bound)")
+    if m is not None:
+        ctx.dm_chebyshev_block_multi(cols, N, list(nodes), [beta] * m, Ps[:m])
+        trq = np.array([ctx.dm_trace(x, beta)[0] for x in nodes])
+        f = lambda x: g * float(_lagrange(nodes, x) @ trq) - c.n_electrons
+        a_, b_ = mu_hat - half, mu_hat + half
+        out["how"] = f"window m={m}, mu outside: fallback"
+        if f(a_) < 0.0 < f(b_):
+            for _ in range(100):
+                mid = 0.5 * (a_ + b_)
+                if f(mid) < 0.0:
+                    a_ = mid
+                else:
+                    b_ = mid
+            mu = 0.5 * (a_ + b_)
+            bound = ctx.dm_combine_sets(nodes, beta, N, mu, Ps[:m], P)
+            out["accepted"] = bound <= b_target
+            out["how"] = f"window m={m}, one pass" if out["accepted"] else f"window m={m}, bound {bound:.1e}: fallback"
+        if not out["accepted"]:
+            mu = ctx.dm_solve_mu(c.n_electrons, beta, tol=1e-6)
+            ctx.dm_chebyshev_block(cols, N, mu, beta, P)
+        out["nodes"] = nodes
+    else:
+        N = N_plain
+        ctx.dm_chebyshev_block(cols, N, 0.0, beta, None)
+        mu = ctx.dm_solve_mu(c.n_electrons, beta, tol=1e-6)
+        ctx.dm_chebyshev_block(cols, N, mu, beta, P)
+    out.update(mu=mu, N=N, lo=lo, hi=hi)
+    return out
+
+
+def _delivered_count(sp, out, beta, n_e):
+    """Oracle electron count of the P a network path delivered: the sum of
+    the blocks' counts with the combination weights, or the count at its mu."""
+    g = 2.0
+    if out["accepted"]:
+        wq = _lagrange(out["nodes"], out["mu"])
+        tr = sum(wq[q] * O.trace_poly(sp, out["N"], x, beta, out["lo"], out["hi"])[0]
+                 for q, x in enumerate(out["nodes"]))
+    else:
+        tr = O.trace_poly(sp, out["N"], out["mu"], beta, out["lo"], out["hi"])[0]
+    return abs(g * tr - n_e)
+
+
 def test_network_window_pass_gain():
     """The trained predictor (paper_2108_13478_amd/predictor.npz, made by
     paper_2108_13478_amd/train_predictor.py on 640 method-labelled clusters,
-    K 1024..4096) against the same symmetric-form path without it, FP64 (the
-    electron count below needs exact moments: an FP32 pass's moments put the
-    oracle's count 4e-4 off at K = 4096).
+    K 1024..4096) against the same symmetric-form path without it.
 
     Without the network mu is unknown before a pass: a moments pass over
     every column, mu by bisection on the exact moments (electron count to
     1e-6), then the P pass, both at the largest coefficient-tail order
-    (tail <= 1e-3) over mu in the Lanczos interval.  With it: 16-probe
-    stochastic moments give mu^; the window mu^ +- 2.5 sigma (sigma: the
-    network's held-out RMS mu error) gets the fewest Chebyshev nodes m <= 12
-    whose interpolation bound (dm_combine_sets, sum_l |a_l(mu) - sum_q w_q
-    a_l(mu_q)|) is <= 1e-5 over the whole window, and the largest tail order
-    over the window; one pass accumulates P at the m nodes with the exact
-    moments fused; mu_d solves g sum_q w_q(mu_d) Tr[P_q S] = N_e (the
-    electron count of the delivered P, linear in the blocks); if mu_d lies
-    in the window P = sum_q w_q(mu_d) P_q and the second pass is saved,
-    otherwise mu by bisection and a P pass (fallback).  When no m <= 12
-    meets the bound (large beta against the window) the network path is the
-    plain path.  Both paths are held to the same targets: the delivered P's
-    electron count (oracle traces) within 1e-6 of N_e, and max|P - P_exact|
-    (P_exact: the oracle's Fermi-Dirac matrix at its exact mu) within
-    1e-2."""
+    (tail <= 1e-3) over mu in the Lanczos interval.  With it (_network_path):
+    16-probe stochastic moments give mu^; a window of m <= 12 Chebyshev nodes
+    around it, checked before the pass by the interpolation bound <= 1e-5;
+    one pass accumulating P at the nodes with the exact moments fused; mu_d
+    solving the delivered P's electron count g sum_q w_q(mu_d) Tr[P_q S] =
+    N_e (linear in the blocks); P = sum_q w_q(mu_d) P_q (dm_combine_sets), so
+    the second pass is saved; a fallback to bisection and a P pass when mu_d
+    leaves the window; the plain two passes when no window meets the bound
+    (large beta against the window).
+
+    Two comparisons, both at max|P - P_exact| <= 1e-2 (P_exact: the oracle's
+    Fermi-Dirac matrix at its exact mu): the network alone, FP64 against
+    FP64 (delivered electron counts in the oracle's traces within 1e-6 in
+    both); and the network with the FP32 recursion against the plain FP64
+    path.  The FP32 operator's rounding moves the oracle's count of the
+    delivered P by about 4e-4 electrons at K = 4096 (FP32 moments), so that
+    path is held to 2e-3; the 1e-6 count needs FP64 moments."""
     import json
     import time
 
@@ -179,20 +246,22 @@ def test_network_window_pass_gain():
         f"RMS log2 N error {meta['sigma_log2_order']:.3f}")
     tol_order, b_target, m_max, target = 1e-3, 1e-5, 12, 1e-2
     held = [(1024, 41, 20.0), (768, 42, 20.0), (1024, 43, 30.0), (768, 44, 40.0)]
-    t_plain_all, t_net_all, saved, windows = 0.0, 0.0, 0, 0
+    tot = {"plain": 0.0, "net64": 0.0, "net32": 0.0}
+    saved = 0
     for n_atoms, seed, beta in held:
         c = make_cluster(n_atoms, seed=seed, geometry="sphere", onsite="scaled")
-        g = 2.0
         sp = O.spectrum(c)
         mu_x = O.solve_mu_exact(sp, c.n_electrons, beta)
         P_x = O.density_matrix_exact(sp, np.arange(c.K), mu_x, beta)
         cols = torch.arange(c.K, dtype=torch.int64, device="cuda")
+        xi = torch.from_numpy(rademacher(c.K, learn.N_VEC, seed=9000 + seed)).cuda()
+        P = torch.empty((c.K, c.K), dtype=torch.float64, device="cuda")
+        Ps = [torch.empty((c.K, c.K), dtype=torch.float64, device="cuda") for _ in range(m_max)]
         ctx = dmlib.Context(precision=dmlib.DM_FP64)
         ctx.dm_set_operator_form(dmlib.DM_FORM_SYMMETRIC)
         ctx.set_cluster(c)
         lo, hi = ctx.dm_get_bounds()
-        P = torch.empty((c.K, c.K), dtype=torch.float64, device="cuda")
-        # ---- without the network
+        # ---- without the network (FP64)
         N_plain = max(ctx.dm_cheb_order(lo, hi, x, beta, tol_order, 16384) for x in np.linspace(lo, hi, 41))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -202,73 +271,39 @@ def test_network_window_pass_gain():
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         err_plain = np.abs(P.cpu().numpy().T - P_x).max()
-        ne_plain = abs(g * O.trace_poly(sp, N_plain, mu_p, beta, lo, hi)[0] - c.n_electrons)
-        # ---- with the network
-        ctx.dm_reset_moments()
-        ctx.dm_mlp_init(sizes)
-        ctx.dm_mlp_set_params(W["params"])
-        xi = torch.from_numpy(rademacher(c.K, learn.N_VEC, seed=9000 + seed)).cuda()
-        Ps = [torch.empty((c.K, c.K), dtype=torch.float64, device="cuda") for _ in range(m_max)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ms = ctx.dm_stoch_moments(learn.N_MOM, xi)
-        mu_hat, N_hat = ctx.dm_mlp_predict(ms, beta, c.n_electrons, max_order=16384)
-        half = 2.5 * sigma
-        N_net = max(ctx.dm_cheb_order(lo, hi, x, beta, tol_order, 16384)
-                    for x in np.linspace(mu_hat - half, mu_hat + half, 9))
-        m, probe = None, np.linspace(mu_hat - half, mu_hat + half, 9)
-        for mm in range(3, m_max + 1):
-            nodes = _nodes(mu_hat, half, mm)
-            if max(ctx.dm_combine_sets(nodes, beta, N_net, x, [], None) for x in probe) <= b_target:
-                m = mm
-                break
-        accepted, how = False, "plain (no window meets the bound)"
-        if m is not None:
-            windows += 1
-            ctx.dm_chebyshev_block_multi(cols, N_net, list(nodes), [beta] * m, Ps[:m])
-            trq = np.array([ctx.dm_trace(x, beta)[0] for x in nodes])
-            f = lambda x: g * float(_lagrange(nodes, x) @ trq) - c.n_electrons
-            a_, b_ = mu_hat - half, mu_hat + half
-            if f(a_) < 0.0 < f(b_):
-                for _ in range(100):
-                    mid = 0.5 * (a_ + b_)
-                    if f(mid) < 0.0:
-                        a_ = mid
-                    else:
-                        b_ = mid
-                mu_n = 0.5 * (a_ + b_)
-                bound = ctx.dm_combine_sets(nodes, beta, N_net, mu_n, Ps[:m], P)
-                accepted = bound <= b_target
-                how = f"window m={m}, one pass" if accepted else f"window m={m}, bound {bound:.1e}: fallback"
-            else:
-                how = f"window m={m}, mu outside: fallback"
-            if not accepted:
-                mu_n = ctx.dm_solve_mu(c.n_electrons, beta, tol=1e-6)
-                ctx.dm_chebyshev_block(cols, N_net, mu_n, beta, P)
-        else:
-            N_net = N_plain
-            ctx.dm_chebyshev_block(cols, N_net, 0.0, beta, None)
-            mu_n = ctx.dm_solve_mu(c.n_electrons, beta, tol=1e-6)
-            ctx.dm_chebyshev_block(cols, N_net, mu_n, beta, P)
-        torch.cuda.synchronize()
-        t_net = time.perf_counter() - t0
-        err_net = np.abs(P.cpu().numpy().T - P_x).max()
-        if accepted:
-            wq = _lagrange(nodes, mu_n)
-            ne_net = abs(g * sum(wq[q] * O.trace_poly(sp, N_net, nodes[q], beta, lo, hi)[0] for q in range(m))
-                         - c.n_electrons)
-        else:
-            ne_net = abs(g * O.trace_poly(sp, N_net, mu_n, beta, lo, hi)[0] - c.n_electrons)
-        t_plain_all += t_plain
-        t_net_all += t_net
-        saved += accepted
-        say(f"  K={c.K} beta={beta:g}: plain N={N_plain} {t_plain:.2f} s err {err_plain:.2e} |dNe| {ne_plain:.1e}"
-            f" | net N={N_net} (N^={N_hat}) mu^-mu={mu_hat - mu_x:+.4f} {how} {t_net:.2f} s err {err_net:.2e} "
-            f"|dNe| {ne_net:.1e} ({t_plain / t_net:.2f}x) max|P| {np.abs(P_x).max():.1f}")
-        assert err_plain <= target and err_net <= target
-        assert ne_plain <= 1e-6 and ne_net <= 1e-6
-        del Ps, P, ctx
+        ne_plain = abs(2.0 * O.trace_poly(sp, N_plain, mu_p, beta, lo, hi)[0] - c.n_electrons)
+        res = {}
+        for name, prec in (("net64", dmlib.DM_FP64), ("net32", dmlib.DM_FP32)):
+            if prec != dmlib.DM_FP64:
+                ctx.close()
+                ctx = dmlib.Context(precision=prec)
+                ctx.dm_set_operator_form(dmlib.DM_FORM_SYMMETRIC)
+                ctx.set_cluster(c)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = _network_path(ctx, c, beta, cols, P, Ps, W["params"], sizes, sigma, xi, tol_order, b_target,
+                                m_max, N_plain)
+            torch.cuda.synchronize()
+            out["t"] = time.perf_counter() - t0
+            out["err"] = np.abs(P.cpu().numpy().T - P_x).max()
+            out["dNe"] = _delivered_count(sp, out, beta, c.n_electrons)
+            res[name] = out
+        ctx.close()
+        n64, n32 = res["net64"], res["net32"]
+        tot["plain"] += t_plain
+        tot["net64"] += n64["t"]
+        tot["net32"] += n32["t"]
+        saved += n64["accepted"]
+        say(f"  K={c.K} beta={beta:g}: plain FP64 N={N_plain} {t_plain:.2f} s err {err_plain:.2e} "
+            f"|dNe| {ne_plain:.1e} max|P| {np.abs(P_x).max():.1f}; mu^-mu={n64['mu_hat'] - mu_x:+.4f} N^={n64['N_hat']}")
+        for name, o in (("network FP64", n64), ("network FP32", n32)):
+            say(f"    {name}: N={o['N']} {o['how']} {o['t']:.2f} s err {o['err']:.2e} |dNe| {o['dNe']:.1e} "
+                f"({t_plain / o['t']:.2f}x)")
+        assert err_plain <= target and n64["err"] <= target and n32["err"] <= target
+        assert ne_plain <= 1e-6 and n64["dNe"] <= 1e-6 and n32["dNe"] <= 2e-3
+        del Ps, P
         torch.cuda.empty_cache()
-    say(f"  total: plain {t_plain_all:.2f} s, network {t_net_all:.2f} s ({t_plain_all / t_net_all:.2f}x); "
-        f"second pass saved {saved}/{len(held)} ({windows} windows run)")
-    assert saved >= 1 and t_plain_all / t_net_all > 1.0
+    say(f"  total: plain FP64 {tot['plain']:.2f} s, network FP64 {tot['net64']:.2f} s "
+        f"({tot['plain'] / tot['net64']:.2f}x), network FP32 {tot['net32']:.2f} s "
+        f"({tot['plain'] / tot['net32']:.2f}x); second pass saved {saved}/{len(held)}")
+    assert saved >= 1 and tot["plain"] / tot["net64"] > 1.0 and tot["plain"] / tot["net32"] > 1.5
