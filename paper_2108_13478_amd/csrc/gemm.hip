@@ -12,6 +12,8 @@
 // j + 16 * (i / 4), element i % 4, so each lane owns four consecutive rows of
 // one column: the epilogue reads and writes 4-element vectors of column-major
 // blocks.
+#include <type_traits>
+
 #include "dm_common.hpp"
 
 namespace dm {
@@ -408,34 +410,54 @@ cheb_step_kernel(ChebStepArgs a) {
     const int li = lane & 15, lq = lane >> 4;
     const C alpha = static_cast<C>(a.alpha);
     const double c0 = a.coef[a.l];
-    const S* Uprev = static_cast<const S*>(a.Uprev);
-    S* Unext = static_cast<S*>(a.Unext);
+    const S* __restrict__ Uprev = static_cast<const S*>(a.Uprev);
+    S* __restrict__ Unext = static_cast<S*>(a.Unext);
+    const double* __restrict__ Zp = a.Z;
+    double* __restrict__ Pp = a.P;
+    // Epilogue in groups of EG tiles: every load of a group is issued before
+    // the group's arithmetic, so a lane waits for memory once per group and
+    // coefficient set instead of once per tile.  Per element the arithmetic
+    // and the order of the moment sum are those of one tile at a time.  The
+    // group is as large as the registers left by the main loop allow (two
+    // waves per SIMD, or the refined type's FP64 copies: smaller groups).
+    constexpr int NTILE = TM * TN;
+    constexpr int EGMAX = WM * WN > 4 ? 1 : (std::is_same<T, W32>::value ? 2 : 4);
+    constexpr int EG = NTILE % EGMAX == 0 ? EGMAX : 1;
     double msum = 0.0;
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int g0 = 0; g0 < NTILE; g0 += EG) {
+        long idx[EG];
+        svec_t up[EG];
+        double4_t z[EG], pv[EG], od[EG];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const long idx = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * a.Kp;
-            cvec_t out = alpha * acc[i][j];
-            if (a.has_prev)
-                out -= __builtin_convertvector(*reinterpret_cast<const svec_t*>(Uprev + idx), cvec_t);
-            const svec_t st = __builtin_convertvector(out, svec_t);
-            *reinterpret_cast<svec_t*>(Unext + idx) = st;
-            const double4_t z = *reinterpret_cast<const double4_t*>(a.Z + idx);
-            double4_t od = {(double)st[0], (double)st[1], (double)st[2], (double)st[3]};
-            msum += z[0] * od[0] + z[1] * od[1] + z[2] * od[2] + z[3] * od[3];
-            if (c0 != 0.0) {
-                double4_t* p = reinterpret_cast<double4_t*>(a.P + idx);
-                *p = *p + c0 * od;
-            }
-            for (int q = 1; q < a.nsets; ++q) {
-                const double c = a.coef[q * a.cstride + a.l];
-                if (c != 0.0) {
-                    double4_t* p = reinterpret_cast<double4_t*>(a.P + q * a.pstride + idx);
-                    *p = *p + c * od;
-                }
-            }
+        for (int t = 0; t < EG; ++t) {
+            const int i = (g0 + t) / TN, j = (g0 + t) % TN;
+            idx[t] = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * a.Kp;
+            if (a.has_prev) up[t] = *reinterpret_cast<const svec_t*>(Uprev + idx[t]);
+            z[t] = *reinterpret_cast<const double4_t*>(Zp + idx[t]);
+            if (c0 != 0.0) pv[t] = *reinterpret_cast<const double4_t*>(Pp + idx[t]);
         }
+#pragma unroll
+        for (int t = 0; t < EG; ++t) {
+            const int i = (g0 + t) / TN, j = (g0 + t) % TN;
+            cvec_t out = alpha * acc[i][j];
+            if (a.has_prev) out -= __builtin_convertvector(up[t], cvec_t);
+            const svec_t st = __builtin_convertvector(out, svec_t);
+            *reinterpret_cast<svec_t*>(Unext + idx[t]) = st;
+            od[t] = double4_t{(double)st[0], (double)st[1], (double)st[2], (double)st[3]};
+            msum += z[t][0] * od[t][0] + z[t][1] * od[t][1] + z[t][2] * od[t][2] + z[t][3] * od[t][3];
+            if (c0 != 0.0) *reinterpret_cast<double4_t*>(Pp + idx[t]) = pv[t] + c0 * od[t];
+        }
+        for (int q = 1; q < a.nsets; ++q) {
+            const double c = a.coef[q * a.cstride + a.l];
+            if (c == 0.0) continue;
+            double* __restrict__ Pq = Pp + q * a.pstride;
+#pragma unroll
+            for (int t = 0; t < EG; ++t) pv[t] = *reinterpret_cast<const double4_t*>(Pq + idx[t]);
+#pragma unroll
+            for (int t = 0; t < EG; ++t) *reinterpret_cast<double4_t*>(Pq + idx[t]) = pv[t] + c * od[t];
+        }
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) msum += __shfl_xor(msum, off, 64);
     __shared__ double red[WM * WN];
@@ -583,22 +605,36 @@ cheb_batch_kernel(BatchArgs a) {
                 const int row0 = r0 + (wave % WM) * TM * 16;
                 typename Mfma<T>::acc_t acc[TM][TN];
                 gemm_mainloop<T, TM, TN, KV, DEPTH>(Kp, HN, Kp, ucur, Kp, row0, col0, acc);
+                // the step kernel's epilogue, loads of EG tiles issued together
+                // (pairs in FP32; one at a time where the persistent loop's
+                // registers are short: FP64, two waves per SIMD)
+                constexpr int NTILE = TM * TN;
+                constexpr int EGMAX = (WM * WN > 4 || sizeof(T) == 8) ? 1 : 2;
+                constexpr int EG = NTILE % EGMAX == 0 ? EGMAX : 1;
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
+                for (int g0 = 0; g0 < NTILE; g0 += EG) {
+                    long idx[EG];
+                    vec_t up[EG];
+                    double4_t z[EG], pv[EG];
 #pragma unroll
-                    for (int j = 0; j < TN; ++j) {
-                        const long idx = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * Kp;
-                        vec_t out = alpha * acc[i][j];
-                        if (l > 1) out -= *reinterpret_cast<const vec_t*>(unext + idx);
-                        *reinterpret_cast<vec_t*>(unext + idx) = out;
-                        const double4_t z = *reinterpret_cast<const double4_t*>(cl.Z + idx);
-                        double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
-                        msum += z[0] * od[0] + z[1] * od[1] + z[2] * od[2] + z[3] * od[3];
-                        if (c != 0.0) {
-                            double4_t* p = reinterpret_cast<double4_t*>(cl.P + idx);
-                            *p = *p + c * od;
-                        }
+                    for (int t = 0; t < EG; ++t) {
+                        const int i = (g0 + t) / TN, j = (g0 + t) % TN;
+                        idx[t] = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * Kp;
+                        if (l > 1) up[t] = *reinterpret_cast<const vec_t*>(unext + idx[t]);
+                        z[t] = *reinterpret_cast<const double4_t*>(cl.Z + idx[t]);
+                        if (c != 0.0) pv[t] = *reinterpret_cast<const double4_t*>(cl.P + idx[t]);
                     }
+#pragma unroll
+                    for (int t = 0; t < EG; ++t) {
+                        const int i = (g0 + t) / TN, j = (g0 + t) % TN;
+                        vec_t out = alpha * acc[i][j];
+                        if (l > 1) out -= up[t];
+                        *reinterpret_cast<vec_t*>(unext + idx[t]) = out;
+                        double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
+                        msum += z[t][0] * od[0] + z[t][1] * od[1] + z[t][2] * od[2] + z[t][3] * od[3];
+                        if (c != 0.0) *reinterpret_cast<double4_t*>(cl.P + idx[t]) = pv[t] + c * od;
+                    }
+                }
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) msum += __shfl_xor(msum, off, 64);
