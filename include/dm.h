@@ -454,9 +454,11 @@ dm_status dm_set_moments_precision(dm_ctx* ctx, int precision);
  * P_out: NULL or host array of n pointers (each host or device memory, K_c x
  * K_c column-major FP64, or NULL to skip that cluster).
  * Errors: DM_E_STATE (no batch; or a gang member was not resident, so a
- * step barrier gave up and the results are void), DM_E_ARG, DM_E_BOUNDS,
- * DM_E_NOCONV (a bisection stopped at rounding level before tol; mu_out
- * still filled). */
+ * step barrier gave up after 2^20 polls and the results are void; the
+ * environment variable DM_BATCH_BARRIER_POLLS sets another limit, read when
+ * the launch sequence is built: at every eager run, at capture for the
+ * graph), DM_E_ARG, DM_E_BOUNDS, DM_E_NOCONV (a bisection stopped at
+ * rounding level before tol; mu_out still filled). */
 dm_status dm_batch_run(dm_ctx* ctx, int order, double beta, const double* n_e, double tol,
                        double* mu_out, double* const* P_out, int flags);
 

@@ -2522,6 +2522,19 @@ int batch_mom_cfg(int cfg) {
     return first;
 }
 
+// Polls after which a gang barrier of the batch kernel gives up: 2^20, or
+// the environment variable DM_BATCH_BARRIER_POLLS (>= 0) read when a batch
+// launch sequence is built (so tests can make the give-up path run).
+int batch_barrier_polls() {
+    const char* v = std::getenv("DM_BATCH_BARRIER_POLLS");
+    if (v && *v) {
+        char* end = nullptr;
+        const long x = std::strtol(v, &end, 10);
+        if (end && *end == '\0' && x >= 0 && x <= (1L << 30)) return (int)x;
+    }
+    return 1 << 20;
+}
+
 // Items of at least this many operator rows are shared by a gang (its
 // members split the row tiles and meet after every step); smaller ones run
 // on one workgroup each, kGang of similar size to a round.
@@ -2736,8 +2749,9 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
     const int cfg1 = split_mom ? bs.cfg_m : bs.cfg;
     const BatchTable& t1 = split_mom ? bs.tab_m : bs.tab;
     BQ(batch_start(c, true, mprec));
+    const int polls = batch_barrier_polls();
     BatchArgs a{split_mom ? bs.d_clusters_m.p : bs.d_clusters.p, t1.rounds.p, t1.gang_start.p, bs.counter.p,
-                c->flag.p, order, 0, t1.gmap};
+                c->flag.p, order, 0, t1.gmap, polls};
     BQ(cheb_batch(a, cfg1, mprec, t1.grid, s));
     const int BN = cheb_tile_cols(cfg1);
     for (int i = 0; i < n; ++i) {
@@ -2756,7 +2770,7 @@ hipError_t batch_enqueue(dm_ctx* c, int order, double beta, const std::vector<do
     // pass 2: P at mu_c
     BQ(batch_start(c, false, c->precision));
     BatchArgs a2{bs.d_clusters.p, bs.tab.rounds.p, bs.tab.gang_start.p, bs.counter.p + ngm, c->flag.p, order, 1,
-                 bs.tab.gmap};
+                 bs.tab.gmap, polls};
     BQ(cheb_batch(a2, bs.cfg, c->precision, bs.tab.grid, s));
     // symmetric form: P = L^T Q into the Z buffer (Z is not read after the pass)
     for (int i = 0; i < n; ++i) {
@@ -2966,13 +2980,19 @@ dm_status dm_batch_autotune(dm_ctx* c, int steps, double* table, int* ntable, in
         HIPTRY(c, fill_i32(bs.counter.p, 0, bs.tab.ngangs, s));
         HIPTRY(c, fill_i32(c->flag.p, 0, 4, s));
         BatchArgs a{bs.d_clusters.p, bs.tab.rounds.p, bs.tab.gang_start.p, bs.counter.p, c->flag.p, steps, 0,
-                    bs.tab.gmap};
+                    bs.tab.gmap, batch_barrier_polls()};
         HIPTRY(c, hipEventRecord(e0, s));
         HIPTRY(c, cheb_batch(a, cfg, c->precision, bs.tab.grid, s));
         HIPTRY(c, hipEventRecord(e1, s));
         HIPTRY(c, hipEventSynchronize(e1));
         float ms = 0;
         HIPTRY(c, hipEventElapsedTime(&ms, e0, e1));
+        int hflag = 0;
+        HIPTRY(c, hipMemcpy(&hflag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost));
+        if (hflag & 8) {
+            st = set_err(c, DM_E_STATE, "a batch workgroup waited too long for its gang (too few resident)");
+            break;
+        }
         res.push_back({cfg, ms});
     }
     (void)hipEventDestroy(e0);

@@ -122,6 +122,7 @@ struct BatchArgs {
     int order;
     int with_P;
     int gmap;               // 8: gang g's members share XCD g % 8; 1: gangs of consecutive workgroups
+    int max_polls;          // a barrier wait gives up after this many polls
 };
 hipError_t cheb_batch(const BatchArgs& a, int cfg, int precision, int grid, hipStream_t s);
 // Workgroups of tile shape cfg that fit on one CU at once.

@@ -545,11 +545,12 @@ __global__ void __launch_bounds__(256) cheb_combine_kernel(ChebStepArgs a) {
 // Waits until the gang's barrier counter reaches `target` (every member has
 // arrived); the release / acquire pair at agent scope orders this
 // workgroup's U stores before the other members' loads of them.  Members
-// arrive within about one row tile of each other, so a wait of 2^20 polls
-// means a member is not running: the waiter sets flag bit 8 and goes on, and
-// once that bit is set no barrier waits any more, so the launch drains (the
-// results are then void and the host reports it).
-__device__ inline void gang_barrier(int* bar, int target, int* flag) {
+// arrive within about one row tile of each other, so a wait of max_polls
+// polls (2^20 by default) means a member is not running: the waiter sets
+// flag bit 8 and goes on, and once that bit is set no barrier waits any
+// more, so the launch drains (the results are then void and the host
+// reports it).
+__device__ inline void gang_barrier(int* bar, int target, int* flag, int max_polls) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -557,7 +558,7 @@ __device__ inline void gang_barrier(int* bar, int target, int* flag) {
         while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 8) break;
             __builtin_amdgcn_s_sleep(1);
-            if (++polls > (1 << 20)) {
+            if (++polls > max_polls) {
                 atomicOr(flag, 8);
                 break;
             }
@@ -654,7 +655,7 @@ cheb_batch_kernel(BatchArgs a) {
             // the barrier (or, alone, the workgroup barrier) also orders this
             // step's U writes before the next step's reads
             if (rd.split)
-                gang_barrier(a.bar + gang, kGang * ++nbar, a.flag);
+                gang_barrier(a.bar + gang, kGang * ++nbar, a.flag, a.max_polls);
             else
                 __syncthreads();
         }

@@ -178,3 +178,28 @@ def test_batch_refuses_other_precision():
         ctx.dm_batch_autotune(steps=4)
     ctx.dm_set_precision(dmlib.DM_FP32)
     ctx.dm_batch_run(50, 10.0, ne, tol=1e-4, flags=dmlib.DM_BATCH_MOMENTS_ONLY)
+
+
+def test_gang_barrier_give_up_is_reported(monkeypatch):
+    """The step barrier of a gang gives up after a bounded number of polls
+    and the run reports DM_E_STATE instead of waiting forever or returning
+    silently.  Forced from the host: with DM_BATCH_BARRIER_POLLS = 0 a member
+    that arrives before the others gives up at once, the launch drains, and
+    the context runs normally again once the limit is back to its default."""
+    clusters = make_batch([640, 60], [400, 401], processes=1)  # K = 2560 (shared by a gang), 240
+    say(f"case: barrier give-up, K = {[c.K for c in clusters]}")
+    ne = [c.n_electrons for c in clusters]
+    ref = dmlib.Context(precision=dmlib.DM_FP32)
+    ref.dm_batch_set_focks(clusters)
+    mu_ref = ref.dm_batch_run(60, 10.0, ne, tol=1e-4, flags=dmlib.DM_BATCH_EAGER | dmlib.DM_BATCH_MOMENTS_ONLY)
+    ctx = dmlib.Context(precision=dmlib.DM_FP32)
+    ctx.dm_batch_set_focks(clusters)
+    monkeypatch.setenv("DM_BATCH_BARRIER_POLLS", "0")
+    with pytest.raises(dmlib.DMError) as ei:
+        ctx.dm_batch_run(60, 10.0, ne, tol=1e-4, flags=dmlib.DM_BATCH_EAGER | dmlib.DM_BATCH_MOMENTS_ONLY)
+    say(f"  with no patience: {ei.value}")
+    assert ei.value.status == dmlib.DM_E_STATE and "gang" in str(ei.value)
+    monkeypatch.delenv("DM_BATCH_BARRIER_POLLS")
+    mu = ctx.dm_batch_run(60, 10.0, ne, tol=1e-4, flags=dmlib.DM_BATCH_EAGER | dmlib.DM_BATCH_MOMENTS_ONLY)
+    say(f"  default patience again: mu {mu} (fresh context {mu_ref})")
+    assert np.array_equal(mu, mu_ref)
