@@ -2575,6 +2575,7 @@ dm_status batch_pass_table(dm_ctx* c, int cfg, bool fp64_copy, int precision, De
         BatchClusterBufs& b = bs.cl[i];
         BatchCluster& h = hcl[i];
         h.Kp = op.Kp;
+        h.Kt = (int)round_up(op.K, 128);
         h.Bp = b.Bp;
         h.nblocks = b.Bp / BN;
         h.HN = fp64_copy ? op.HN64.p : op.HNbuf.p;

@@ -91,6 +91,8 @@ int cheb_num_tiles(int Kp, int Bp, int cfg);
 // partial[l * nblocks + block] receives the block's moment sum of step l.
 struct BatchCluster {
     int Kp, Bp, nblocks;
+    int Kt;  // K rounded up to 128: the rows and reduction length that carry data
+             // (rows Kt..Kp-1 of H_N and of every U_l are zero)
     const void* HN;
     void* Ua;
     void* Ub;

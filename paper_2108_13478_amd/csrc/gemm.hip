@@ -578,6 +578,7 @@ __global__ void __launch_bounds__(64 * WM * WN)
 cheb_batch_kernel(BatchArgs a) {
     typedef typename Mfma<T>::vec_t vec_t;
     constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN;
+    static_assert(128 % (4 * KV * DEPTH) == 0 && 128 % BM == 0, "the live extent Kt is a multiple of 128");
     __shared__ double red[WM * WN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lq = lane >> 4;
@@ -602,10 +603,12 @@ cheb_batch_kernel(BatchArgs a) {
             const double c = a.with_P ? cl.coef[l] : 0.0;
             const T alpha = static_cast<T>(l == 1 ? 1.0 : 2.0);
             double msum = 0.0;
-            for (int r0 = row_first * BM; r0 < Kp; r0 += row_step * BM) {
+            // rows and reduction only up to Kt: beyond it H_N and U_l are zero
+            // (the rows Kt..Kp-1 of U_{l+1} are neither written nor read)
+            for (int r0 = row_first * BM; r0 < cl.Kt; r0 += row_step * BM) {
                 const int row0 = r0 + (wave % WM) * TM * 16;
                 typename Mfma<T>::acc_t acc[TM][TN];
-                gemm_mainloop<T, TM, TN, KV, DEPTH>(Kp, HN, Kp, ucur, Kp, row0, col0, acc);
+                gemm_mainloop<T, TM, TN, KV, DEPTH>(cl.Kt, HN, Kp, ucur, Kp, row0, col0, acc);
                 // the step kernel's epilogue, loads of EG tiles issued together
                 // (pairs in FP32; one at a time where the persistent loop's
                 // registers are short: FP64, two waves per SIMD)
