@@ -410,8 +410,12 @@ cheb_step_kernel(ChebStepArgs a) {
     const int li = lane & 15, lq = lane >> 4;
     const C alpha = static_cast<C>(a.alpha);
     const double c0 = a.coef[a.l];
-    const S* __restrict__ Uprev = static_cast<const S*>(a.Uprev);
-    S* __restrict__ Unext = static_cast<S*>(a.Unext);
+    // Uprev and Unext are one buffer (U_{l+1} overwrites U_{l-1} element by
+    // element, each element read before it is written), so they carry no
+    // __restrict__; the program order below already issues every load of a
+    // group before the stores that could alias it.
+    const S* Uprev = static_cast<const S*>(a.Uprev);
+    S* Unext = static_cast<S*>(a.Unext);
     const double* __restrict__ Zp = a.Z;
     double* __restrict__ Pp = a.P;
     // Epilogue in groups of EG tiles: every load of a group is issued before
@@ -420,42 +424,106 @@ cheb_step_kernel(ChebStepArgs a) {
     // and the order of the moment sum are those of one tile at a time.  The
     // group is as large as the registers left by the main loop allow (two
     // waves per SIMD, or the refined type's FP64 copies: smaller groups).
+    // Register-tile shapes (PIPE) also issue the next group's loads before
+    // this group's arithmetic, in straight-line versions for the two uniform
+    // conditions (a previous vector; a P block to accumulate); the
+    // shared-panel shapes have no registers for a second group.
     constexpr int NTILE = TM * TN;
     constexpr int EGMAX = WM * WN > 4 ? 1 : (std::is_same<T, W32>::value ? 2 : 4);
     constexpr int EG = NTILE % EGMAX == 0 ? EGMAX : 1;
+    constexpr int NG = NTILE / EG;
+    constexpr bool PIPE = !LDSB;
     double msum = 0.0;
+    if constexpr (PIPE) {
+        auto at = [&](int g, int t) {
+            const int i = (g * EG + t) / TN, j = (g * EG + t) % TN;
+            return (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * a.Kp;
+        };
+        auto pipelined = [&](auto has_prev_c, auto with_p_c) {
+            constexpr bool HP = decltype(has_prev_c)::value, WP = decltype(with_p_c)::value;
+            svec_t up[2][EG];
+            double4_t z[2][EG], pv[2][EG];
+            auto load = [&](int g, int buf) {
 #pragma unroll
-    for (int g0 = 0; g0 < NTILE; g0 += EG) {
-        long idx[EG];
-        svec_t up[EG];
-        double4_t z[EG], pv[EG], od[EG];
+                for (int t = 0; t < EG; ++t) {
+                    if constexpr (HP) up[buf][t] = *reinterpret_cast<const svec_t*>(Uprev + at(g, t));
+                    z[buf][t] = *reinterpret_cast<const double4_t*>(Zp + at(g, t));
+                    if constexpr (WP) pv[buf][t] = *reinterpret_cast<const double4_t*>(Pp + at(g, t));
+                }
+            };
+            load(0, 0);
 #pragma unroll
-        for (int t = 0; t < EG; ++t) {
-            const int i = (g0 + t) / TN, j = (g0 + t) % TN;
-            idx[t] = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * a.Kp;
-            if (a.has_prev) up[t] = *reinterpret_cast<const svec_t*>(Uprev + idx[t]);
-            z[t] = *reinterpret_cast<const double4_t*>(Zp + idx[t]);
-            if (c0 != 0.0) pv[t] = *reinterpret_cast<const double4_t*>(Pp + idx[t]);
+            for (int g = 0; g < NG; ++g) {
+                const int buf = g & 1;
+                if (g + 1 < NG) load(g + 1, buf ^ 1);
+                double4_t od[EG];
+#pragma unroll
+                for (int t = 0; t < EG; ++t) {
+                    const int i = (g * EG + t) / TN, j = (g * EG + t) % TN;
+                    cvec_t out = alpha * acc[i][j];
+                    if constexpr (HP) out -= __builtin_convertvector(up[buf][t], cvec_t);
+                    const svec_t st = __builtin_convertvector(out, svec_t);
+                    *reinterpret_cast<svec_t*>(Unext + at(g, t)) = st;
+                    od[t] = double4_t{(double)st[0], (double)st[1], (double)st[2], (double)st[3]};
+                    msum += z[buf][t][0] * od[t][0] + z[buf][t][1] * od[t][1] + z[buf][t][2] * od[t][2] +
+                            z[buf][t][3] * od[t][3];
+                    if constexpr (WP) *reinterpret_cast<double4_t*>(Pp + at(g, t)) = pv[buf][t] + c0 * od[t];
+                }
+                for (int q = 1; q < a.nsets; ++q) {
+                    const double c = a.coef[q * a.cstride + a.l];
+                    if (c == 0.0) continue;
+                    double* __restrict__ Pq = Pp + q * a.pstride;
+                    double4_t pq[EG];
+#pragma unroll
+                    for (int t = 0; t < EG; ++t) pq[t] = *reinterpret_cast<const double4_t*>(Pq + at(g, t));
+#pragma unroll
+                    for (int t = 0; t < EG; ++t) *reinterpret_cast<double4_t*>(Pq + at(g, t)) = pq[t] + c * od[t];
+                }
+            }
+        };
+        typedef std::integral_constant<bool, true> yes;
+        typedef std::integral_constant<bool, false> no;
+        if (a.has_prev) {
+            if (c0 != 0.0) pipelined(yes{}, yes{});
+            else pipelined(yes{}, no{});
+        } else {
+            if (c0 != 0.0) pipelined(no{}, yes{});
+            else pipelined(no{}, no{});
         }
+    } else {
 #pragma unroll
-        for (int t = 0; t < EG; ++t) {
-            const int i = (g0 + t) / TN, j = (g0 + t) % TN;
-            cvec_t out = alpha * acc[i][j];
-            if (a.has_prev) out -= __builtin_convertvector(up[t], cvec_t);
-            const svec_t st = __builtin_convertvector(out, svec_t);
-            *reinterpret_cast<svec_t*>(Unext + idx[t]) = st;
-            od[t] = double4_t{(double)st[0], (double)st[1], (double)st[2], (double)st[3]};
-            msum += z[t][0] * od[t][0] + z[t][1] * od[t][1] + z[t][2] * od[t][2] + z[t][3] * od[t][3];
-            if (c0 != 0.0) *reinterpret_cast<double4_t*>(Pp + idx[t]) = pv[t] + c0 * od[t];
-        }
-        for (int q = 1; q < a.nsets; ++q) {
-            const double c = a.coef[q * a.cstride + a.l];
-            if (c == 0.0) continue;
-            double* __restrict__ Pq = Pp + q * a.pstride;
+        for (int g0 = 0; g0 < NTILE; g0 += EG) {
+            long idx[EG];
+            svec_t up[EG];
+            double4_t z[EG], pv[EG], od[EG];
 #pragma unroll
-            for (int t = 0; t < EG; ++t) pv[t] = *reinterpret_cast<const double4_t*>(Pq + idx[t]);
+            for (int t = 0; t < EG; ++t) {
+                const int i = (g0 + t) / TN, j = (g0 + t) % TN;
+                idx[t] = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * a.Kp;
+                if (a.has_prev) up[t] = *reinterpret_cast<const svec_t*>(Uprev + idx[t]);
+                z[t] = *reinterpret_cast<const double4_t*>(Zp + idx[t]);
+                if (c0 != 0.0) pv[t] = *reinterpret_cast<const double4_t*>(Pp + idx[t]);
+            }
 #pragma unroll
-            for (int t = 0; t < EG; ++t) *reinterpret_cast<double4_t*>(Pq + idx[t]) = pv[t] + c * od[t];
+            for (int t = 0; t < EG; ++t) {
+                const int i = (g0 + t) / TN, j = (g0 + t) % TN;
+                cvec_t out = alpha * acc[i][j];
+                if (a.has_prev) out -= __builtin_convertvector(up[t], cvec_t);
+                const svec_t st = __builtin_convertvector(out, svec_t);
+                *reinterpret_cast<svec_t*>(Unext + idx[t]) = st;
+                od[t] = double4_t{(double)st[0], (double)st[1], (double)st[2], (double)st[3]};
+                msum += z[t][0] * od[t][0] + z[t][1] * od[t][1] + z[t][2] * od[t][2] + z[t][3] * od[t][3];
+                if (c0 != 0.0) *reinterpret_cast<double4_t*>(Pp + idx[t]) = pv[t] + c0 * od[t];
+            }
+            for (int q = 1; q < a.nsets; ++q) {
+                const double c = a.coef[q * a.cstride + a.l];
+                if (c == 0.0) continue;
+                double* __restrict__ Pq = Pp + q * a.pstride;
+#pragma unroll
+                for (int t = 0; t < EG; ++t) pv[t] = *reinterpret_cast<const double4_t*>(Pq + idx[t]);
+#pragma unroll
+                for (int t = 0; t < EG; ++t) *reinterpret_cast<double4_t*>(Pq + idx[t]) = pv[t] + c * od[t];
+            }
         }
     }
 #pragma unroll
@@ -611,32 +679,87 @@ cheb_batch_kernel(BatchArgs a) {
                 gemm_mainloop<T, TM, TN, KV, DEPTH>(cl.Kt, HN, Kp, ucur, Kp, row0, col0, acc);
                 // the step kernel's epilogue, loads of EG tiles issued together
                 // (pairs in FP32; one at a time where the persistent loop's
-                // registers are short: FP64, two waves per SIMD)
+                // registers are short: FP64, two waves per SIMD); pipelined
+                // shapes also issue the next group's loads before this
+                // group's arithmetic, in straight-line versions for the
+                // uniform conditions
                 constexpr int NTILE = TM * TN;
-                constexpr int EGMAX = (WM * WN > 4 || sizeof(T) == 8) ? 1 : 2;
+                constexpr bool SHORT = WM * WN > 4 || sizeof(T) == 8;
+                constexpr int EGMAX = SHORT ? 1 : 2;
                 constexpr int EG = NTILE % EGMAX == 0 ? EGMAX : 1;
+                constexpr int NG = NTILE / EG;
+                // a second group of loads spills registers in the 4 x 4-tile,
+                // 4-k, four-slab shape
+                constexpr bool PIPE = !SHORT && !(TM * TN == 16 && KV == 4 && DEPTH == 4);
+                if constexpr (PIPE) {
+                    auto at = [&](int g, int t) {
+                        const int i = (g * EG + t) / TN, j = (g * EG + t) % TN;
+                        return (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * Kp;
+                    };
+                    auto pipelined = [&](auto has_prev_c, auto with_p_c) {
+                        constexpr bool HP = decltype(has_prev_c)::value, WP = decltype(with_p_c)::value;
+                        vec_t up[2][EG];
+                        double4_t z[2][EG], pv[2][EG];
+                        auto load = [&](int g, int buf) {
 #pragma unroll
-                for (int g0 = 0; g0 < NTILE; g0 += EG) {
-                    long idx[EG];
-                    vec_t up[EG];
-                    double4_t z[EG], pv[EG];
+                            for (int t = 0; t < EG; ++t) {
+                                if constexpr (HP) up[buf][t] = *reinterpret_cast<const vec_t*>(unext + at(g, t));
+                                z[buf][t] = *reinterpret_cast<const double4_t*>(cl.Z + at(g, t));
+                                if constexpr (WP) pv[buf][t] = *reinterpret_cast<const double4_t*>(cl.P + at(g, t));
+                            }
+                        };
+                        load(0, 0);
 #pragma unroll
-                    for (int t = 0; t < EG; ++t) {
-                        const int i = (g0 + t) / TN, j = (g0 + t) % TN;
-                        idx[t] = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * Kp;
-                        if (l > 1) up[t] = *reinterpret_cast<const vec_t*>(unext + idx[t]);
-                        z[t] = *reinterpret_cast<const double4_t*>(cl.Z + idx[t]);
-                        if (c != 0.0) pv[t] = *reinterpret_cast<const double4_t*>(cl.P + idx[t]);
+                        for (int g = 0; g < NG; ++g) {
+                            const int buf = g & 1;
+                            if (g + 1 < NG) load(g + 1, buf ^ 1);
+#pragma unroll
+                            for (int t = 0; t < EG; ++t) {
+                                const int i = (g * EG + t) / TN, j = (g * EG + t) % TN;
+                                vec_t out = alpha * acc[i][j];
+                                if constexpr (HP) out -= up[buf][t];
+                                *reinterpret_cast<vec_t*>(unext + at(g, t)) = out;
+                                double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
+                                msum += z[buf][t][0] * od[0] + z[buf][t][1] * od[1] + z[buf][t][2] * od[2] +
+                                        z[buf][t][3] * od[3];
+                                if constexpr (WP)
+                                    *reinterpret_cast<double4_t*>(cl.P + at(g, t)) = pv[buf][t] + c * od;
+                            }
+                        }
+                    };
+                    typedef std::integral_constant<bool, true> yes;
+                    typedef std::integral_constant<bool, false> no;
+                    if (l > 1) {
+                        if (c != 0.0) pipelined(yes{}, yes{});
+                        else pipelined(yes{}, no{});
+                    } else {
+                        if (c != 0.0) pipelined(no{}, yes{});
+                        else pipelined(no{}, no{});
                     }
+                } else {
 #pragma unroll
-                    for (int t = 0; t < EG; ++t) {
-                        const int i = (g0 + t) / TN, j = (g0 + t) % TN;
-                        vec_t out = alpha * acc[i][j];
-                        if (l > 1) out -= up[t];
-                        *reinterpret_cast<vec_t*>(unext + idx[t]) = out;
-                        double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
-                        msum += z[t][0] * od[0] + z[t][1] * od[1] + z[t][2] * od[2] + z[t][3] * od[3];
-                        if (c != 0.0) *reinterpret_cast<double4_t*>(cl.P + idx[t]) = pv[t] + c * od;
+                    for (int g0 = 0; g0 < NTILE; g0 += EG) {
+                        long idx[EG];
+                        vec_t up[EG];
+                        double4_t z[EG], pv[EG];
+#pragma unroll
+                        for (int t = 0; t < EG; ++t) {
+                            const int i = (g0 + t) / TN, j = (g0 + t) % TN;
+                            idx[t] = (long)(row0 + 16 * i + 4 * lq) + (long)(col0 + 16 * j + li) * Kp;
+                            if (l > 1) up[t] = *reinterpret_cast<const vec_t*>(unext + idx[t]);
+                            z[t] = *reinterpret_cast<const double4_t*>(cl.Z + idx[t]);
+                            if (c != 0.0) pv[t] = *reinterpret_cast<const double4_t*>(cl.P + idx[t]);
+                        }
+#pragma unroll
+                        for (int t = 0; t < EG; ++t) {
+                            const int i = (g0 + t) / TN, j = (g0 + t) % TN;
+                            vec_t out = alpha * acc[i][j];
+                            if (l > 1) out -= up[t];
+                            *reinterpret_cast<vec_t*>(unext + idx[t]) = out;
+                            double4_t od = {(double)out[0], (double)out[1], (double)out[2], (double)out[3]};
+                            msum += z[t][0] * od[0] + z[t][1] * od[1] + z[t][2] * od[2] + z[t][3] * od[3];
+                            if (c != 0.0) *reinterpret_cast<double4_t*>(cl.P + idx[t]) = pv[t] + c * od;
+                        }
                     }
                 }
             }
