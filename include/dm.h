@@ -340,8 +340,11 @@ dm_status dm_dos(dm_ctx* ctx, int kind, int n, const double* energies, double si
  * by dm_chebyshev_block); n_out (host or device, nx ny nz FP64) is
  * accumulated.  Independent of any loaded Fock matrix.  Needs device
  * memory for two copies of P_cols (the second with its rows in the
- * library's spatial order of the functions) besides the grid; the result
- * does not depend on timing.
+ * library's spatial order of the functions), the grid and the per-cell
+ * function lists; the context keeps them until dm_destroy, and a call whose
+ * centres, exponents, origin, h, dims, eta and columns equal those of its
+ * previous call reuses the lists (they do not depend on P) and only stages P
+ * and n.  The result does not depend on timing or on earlier calls.
  * Errors: DM_E_ARG (bad sizes, exponents <= 0, non-finite centres, h <= 0,
  * eta outside (0, 1), bad or repeated columns), DM_E_OOM, DM_E_HIP. */
 dm_status dm_density_on_grid(dm_ctx* ctx, long long K, const double* centres, const double* exponents,

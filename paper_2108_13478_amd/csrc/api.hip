@@ -160,6 +160,25 @@ struct Op {
 struct BatchState;
 struct MlpState;
 
+// dm_density_on_grid: the per-function arrays and cell lists of the last
+// call (they depend on the basis, the grid, eta and the columns, not on P),
+// reused while those inputs are the same, and the staging buffers of P and n.
+struct GridPlan {
+    bool valid = false;
+    long long K = 0;
+    int dims[3] = {0, 0, 0};
+    std::vector<double> key;         // centres, exponents, origin, h, eta
+    std::vector<long long> key_cols;
+    int ncx = 0, ncy = 0, ncz = 0;
+    DevBuf<double> fx, fy, fz, fe, fn, fr, P, Pp, n;
+    DevBuf<int> bp, bi, ap, ai, ac, perm;
+    void release() {
+        for (auto* x : {&fx, &fy, &fz, &fe, &fn, &fr, &P, &Pp, &n}) x->release();
+        for (auto* x : {&bp, &bi, &ap, &ai, &ac, &perm}) x->release();
+        valid = false;
+    }
+};
+
 struct dm_ctx {
     dm_options opt{};
     hipStream_t stream = nullptr;
@@ -206,6 +225,7 @@ struct dm_ctx {
     DevBuf<double> cs_coef, cs_fk, cs_out, cs_stage;
     DevBuf<int> flag;
     DevBuf<long long> cols;
+    GridPlan grid;
 };
 
 // Device buffers and launch tables of a loaded batch.
@@ -1150,6 +1170,7 @@ void dm_destroy(dm_ctx* c) {
     for (auto& o : c->batch) o.release();
     delete c->bstate;
     delete c->mlp;
+    c->grid.release();
     c->flag.release();
     c->cols.release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1960,28 +1981,15 @@ static double window_depth_s(double eta) {
     return d;
 }
 
-dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, const double* exponents,
-                             const double* origin, double h, const int* dims, double eta, const long long* cols,
-                             long long ncols, const double* P_cols, double* n_out) try {
-    if (!c) return DM_E_ARG;
-    dm_status st = enter(c);
-    if (st != DM_OK) return st;
-    if (K <= 0 || K > (1LL << 30) || !centres || !exponents || !origin || !dims || !n_out)
-        return set_err(c, DM_E_ARG, "bad basis or grid arguments");
-    if (!(h > 0) || !std::isfinite(h) || !(eta > 0 && eta < 1)) return set_err(c, DM_E_ARG, "need h > 0 and 0 < eta < 1");
-    if (ncols < 0 || ncols > K || (ncols > 0 && (!cols || !P_cols))) return set_err(c, DM_E_ARG, "bad columns");
-    const int nx = dims[0], ny = dims[1], nz = dims[2];
-    if (nx < 1 || ny < 1 || nz < 1) return set_err(c, DM_E_ARG, "grid dimensions must be >= 1");
-    const long long G = (long long)nx * ny * nz;
-    if (ncols == 0) return DM_OK;
-    std::vector<long long> hc;
-    HIPTRY(c, to_host(hc, cols, (size_t)ncols));
+// Per-function arrays (spatial order) and per-cell function lists of
+// dm_density_on_grid, uploaded into the context's grid plan; waits for the
+// uploads, so the host arrays may go when it returns.  The inputs have been
+// checked for sizes and columns by the caller.
+static dm_status build_grid_plan(dm_ctx* c, long long K, const double* centres, const double* exponents,
+                                 const double* origin, double h, int nx, int ny, int nz, double eta,
+                                 const std::vector<long long>& hc) {
     std::vector<int> colpos((size_t)K, -1);
-    for (long long j = 0; j < ncols; ++j) {
-        if (hc[j] < 0 || hc[j] >= K) return set_err(c, DM_E_ARG, "column index out of range");
-        if (colpos[hc[j]] >= 0) return set_err(c, DM_E_ARG, "repeated column index");
-        colpos[hc[j]] = (int)j;
-    }
+    for (size_t j = 0; j < hc.size(); ++j) colpos[(size_t)hc[j]] = (int)j;
     // per-function data and window half-widths (host arrays, K entries)
     std::vector<double> fx(K), fy(K), fz(K), fe(K), fn(K), fr(K);
     const double dwin = window_depth_s(eta);
@@ -2132,18 +2140,16 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
             }
         });
     }
+    GridPlan& gp = c->grid;
+    gp.ncx = ncx;
+    gp.ncy = ncy;
+    gp.ncz = ncz;
     hipStream_t s = c->stream;
-    DevBuf<double> dfx, dfy, dfz, dfe, dfn, dfr, dP, dPp, dn;
-    DevBuf<int> dbp, dbi, dap, dai, dac, dperm;
-    auto rel = [&]() {
-        for (auto* x : {&dfx, &dfy, &dfz, &dfe, &dfn, &dfr, &dP, &dPp, &dn}) x->release();
-        for (auto* x : {&dbp, &dbi, &dap, &dai, &dac, &dperm}) x->release();
-    };
     hipError_t e;
 #define GR(expr)                          \
     do {                                  \
         if ((e = (expr)) != hipSuccess) { \
-            rel();                        \
+            gp.release();                 \
             return fail_hip(c, e, #expr); \
         }                                 \
     } while (0)
@@ -2157,39 +2163,101 @@ dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, cons
         if (r == hipSuccess && !v.empty()) r = hipMemcpyAsync(d.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s);
         return r;
     };
-    GR(up_d(dfx, fx));
-    GR(up_d(dfy, fy));
-    GR(up_d(dfz, fz));
-    GR(up_d(dfe, fe));
-    GR(up_d(dfn, fn));
-    GR(up_d(dfr, fr));
-    GR(up_i(dbp, std::vector<int>(bcount.begin(), bcount.end())));
-    GR(up_i(dbi, bidx));
-    GR(up_i(dap, std::vector<int>(acount.begin(), acount.end())));
-    GR(up_i(dai, aidx));
-    GR(up_i(dac, acol));
-    GR(up_i(dperm, perm));
-    // P and n through device buffers (either may be host memory); the rows
-    // of P in the functions' new order
-    GR(ensure(dP, (size_t)K * ncols));
-    GR(hipMemcpyAsync(dP.p, P_cols, (size_t)K * ncols * 8, hipMemcpyDefault, s));
-    GR(ensure(dPp, (size_t)K * ncols));
-    GR(permute_rows((int)K, ncols, dperm.p, dP.p, dPp.p, s));
-    GR(ensure(dn, (size_t)G));
-    GR(hipMemcpyAsync(dn.p, n_out, (size_t)G * 8, hipMemcpyDefault, s));
-    GridArgs ga{};
-    ga.nx = nx; ga.ny = ny; ga.nz = nz; ga.ncx = ncx; ga.ncy = ncy; ga.ncz = ncz;
-    ga.ox = origin[0]; ga.oy = origin[1]; ga.oz = origin[2]; ga.h = h;
-    ga.cx = dfx.p; ga.cy = dfy.p; ga.cz = dfz.p; ga.ex = dfe.p; ga.norm = dfn.p; ga.R = dfr.p;
-    ga.beta_ptr = dbp.p; ga.beta_idx = dbi.p; ga.alpha_ptr = dap.p; ga.alpha_idx = dai.p; ga.alpha_col = dac.p;
-    ga.P = dPp.p;
-    ga.ldp = K;
-    ga.n = dn.p;
-    GR(density_on_grid(ga, s));
-    GR(hipMemcpyAsync(n_out, dn.p, (size_t)G * 8, hipMemcpyDefault, s));
+    const std::vector<int> bptr(bcount.begin(), bcount.end()), aptr(acount.begin(), acount.end());
+    GR(up_d(gp.fx, fx));
+    GR(up_d(gp.fy, fy));
+    GR(up_d(gp.fz, fz));
+    GR(up_d(gp.fe, fe));
+    GR(up_d(gp.fn, fn));
+    GR(up_d(gp.fr, fr));
+    GR(up_i(gp.bp, bptr));
+    GR(up_i(gp.bi, bidx));
+    GR(up_i(gp.ap, aptr));
+    GR(up_i(gp.ai, aidx));
+    GR(up_i(gp.ac, acol));
+    GR(up_i(gp.perm, perm));
     GR(hipStreamSynchronize(s));
 #undef GR
-    rel();
+    return DM_OK;
+}
+
+dm_status dm_density_on_grid(dm_ctx* c, long long K, const double* centres, const double* exponents,
+                             const double* origin, double h, const int* dims, double eta, const long long* cols,
+                             long long ncols, const double* P_cols, double* n_out) try {
+    if (!c) return DM_E_ARG;
+    dm_status st = enter(c);
+    if (st != DM_OK) return st;
+    if (K <= 0 || K > (1LL << 30) || !centres || !exponents || !origin || !dims || !n_out)
+        return set_err(c, DM_E_ARG, "bad basis or grid arguments");
+    if (!(h > 0) || !std::isfinite(h) || !(eta > 0 && eta < 1)) return set_err(c, DM_E_ARG, "need h > 0 and 0 < eta < 1");
+    if (ncols < 0 || ncols > K || (ncols > 0 && (!cols || !P_cols))) return set_err(c, DM_E_ARG, "bad columns");
+    const int nx = dims[0], ny = dims[1], nz = dims[2];
+    if (nx < 1 || ny < 1 || nz < 1) return set_err(c, DM_E_ARG, "grid dimensions must be >= 1");
+    const long long G = (long long)nx * ny * nz;
+    if (ncols == 0) return DM_OK;
+    std::vector<long long> hc;
+    HIPTRY(c, to_host(hc, cols, (size_t)ncols));
+    std::vector<int> colpos((size_t)K, -1);
+    for (long long j = 0; j < ncols; ++j) {
+        if (hc[j] < 0 || hc[j] >= K) return set_err(c, DM_E_ARG, "column index out of range");
+        if (colpos[hc[j]] >= 0) return set_err(c, DM_E_ARG, "repeated column index");
+        colpos[hc[j]] = (int)j;
+    }
+    // The lists depend on the basis, the grid, eta and the columns only:
+    // reuse those of the last call when all of them are the same.
+    GridPlan& gp = c->grid;
+    std::vector<double> key;
+    key.reserve((size_t)(4 * K + 5));
+    key.insert(key.end(), centres, centres + 3 * K);
+    key.insert(key.end(), exponents, exponents + K);
+    key.insert(key.end(), origin, origin + 3);
+    key.push_back(h);
+    key.push_back(eta);
+    const bool reuse = gp.valid && gp.K == K && gp.dims[0] == nx && gp.dims[1] == ny && gp.dims[2] == nz &&
+                       gp.key.size() == key.size() &&
+                       std::memcmp(gp.key.data(), key.data(), key.size() * sizeof(double)) == 0 && gp.key_cols == hc;
+    hipStream_t s = c->stream;
+    hipError_t e;
+#define GR(expr)                          \
+    do {                                  \
+        if ((e = (expr)) != hipSuccess) { \
+            gp.release();                 \
+            return fail_hip(c, e, #expr); \
+        }                                 \
+    } while (0)
+    if (!reuse) {
+        gp.valid = false;
+        dm_status bs = build_grid_plan(c, K, centres, exponents, origin, h, nx, ny, nz, eta, hc);
+        if (bs != DM_OK) return bs;
+        gp.K = K;
+        gp.dims[0] = nx;
+        gp.dims[1] = ny;
+        gp.dims[2] = nz;
+        gp.key.swap(key);
+        gp.key_cols = hc;
+        gp.valid = true;
+    }
+    // P and n through the plan's device buffers (either may be host memory);
+    // the rows of P in the functions' spatial order
+    GR(ensure(gp.P, (size_t)K * ncols));
+    GR(hipMemcpyAsync(gp.P.p, P_cols, (size_t)K * ncols * 8, hipMemcpyDefault, s));
+    GR(ensure(gp.Pp, (size_t)K * ncols));
+    GR(permute_rows((int)K, ncols, gp.perm.p, gp.P.p, gp.Pp.p, s));
+    GR(ensure(gp.n, (size_t)G));
+    GR(hipMemcpyAsync(gp.n.p, n_out, (size_t)G * 8, hipMemcpyDefault, s));
+    GridArgs ga{};
+    ga.nx = nx; ga.ny = ny; ga.nz = nz; ga.ncx = gp.ncx; ga.ncy = gp.ncy; ga.ncz = gp.ncz;
+    ga.ox = origin[0]; ga.oy = origin[1]; ga.oz = origin[2]; ga.h = h;
+    ga.cx = gp.fx.p; ga.cy = gp.fy.p; ga.cz = gp.fz.p; ga.ex = gp.fe.p; ga.norm = gp.fn.p; ga.R = gp.fr.p;
+    ga.beta_ptr = gp.bp.p; ga.beta_idx = gp.bi.p; ga.alpha_ptr = gp.ap.p; ga.alpha_idx = gp.ai.p;
+    ga.alpha_col = gp.ac.p;
+    ga.P = gp.Pp.p;
+    ga.ldp = K;
+    ga.n = gp.n.p;
+    GR(density_on_grid(ga, s));
+    GR(hipMemcpyAsync(n_out, gp.n.p, (size_t)G * 8, hipMemcpyDefault, s));
+    GR(hipStreamSynchronize(s));
+#undef GR
     return DM_OK;
 } catch (...) {
     return host_exception(c);

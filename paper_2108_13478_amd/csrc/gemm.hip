@@ -680,17 +680,17 @@ cheb_batch_kernel(BatchArgs a) {
                 // the step kernel's epilogue, loads of EG tiles issued together
                 // (pairs in FP32; one at a time where the persistent loop's
                 // registers are short: FP64, two waves per SIMD); pipelined
-                // shapes also issue the next group's loads before this
-                // group's arithmetic, in straight-line versions for the
-                // uniform conditions
+                // shapes (four waves) also issue the next group's loads
+                // before this group's arithmetic, in straight-line versions
+                // for the uniform conditions
                 constexpr int NTILE = TM * TN;
                 constexpr bool SHORT = WM * WN > 4 || sizeof(T) == 8;
                 constexpr int EGMAX = SHORT ? 1 : 2;
                 constexpr int EG = NTILE % EGMAX == 0 ? EGMAX : 1;
                 constexpr int NG = NTILE / EG;
-                // a second group of loads spills registers in the 4 x 4-tile,
-                // 4-k, four-slab shape
-                constexpr bool PIPE = !SHORT && !(TM * TN == 16 && KV == 4 && DEPTH == 4);
+                // a second group of loads spills registers in the FP32 4 x
+                // 4-tile, 4-k, four-slab shape
+                constexpr bool PIPE = WM * WN <= 4 && !(sizeof(T) == 4 && TM * TN == 16 && KV == 4 && DEPTH == 4);
                 if constexpr (PIPE) {
                     auto at = [&](int g, int t) {
                         const int i = (g * EG + t) / TN, j = (g * EG + t) % TN;

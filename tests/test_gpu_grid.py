@@ -44,6 +44,42 @@ def test_density_matches_oracle_and_shares_add_up():
     assert np.abs(acc - ref).max() < 1e-12 * np.abs(ref).max()
 
 
+def test_density_lists_reused_only_for_the_same_inputs():
+    """A context keeps the cell lists of its last call and reuses them while
+    the basis, grid, eta and columns are the same: every call here must equal
+    the same call on a fresh context, bit for bit, whatever came before."""
+    c = make_cluster(64, seed=0, geometry="cube")  # K = 256
+    sp = O.spectrum(c)
+    P = O.density_matrix_exact(sp, np.arange(c.K), 0.5 * (sp.e[63] + sp.e[64]), 20.0)
+    centres, exps = basis_functions(c)
+    origin, h, dims = grid_around(c, 0.4, 5.0)
+    share = np.random.default_rng(3).permutation(c.K)[:100].astype(np.int64)
+    moved = centres.copy()
+    moved[17] += 0.25
+    calls = [  # (centres, h, eta, columns)
+        (centres, h, 1e-6, np.arange(c.K, dtype=np.int64)),
+        (centres, h, 1e-6, np.arange(c.K, dtype=np.int64)),
+        (centres, 0.5, 1e-6, np.arange(c.K, dtype=np.int64)),
+        (centres, h, 1e-4, np.arange(c.K, dtype=np.int64)),
+        (centres, h, 1e-6, share),
+        (moved, h, 1e-6, share),
+        (centres, h, 1e-6, np.arange(c.K, dtype=np.int64)),
+    ]
+    say(f"case: grid lists reuse K={c.K}, {len(calls)} calls")
+    ctx = dmlib.Context()
+    for i, (cen, hh, eta, cols) in enumerate(calls):
+        Pc = np.ascontiguousarray(P[:, cols].T)
+        n = ctx.dm_density_on_grid(cen, exps, origin, hh, dims, eta, cols, Pc)
+        fresh = dmlib.Context().dm_density_on_grid(cen, exps, origin, hh, dims, eta, cols, Pc)
+        assert np.array_equal(n, fresh), f"call {i}"
+    # after a refused call the next good call still equals a fresh one
+    with pytest.raises(dmlib.DMError):
+        ctx.dm_density_on_grid(centres, -exps, origin, h, dims, 1e-6, calls[0][3], np.ascontiguousarray(P.T))
+    n = ctx.dm_density_on_grid(centres, exps, origin, h, dims, 1e-6, calls[0][3], np.ascontiguousarray(P.T))
+    assert np.array_equal(n, dmlib.Context().dm_density_on_grid(centres, exps, origin, h, dims, 1e-6, calls[0][3],
+                                                                 np.ascontiguousarray(P.T)))
+
+
 def test_density_from_a_pass_integrates_to_electron_count():
     """Columns of P from dm_chebyshev_block (device buffer) on a fine grid:
     h^3 sum n = 2 Tr[P_N S] with the oracle's same-polynomial trace."""
@@ -115,6 +151,15 @@ def test_density_k4096_from_full_pass_timed():
     say(f"case: K={c.K} grid {dims} ({int(np.prod(dims)) / 1e6:.1f} M points), eta 1e-6: {dt * 1e3:.0f} ms "
         f"(call, lists and copies included); h^3 sum n = {total:.6f}, 2 Tr[P_N S] = {2 * tr:.6f}")
     assert abs(total - 2 * tr) < 1e-4 * 2 * tr
+    # the same basis, grid and columns again (a new P in an SCF loop): the
+    # call reuses the cell lists of the last one
+    nd2 = torch.zeros_like(nd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.dm_density_on_grid(centres, exps, origin, h, dims, 1e-6, cols, Pd, nd2)
+    torch.cuda.synchronize()
+    say(f"  same inputs again (lists reused): {(time.perf_counter() - t0) * 1e3:.1f} ms")
+    assert torch.equal(nd, nd2)
     # sampled points against the grid oracle, each computed on its own
     # (a one-point grid at that point) from the same P: 48 anywhere on the
     # grid, 48 in the central third where the most functions overlap
