@@ -45,18 +45,23 @@ PEAK_HBM_GBS = 8000.0
 # Valid only for the recursion-step code they were taken with: the text of
 # gemm.hip before the persistent-batch section (GEMM_STEP_END).
 GEMM_STEP_END = b"// ------------------------------------------------------------ persistent batch"
-COUNTERS = {"kernel_source_sha256_16": "5d81961b90d81fd3", "fetch_kib": 996912.4,
-            "write_kib": 262024.0, "fetch_scale": 2.0, "write_scale": 1.0}
+COUNTERS = {"kernel_source_sha256_16": "5d81961b90d81fd3", "fetch_kib": 997402.8,
+            "write_kib": 262023.8, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 HBM_WORKLOAD = "K32768_sphere8192_fp32"
 HBM_COLUMNS = 32
 HBM_ORDER = 200
+# tile shapes of the HBM point, pinned (the library's defaults for this pass):
+# 128 x 32, column panel in LDS, three slabs in flight, 8 k per lane; the
+# refined twin on the seven-slab shape
+HBM_CFG, HBM_KERNEL = 30, "cheb_step_kernel<float,2,2,4,1,8,4,true>"
+HBM_CFG_REFINED, HBM_KERNEL_REFINED = 29, "cheb_step_kernel<W32,2,2,4,1,8,8,true>"
 # the K = 32768 workload's whole configuration (every column): pass width and
 # tile shape, and the steps timed
 FULL_WIDTH, FULL_CFG, FULL_STEPS = 16384, 27, 4
 # the same counters for the recursion launch of the HBM point (FP32, 32 columns)
-COUNTERS_HBM = {"kernel_source_sha256_16": "5d81961b90d81fd3", "fetch_kib": 2124187.5, "write_kib": 12215.6,
+COUNTERS_HBM = {"kernel_source_sha256_16": "5d81961b90d81fd3", "cfg": 30, "fetch_kib": 2124152.9, "write_kib": 12215.8,
                 "fetch_scale": 2.0, "write_scale": 1.0}
 
 
@@ -160,6 +165,7 @@ def hbm_point(stream, refined=False):
     prec = dmlib.DM_FP32_ACC64 if refined else dmlib.DM_FP32
     ctx = dmlib.Context(device=0, stream=stream.cuda_stream, precision=prec)
     ctx.set_cluster(c)
+    ctx.dm_set_pass_shape(HBM_COLUMNS, HBM_CFG_REFINED if refined else HBM_CFG)
     cols = torch.arange(HBM_COLUMNS, dtype=torch.int64, device="cuda:0")
     ctx.dm_chebyshev_block(cols, 20, 0.0, w["beta"], None)  # warm-up pass
     ctx.dm_reset_moments()
@@ -200,16 +206,17 @@ def hbm_point(stream, refined=False):
     if refined:
         tf = flops / (launch_ms * 1e-3) / 1e12
         return {"workload": HBM_WORKLOAD, "K": K, "columns": HBM_COLUMNS, "steps_timed": HBM_ORDER,
-                "precision": "fp32 storage, fp64 sums", "bound": "mfma", "kernel": "cheb_step_kernel<W32,2,2,4,1,8,8,true>",
+                "precision": "fp32 storage, fp64 sums", "bound": "mfma", "kernel": HBM_KERNEL_REFINED,
                 "launch_ms": launch_ms, "algorithmic_bytes": alg_bytes, "achieved": tf, "unit": "TFLOP/s",
                 "peak": PEAK_FP64_TFLOPS, "frac": tf / PEAK_FP64_TFLOPS, "algorithmic_GBps": gbs,
                 "hbm_frac": gbs / PEAK_HBM_GBS, "traffic": None}
     traffic = None
-    if kernel_source_hash("gemm.hip", GEMM_STEP_END) == COUNTERS_HBM["kernel_source_sha256_16"]:
+    if (kernel_source_hash("gemm.hip", GEMM_STEP_END) == COUNTERS_HBM["kernel_source_sha256_16"]
+            and COUNTERS_HBM["cfg"] == HBM_CFG):
         traffic = 1024.0 * (COUNTERS_HBM["fetch_kib"] * COUNTERS_HBM["fetch_scale"]
                             + COUNTERS_HBM["write_kib"] * COUNTERS_HBM["write_scale"])
     return {"workload": HBM_WORKLOAD, "K": K, "columns": HBM_COLUMNS, "steps_timed": HBM_ORDER,
-            "precision": "fp32", "bound": "hbm", "kernel": "cheb_step_kernel<float,2,2,4,1,8,8,true>",
+            "precision": "fp32", "bound": "hbm", "kernel": HBM_KERNEL,
             "launch_ms": launch_ms, "algorithmic_bytes": alg_bytes, "achieved": gbs, "unit": "GB/s",
             "peak": PEAK_HBM_GBS, "frac": gbs / PEAK_HBM_GBS, "traffic": traffic,
             "counter_GBps": None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9,

@@ -640,7 +640,7 @@ dm_status reset_moments(dm_ctx* c) {
 // operators, which have too few row tiles, take a split-reduction shape.
 int pick_cfg(int Kp, int ncols, int precision) {
     static const int kPrefF64[] = {12, 36, 33, 32, 1, 2, 3};
-    static const int kPrefF32[] = {12, 31, 29, 30, 1, 2, 3};
+    static const int kPrefF32[] = {12, 31, 30, 29, 1, 2, 3};
     static const int kPrefW32[] = {12, 0, 29, 30, 20, 7, 2, 3};
     static const int kSplit[] = {18, 14, 13};
     const int n = std::max(ncols, 1);

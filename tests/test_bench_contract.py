@@ -28,6 +28,7 @@ def test_counters_match_current_kernel_sources():
     # come with counters taken again
     assert bench.kernel_source_hash("gemm.hip", bench.GEMM_STEP_END) == bench.COUNTERS["kernel_source_sha256_16"]
     assert bench.kernel_source_hash("gemm.hip", bench.GEMM_STEP_END) == bench.COUNTERS_HBM["kernel_source_sha256_16"]
+    assert bench.COUNTERS_HBM["cfg"] == bench.HBM_CFG  # taken on the tile shape the HBM point pins
     assert (bench.kernel_source_hash("factored.hip", bench.FACT_DEVICE_END)
             == bench.COUNTERS_FACT["kernel_source_sha256_16"])
 
