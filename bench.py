@@ -53,10 +53,10 @@ HBM_WORKLOAD = "K32768_sphere8192_fp32"
 HBM_COLUMNS = 32
 HBM_ORDER = 200
 # tile shapes of the HBM point, pinned (the library's defaults for this pass):
-# 128 x 32, column panel in LDS, three slabs in flight, 8 k per lane; the
-# refined twin on the seven-slab shape
+# 128 x 32, three slabs in flight, 8 k per lane, the column panel in LDS;
+# the refined twin with the panel read by every wave (no LDS)
 HBM_CFG, HBM_KERNEL = 30, "cheb_step_kernel<float,2,2,4,1,8,4,true>"
-HBM_CFG_REFINED, HBM_KERNEL_REFINED = 29, "cheb_step_kernel<W32,2,2,4,1,8,8,true>"
+HBM_CFG_REFINED, HBM_KERNEL_REFINED = 22, "cheb_step_kernel<W32,2,2,4,1,8,4,false>"
 # the K = 32768 workload's whole configuration (every column): pass width and
 # tile shape, and the steps timed
 FULL_WIDTH, FULL_CFG, FULL_STEPS = 16384, 27, 4

@@ -641,7 +641,7 @@ dm_status reset_moments(dm_ctx* c) {
 int pick_cfg(int Kp, int ncols, int precision) {
     static const int kPrefF64[] = {12, 36, 33, 32, 1, 2, 3};
     static const int kPrefF32[] = {12, 31, 30, 29, 1, 2, 3};
-    static const int kPrefW32[] = {12, 0, 29, 30, 20, 7, 2, 3};
+    static const int kPrefW32[] = {12, 0, 22, 29, 30, 20, 7, 2, 3};
     static const int kSplit[] = {18, 14, 13};
     const int n = std::max(ncols, 1);
     const int n32 = (int)round_up(n, 32);
